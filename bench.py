@@ -1,0 +1,154 @@
+"""Benchmark: scalar Gauss-Legendre SHT at lmax = mmax = 1023 on one MI355X.
+
+One step = one synthesis (spectrum -> 1024 x 2048 grid) plus one analysis
+(grid -> spectrum) of one field, inputs resident in HBM.  Prints ONE JSON
+line; `value` is transforms/s (two transforms per step, the paper's
+convention of averaging forward and backward transform times).
+
+roofline: the dominant Legendre kernel, algorithmic FP64 work
+8 x (latitude pairs) x (spectral coefficients) per launch over its average
+launch duration, timed with HIP event pairs recorded by the library on the
+launch stream during the timed steps; peak = FP64 vector 78.6 TFLOP/s.
+cpu_baseline: the oracle (plain C, OpenMP) doing one full synthesis +
+analysis round trip of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6
+METRIC = "transforms/s & FP64 peak fraction at lmax=1023; batched vs per-field"
+
+
+def _src_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(kernel_name, launches_bytes_scale=None):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    src = os.path.join(ROOT, "paper_1202_6522_amd", "csrc", "legendre.hip")
+    k = d.get(kernel_name)
+    if not k or k.get("source_sha") != _src_hash(src):
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(L, M, nlat, nphi, Q):
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    oracle.build()
+    t0 = time.perf_counter()
+    g = oracle.synth(Q, L, M, nlat, nphi, nthreads=threads)
+    oracle.analys(g, L, M, nlat, nphi, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 / dt, "unit": "transforms/s", "cores": threads, "kind": "oracle",
+            "sample": "one full synthesis + analysis round trip, lmax=1023, 1024x2048 grid, "
+                      "1 field (direct DFT in longitude), %.1f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1202_6522_amd import inputs
+    from paper_1202_6522_amd import shtn as S
+
+    p, Qh = inputs.scalar_case(2)
+    L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+    dev = torch.device("cuda:0")
+    plan = S.Plan(L, M, nlat, nphi, device=dev)
+    Q = torch.from_numpy(Qh).to(dev)
+    grid = torch.empty((1, nlat, nphi), dtype=torch.float64, device=dev)
+    R = torch.empty_like(Q)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    work = plan.workspace(1)
+
+    def step():
+        S.shtn_synth(plan.handle, Q.data_ptr(), grid.data_ptr(), 1, work, stream)
+        S.shtn_analys(plan.handle, grid.data_ptr(), R.data_ptr(), 1, work, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    err = float((R - Q).abs().max() / Q.abs().max())
+
+    S.shtn_profile_reset()
+    S.shtn_profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize(dev)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    S.shtn_profile_enable(False)
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    kern = {}
+    for kind, name in S.PROFILE_KINDS.items():
+        tot, n = S.shtn_profile_read(kind)
+        kern[name] = {"avg_us": 1e3 * tot / max(n, 1), "launches": n}
+
+    flops = plan.legendre_flops()
+    dom = max(("legendre_synth", "legendre_analys"), key=lambda k: kern[k]["avg_us"])
+    avg_s = kern[dom]["avg_us"] * 1e-6
+    achieved = flops / avg_s / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+            "traffic": _traffic(dom), "kernel": dom,
+            "flops_per_launch": flops}
+    out = {
+        "metric": METRIC,
+        "value": round(2.0 * args.steps / (ms * 1e-3), 2),
+        "unit": "transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "scalar SHT synthesis+analysis, lmax=mmax=1023, nlat=1024 Gauss "
+                               "nodes, nphi=2048, 1 field, spectrum N(0,1)(n+1)^-1.5 seed 12026524",
+                   "lmax": L, "nlat": nlat, "nphi": nphi, "fields": 1},
+        "roofline": roof,
+        "kernels_us": {k: round(v["avg_us"], 3) for k, v in kern.items()},
+        "round_trip_rel_err": err,
+        "legendre_tflops": {k: round(flops / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
+                            for k in ("legendre_synth", "legendre_analys")},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, M, nlat, nphi, Qh[0])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * shtn -- Gauss-Legendre spherical harmonic transform for AMD MI355X (gfx950).
+ *
+ * Method: N. Schaeffer, "Efficient Spherical Harmonic Transforms aimed at
+ * pseudo-spectral numerical simulations", arXiv 1202.6522.  Section numbers
+ * below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Truncation: degree n <= lmax, order 0 <= m <= min(n, mmax).
+ *  Spectral arrays: complex FP64, interleaved (re, im) -- the memory layout of
+ *    torch.complex128 / double _Complex -- in m-major triangular order
+ *      idx(n, m) = m (2 lmax + 1 - m) / 2 + n,
+ *    nlm = (mmax+1)(lmax+1) - mmax(mmax+1)/2 coefficients per field; fields are
+ *    contiguous with stride nlm.  Only m >= 0 is stored: the fields are real,
+ *    so f_n^{-m} = conj(f_n^m) (Sec. 3.1, Hermitian symmetry).  Im Q_n^0 is
+ *    ignored on input and returned as 0.
+ *  Grids: FP64 [nfields][nlat][nphi], row i = colatitude theta_i increasing
+ *    (Gauss node x_i = cos theta_i decreasing, north to south), column
+ *    k = longitude phi_k = 2 pi k / nphi.
+ *  P_n^m: orthonormal associated Legendre functions with the (-1)^m
+ *    Condon-Shortley factor of the definition in Sec. 2.1.
+ *
+ *  Pointers: every data pointer (Q, grid, work, device plan buffer) is a
+ *    device pointer owned by the caller; arrays are contiguous.  `stream` is a
+ *    hipStream_t passed as void* (NULL = the default stream).  The library
+ *    allocates no device memory: tables and scratch live in caller buffers.
+ *    Inputs are never modified.  Inputs and outputs must not overlap.
+ *  Errors: entry points return SHTN_OK (0) or a negative code below;
+ *    shtn_last_error_detail() gives a thread-local message.  Transform calls
+ *    are asynchronous on `stream`: a device fault surfaces at the caller's
+ *    next synchronisation.  No C++ exception crosses this interface.
+ */
+#ifndef SHTN_H
+#define SHTN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHTN_OK 0
+#define SHTN_EINVAL (-1)       /* invalid argument (bad size, null pointer, short workspace) */
+#define SHTN_EUNSUPPORTED (-2) /* valid but not implemented (e.g. nphi not a power of two)   */
+#define SHTN_ESTATE (-3)       /* plan not uploaded to the device yet                         */
+#define SHTN_EHIP (-4)         /* the HIP runtime reported an error                           */
+#define SHTN_ENOMEM (-5)       /* host allocation failed                                      */
+
+typedef struct shtn_plan_s* shtn_plan_t;
+
+/* Builds a transform plan on the host (no device call).
+ * lmax >= 0, 0 <= mmax <= lmax, nlat >= 1 Gauss nodes (nlat >= lmax+1 makes
+ * the analysis exact, Sec. 2.3), nphi equispaced longitudes with nphi > 2 mmax
+ * and nphi a power of two.  Computes the Gauss nodes and weights (Sec. 2.3,
+ * eq. gauss), the recurrence tables of Sec. 3.2 (eq. rec) in the rescaled form
+ * used by the kernels, the P_m^m start values with their scaled exponents
+ * (Sec. 3.5), the restart states that split long orders into balanced work
+ * units, the FFT twiddles and the work-unit lists.  Returns NULL on error
+ * (see shtn_last_error_detail). */
+shtn_plan_t shtn_plan(int lmax, int mmax, int nlat, int nphi);
+void shtn_plan_destroy(shtn_plan_t plan); /* NULL is ignored */
+
+/* Size in bytes of the device buffer that holds the plan's tables. */
+size_t shtn_plan_device_bytes(shtn_plan_t plan);
+
+/* Copies the plan's tables into the caller's device buffer `dev_buf`
+ * (>= shtn_plan_device_bytes, 256-byte aligned) and synchronises `stream`.
+ * The buffer must outlive every transform call with this plan. */
+int shtn_plan_upload(shtn_plan_t plan, void* dev_buf, void* stream);
+
+/* Device workspace bytes needed by a transform of `nfields` fields (the
+ * longitude-Fourier coefficients F_m(theta_i) and the rescaled spectrum). */
+size_t shtn_work_bytes(shtn_plan_t plan, int nfields);
+
+/* Synthesis (Sec. 2.2): grid = S Q.
+ * f(theta_i, phi_k) = Re F_0(theta_i) + 2 Re sum_{m=1}^{mmax} F_m(theta_i) e^{i m phi_k},
+ * F_m(theta) = sum_{n=m}^{lmax} Q_n^m P_n^m(cos theta) (eq. synth_direct),
+ * with P_n^m generated on the fly by the recurrence (Sec. 3.2) and the
+ * equatorial mirror symmetry folded in (Sec. 3.1).
+ * Q: nfields x nlm complex; grid: nfields x nlat x nphi. */
+int shtn_synth(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work,
+               void* stream);
+
+/* Analysis (Sec. 2.3): Q = A grid.
+ * F_m(theta_i) = (2 pi / nphi) sum_k f(theta_i, phi_k) e^{-i m phi_k},
+ * Q_n^m = sum_i w_i P_n^m(x_i) F_m(theta_i) (eq. gauss).  Im Q_n^0 = 0. */
+int shtn_analys(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work,
+                void* stream);
+
+/* Adjoint of the synthesis (the transpose of the real-linear map
+ * (Re Q, Im Q) -> grid), returned as d + i e with d, e the Re and Im parts:
+ * (S^T g)_n^m = c_m sum_i P_n^m(x_i) sum_k g_ik e^{-i m phi_k},
+ * c_0 = 1, c_m = 2 (m >= 1).  With g = dL/dgrid this is the gradient of L with
+ * respect to Q in PyTorch's complex convention (dL/dRe Q + i dL/dIm Q). */
+int shtn_synth_adj(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work,
+                   void* stream);
+
+/* Adjoint of the analysis (transpose of grid -> (Re Q, Im Q)):
+ * (A^T h)_ik = (2 pi / nphi) w_i [Re H_0(theta_i) + sum_{m>=1} Re(H_m(theta_i) e^{i m phi_k})],
+ * H_m(theta) = sum_n h_n^m P_n^m(cos theta).  Im h_n^0 is ignored. */
+int shtn_analys_adj(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work,
+                    void* stream);
+
+/* Plan queries (host only). */
+long shtn_nlm(shtn_plan_t plan);
+long shtn_lm_index(shtn_plan_t plan, int n, int m); /* -1 if (n, m) is outside the truncation */
+/* Copies the nlat Gauss nodes x_i (decreasing) and weights w_i to host arrays. */
+int shtn_get_grid(shtn_plan_t plan, double* x_host, double* w_host);
+/* Algorithmic FP64 operations of one Legendre pass over one field:
+ * 8 per (n, m, latitude pair) -- the recurrence step (3 multiplications and
+ * one addition, Sec. 3.2) plus the complex multiply-accumulate. */
+double shtn_legendre_flops(shtn_plan_t plan);
+
+/* Copies a host-side plan table for inspection (tests, tools).
+ * which: 0 x per pair, 1 sin(theta) per pair, 2 weight per pair (the middle
+ * node of an odd grid carries half its weight), 3 beta (nlm), 4 gamma (nlm),
+ * 5 start mantissa ((mmax+1) x npair), 6 start exponent (int32, same shape),
+ * 7 segment exponent shifts (int32), 8 segment offsets per m (int32, mmax+2),
+ * 9 restart states (double, nrestart x npair x 2), 10 restart exponents
+ * (int32, nrestart x npair), 11 analysis units (int32 x 4 each),
+ * 12 synthesis units (int32 x 4 each), 13 tiling (int32 x 8).
+ * Returns the table size in bytes; copies only if dst != NULL and
+ * bytes >= size.  Negative on error. */
+long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
+
+/* Tiling of the Legendre kernels (the runtime-tuning knob of Sec. 3.2):
+ * synth_lp / analys_lp latitude pairs per lane (1, 2, 4, 8), fields per
+ * wave fw (1, 2; fw = 2 needs lp <= 4), m_pairing (0/1: one wave takes orders m and mmax-m),
+ * split (analysis n-range piece length, a multiple of 32; 0 = automatic).
+ * Changing the split rebuilds the restart tables: re-upload afterwards.
+ * Returns SHTN_EINVAL for unsupported values. */
+int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
+                         int split);
+
+/* ---- batches of fields with different truncations (one launch per stage) ---- */
+typedef struct shtn_batch_s* shtn_batch_t;
+
+/* A batch of nfields fields; field f uses plans[f] (plans may repeat; fields
+ * sharing a plan are grouped so one wave can serve several of them).  The
+ * plans must stay alive and uploaded.  Packed buffers hold the fields back to
+ * back in field order: spectra at q_off[f] doubles (2 per coefficient), grids
+ * at grid_off[f] doubles. */
+shtn_batch_t shtn_batch(int nfields, const shtn_plan_t* plans);
+void shtn_batch_destroy(shtn_batch_t batch);
+/* q_off, grid_off: host arrays of nfields+1 offsets in doubles (last = total). */
+int shtn_batch_offsets(shtn_batch_t batch, size_t* q_off, size_t* grid_off);
+size_t shtn_batch_device_bytes(shtn_batch_t batch); /* unit/field tables */
+size_t shtn_batch_work_bytes(shtn_batch_t batch);
+int shtn_batch_upload(shtn_batch_t batch, void* dev_buf, void* stream);
+/* Batched synthesis / analysis of every field, each stage one launch over all
+ * fields (longest work units first).  Same maths as shtn_synth / shtn_analys. */
+int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpacked, void* work,
+                     void* stream);
+int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpacked, void* work,
+                      void* stream);
+/* Sets the batch tiling (same meaning as shtn_plan_set_tiling; split is
+ * ignored).  Re-upload afterwards. */
+int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int analys_lp, int fw, int m_pairing);
+
+/* ---- kernel timing for benchmarks ----
+ * When enabled, every kernel launched by the library is bracketed by a pair of
+ * HIP events recorded on the launch stream.  shtn_profile_read waits for the
+ * recorded events and returns, for one kernel kind, the summed duration in
+ * milliseconds and the number of launches since the last reset.  Kinds:
+ * 0 spectrum rescale, 1 Legendre synthesis, 2 Legendre analysis,
+ * 3 Fourier synthesis (c2r), 4 Fourier analysis (r2c).  Not for use under
+ * stream capture. */
+int shtn_profile_enable(int on);
+int shtn_profile_read(int kind, double* total_ms, long* launches);
+void shtn_profile_reset(void);
+
+/* Error reporting. */
+const char* shtn_strerror(int code);
+const char* shtn_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHTN_H */

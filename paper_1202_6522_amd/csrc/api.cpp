@@ -1,0 +1,387 @@
+// C-ABI of libshtn (declared in include/shtn.h): validation, plan upload and
+// the launch sequences of the four transforms.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "shtn.h"
+#include "shtn_internal.h"
+#include "shtn_profile.h"
+
+using namespace shtn;
+
+struct shtn_plan_s {
+    Plan* p;
+};
+
+namespace {
+thread_local std::string g_detail;
+
+int fail(int code, const std::string& msg)
+{
+    g_detail = msg;
+    return code;
+}
+
+int hip_fail(int e, const char* where)
+{
+    g_detail = std::string(where) + ": " + hipGetErrorString((hipError_t)e);
+    return SHTN_EHIP;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+const DevPlan* dplan(const Plan& p) { return (const DevPlan*)p.dev; }
+const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.dev + p.table_off[t]); }
+
+int rows_per_block(const Plan& p)
+{
+    int r = 4096 / p.K;
+    if (r < 1) r = 1;
+    if (r > p.nlat) r = p.nlat;
+    return r;
+}
+
+int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, const void* work)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (!plan->p->uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
+    if (!in || !out || !work) return fail(SHTN_EINVAL, "null data or workspace pointer");
+    if (nfields < 1) return fail(SHTN_EINVAL, "nfields must be >= 1");
+    if (in == out) return fail(SHTN_EINVAL, "input and output must not alias");
+    return SHTN_OK;
+}
+
+// Legendre synthesis-type pass (synthesis or adjoint of the analysis) then c2r.
+int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream,
+            int adjoint)
+{
+    int rc = check_call(plan, Q, grid, nfields, work);
+    if (rc) return rc;
+    const Plan& p = *plan->p;
+    WorkLayout wl = work_layout(p, nfields);
+    double* F = (double*)work;
+    double* Qs = (double*)((char*)work + wl.f_bytes);
+    int e;
+    {
+        ProfScope ps(PK_PRESCALE, stream);
+        e = launch_prescale(dplan(p), nullptr, nullptr, nullptr, Q, Qs, p.nlm, nfields, stream);
+    }
+    if (e) return hip_fail(e, "prescale launch");
+    LegLaunch l{};
+    l.plans = dplan(p);
+    l.units = dev_table_int(p, 13);
+    l.nunits = (int)(p.synth_units.size() / kUnitInts);
+    l.grid_y = (nfields + p.tiling.fw - 1) / p.tiling.fw;
+    l.in = Qs;
+    l.out = F;
+    l.nfields = nfields;
+    l.adjoint = adjoint;
+    l.lp = p.tiling.synth_lp;
+    l.fw = p.tiling.fw;
+    {
+        ProfScope ps(PK_LEG_SYNTH, stream);
+        e = launch_legendre_synth(l, stream);
+    }
+    if (e) return hip_fail(e, "legendre synthesis launch");
+    FftLaunch f{};
+    f.plans = dplan(p);
+    f.rows_per_block = rows_per_block(p);
+    f.nblocks = (p.nlat + f.rows_per_block - 1) / f.rows_per_block;
+    f.grid_y = nfields;
+    f.K = p.K;
+    f.in = F;
+    f.out = grid;
+    f.nfields = nfields;
+    f.scale = 1.0;
+    {
+        ProfScope ps(PK_C2R, stream);
+        e = launch_c2r(f, stream);
+    }
+    if (e) return hip_fail(e, "c2r launch");
+    return SHTN_OK;
+}
+
+// r2c then Legendre analysis-type pass (analysis or adjoint of the synthesis).
+int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work, void* stream,
+            int adjoint)
+{
+    int rc = check_call(plan, grid, Q, nfields, work);
+    if (rc) return rc;
+    const Plan& p = *plan->p;
+    if (p.npair > kMaxAnalysPairs)
+        return fail(SHTN_EUNSUPPORTED, "analysis supports at most 1024 latitudes");
+    double* F = (double*)work;
+    FftLaunch f{};
+    f.plans = dplan(p);
+    f.rows_per_block = rows_per_block(p);
+    f.nblocks = (p.nlat + f.rows_per_block - 1) / f.rows_per_block;
+    f.grid_y = nfields;
+    f.K = p.K;
+    f.in = grid;
+    f.out = F;
+    f.nfields = nfields;
+    f.scale = adjoint ? 1.0 : 2.0 * 3.14159265358979323846 / p.nphi;
+    int e;
+    {
+        ProfScope ps(PK_R2C, stream);
+        e = launch_r2c(f, stream);
+    }
+    if (e) return hip_fail(e, "r2c launch");
+    LegLaunch l{};
+    l.plans = dplan(p);
+    l.units = dev_table_int(p, 14);
+    l.nunits = (int)(p.analys_units.size() / kUnitInts);
+    l.grid_y = (nfields + p.tiling.fw - 1) / p.tiling.fw;
+    l.in = F;
+    l.out = Q;
+    l.nfields = nfields;
+    l.adjoint = adjoint;
+    l.lp = p.tiling.analys_lp;
+    l.fw = p.tiling.fw;
+    {
+        ProfScope ps(PK_LEG_ANALYS, stream);
+        e = launch_legendre_analys(l, stream);
+    }
+    if (e) return hip_fail(e, "legendre analysis launch");
+    return SHTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+shtn_plan_t shtn_plan(int lmax, int mmax, int nlat, int nphi)
+{
+    try {
+        if (nphi >= 1 && !is_pow2(nphi)) {
+            g_detail = "nphi must be a power of two";
+            return nullptr;
+        }
+        if (nphi < 2) {
+            g_detail = "nphi must be >= 2";
+            return nullptr;
+        }
+        if (nphi > 8192) {
+            g_detail = "nphi > 8192 is not supported";
+            return nullptr;
+        }
+        if (lmax > 8191) {
+            g_detail = "lmax > 8191 is not supported";
+            return nullptr;
+        }
+        std::string err;
+        Plan* p = build_plan(lmax, mmax, nlat, nphi, err);
+        if (!p) {
+            g_detail = err;
+            return nullptr;
+        }
+        shtn_plan_s* h = new shtn_plan_s;
+        h->p = p;
+        return h;
+    } catch (const std::bad_alloc&) {
+        g_detail = "out of host memory";
+        return nullptr;
+    } catch (...) {
+        g_detail = "internal error";
+        return nullptr;
+    }
+}
+
+void shtn_plan_destroy(shtn_plan_t plan)
+{
+    if (!plan) return;
+    delete plan->p;
+    delete plan;
+}
+
+size_t shtn_plan_device_bytes(shtn_plan_t plan)
+{
+    if (!plan || !plan->p) return 0;
+    return plan->p->image.size();
+}
+
+int shtn_plan_upload(shtn_plan_t plan, void* dev_buf, void* stream)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (!dev_buf) return fail(SHTN_EINVAL, "null device buffer");
+    if ((uintptr_t)dev_buf % 256) return fail(SHTN_EINVAL, "device buffer must be 256-byte aligned");
+    Plan& p = *plan->p;
+    char* base = (char*)dev_buf;
+    DevPlan d{};
+    int t = 0;
+    d.xp = (const double*)(base + p.table_off[t++]);
+    d.wq = (const double*)(base + p.table_off[t++]);
+    d.wfull = (const double*)(base + p.table_off[t++]);
+    d.beta = (const double*)(base + p.table_off[t++]);
+    d.gamma = (const double*)(base + p.table_off[t++]);
+    d.start_y = (const double*)(base + p.table_off[t++]);
+    d.start_k = (const int*)(base + p.table_off[t++]);
+    d.segexp = (const int*)(base + p.table_off[t++]);
+    d.segoff = (const int*)(base + p.table_off[t++]);
+    d.rst_y = (const double*)(base + p.table_off[t++]);
+    d.rst_k = (const int*)(base + p.table_off[t++]);
+    d.tw = (const double*)(base + p.table_off[t++]);
+    d.rtw = (const double*)(base + p.table_off[t++]);
+    d.synth_units = (const int*)(base + p.table_off[t++]);
+    d.analys_units = (const int*)(base + p.table_off[t++]);
+    d.L = p.L;
+    d.M = p.M;
+    d.nlat = p.nlat;
+    d.nphi = p.nphi;
+    d.npair = p.npair;
+    d.K = p.K;
+    d.nlm = p.nlm;
+    d.n_synth_units = (int)(p.synth_units.size() / kUnitInts);
+    d.n_analys_units = (int)(p.analys_units.size() / kUnitInts);
+    d.synth_lp = p.tiling.synth_lp;
+    d.analys_lp = p.tiling.analys_lp;
+    d.fw = p.tiling.fw;
+    std::memcpy(p.image.data(), &d, sizeof(DevPlan));
+    hipError_t e = hipMemcpyAsync(dev_buf, p.image.data(), p.image.size(), hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail((int)e, "plan upload copy");
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail((int)e, "plan upload sync");
+    p.dev = dev_buf;
+    p.uploaded = true;
+    return SHTN_OK;
+}
+
+size_t shtn_work_bytes(shtn_plan_t plan, int nfields)
+{
+    if (!plan || !plan->p || nfields < 1) return 0;
+    return work_layout(*plan->p, nfields).total;
+}
+
+int shtn_synth(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream)
+{
+    return to_grid(plan, Q, grid, nfields, work, stream, 0);
+}
+
+int shtn_analys_adj(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work,
+                    void* stream)
+{
+    return to_grid(plan, Q, grid, nfields, work, stream, 1);
+}
+
+int shtn_analys(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work, void* stream)
+{
+    return to_spec(plan, grid, Q, nfields, work, stream, 0);
+}
+
+int shtn_synth_adj(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work,
+                   void* stream)
+{
+    return to_spec(plan, grid, Q, nfields, work, stream, 1);
+}
+
+long shtn_nlm(shtn_plan_t plan)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    return plan->p->nlm;
+}
+
+long shtn_lm_index(shtn_plan_t plan, int n, int m)
+{
+    if (!plan || !plan->p) return -1;
+    const Plan& p = *plan->p;
+    if (m < 0 || m > p.M || n < m || n > p.L) return -1;
+    return lm_index(p.L, n, m);
+}
+
+int shtn_get_grid(shtn_plan_t plan, double* x_host, double* w_host)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    const Plan& p = *plan->p;
+    if (x_host) std::memcpy(x_host, p.x.data(), sizeof(double) * p.nlat);
+    if (w_host) std::memcpy(w_host, p.w.data(), sizeof(double) * p.nlat);
+    return SHTN_OK;
+}
+
+double shtn_legendre_flops(shtn_plan_t plan)
+{
+    if (!plan || !plan->p) return 0.0;
+    return 8.0 * (double)plan->p->npair * (double)plan->p->nlm;
+}
+
+long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    const Plan& p = *plan->p;
+    const void* src = nullptr;
+    size_t n = 0;
+    int tiling[8] = {p.tiling.synth_lp, p.tiling.analys_lp, p.tiling.fw, p.tiling.m_pairing,
+                     p.split_used, kSegLen, kGuardUnit, kChunk};
+    switch (which) {
+    case 0: src = p.xp.data(); n = p.xp.size() * 8; break;
+    case 1: src = p.sp.data(); n = p.sp.size() * 8; break;
+    case 2: src = p.wq.data(); n = p.wq.size() * 8; break;
+    case 3: src = p.beta.data(); n = p.beta.size() * 8; break;
+    case 4: src = p.gamma.data(); n = p.gamma.size() * 8; break;
+    case 5: src = p.start_y.data(); n = p.start_y.size() * 8; break;
+    case 6: src = p.start_k.data(); n = p.start_k.size() * 4; break;
+    case 7: src = p.segexp.data(); n = p.segexp.size() * 4; break;
+    case 8: src = p.segoff.data(); n = p.segoff.size() * 4; break;
+    case 9: src = p.rst_y.data(); n = p.rst_y.size() * 8; break;
+    case 10: src = p.rst_k.data(); n = p.rst_k.size() * 4; break;
+    case 11: src = p.analys_units.data(); n = p.analys_units.size() * 4; break;
+    case 12: src = p.synth_units.data(); n = p.synth_units.size() * 4; break;
+    case 13: src = tiling; n = sizeof(tiling); break;
+    default: return fail(SHTN_EINVAL, "unknown table");
+    }
+    if (dst && bytes >= n && n) std::memcpy(dst, src, n);
+    return (long)n;
+}
+
+int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
+                         int split)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    Plan& p = *plan->p;
+    auto okl = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
+    if (!okl(synth_lp) || !okl(analys_lp)) return fail(SHTN_EINVAL, "lp must be 1, 2, 4 or 8");
+    if (!(fw == 1 || fw == 2)) return fail(SHTN_EINVAL, "fw must be 1 or 2");
+    if (fw == 2 && synth_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs synth_lp <= 4");
+    if (fw == 2 && analys_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs analys_lp <= 4");
+    if (64 * analys_lp < p.npair && p.npair <= kMaxAnalysPairs)
+        return fail(SHTN_EINVAL, "analys_lp too small: one analysis wave must cover all latitude pairs");
+    if (split < 0 || split % kSegLen) return fail(SHTN_EINVAL, "split must be a multiple of 32");
+    Tiling old = p.tiling;
+    p.tiling.synth_lp = synth_lp;
+    p.tiling.analys_lp = analys_lp;
+    p.tiling.fw = fw;
+    p.tiling.m_pairing = m_pairing ? 1 : 0;
+    p.tiling.split = split;
+    std::string err;
+    if (rebuild_units(p, err)) {
+        p.tiling = old;
+        rebuild_units(p, err);
+        build_image(p);
+        return fail(SHTN_EINVAL, err);
+    }
+    build_image(p);
+    p.uploaded = false;
+    p.dev = nullptr;
+    return SHTN_OK;
+}
+
+const char* shtn_strerror(int code)
+{
+    switch (code) {
+    case SHTN_OK: return "success";
+    case SHTN_EINVAL: return "invalid argument";
+    case SHTN_EUNSUPPORTED: return "unsupported configuration";
+    case SHTN_ESTATE: return "plan not uploaded";
+    case SHTN_EHIP: return "HIP runtime error";
+    case SHTN_ENOMEM: return "out of host memory";
+    default: return "unknown error";
+    }
+}
+
+const char* shtn_last_error_detail(void) { return g_detail.c_str(); }
+
+}  // extern "C"

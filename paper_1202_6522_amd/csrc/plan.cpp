@@ -1,0 +1,359 @@
+// Host-side plan construction: Gauss grid, recurrence tables, start values
+// with scaled exponents, analysis restart states, FFT twiddles and the work
+// unit lists.  Pure host code: no device calls.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "shtn_internal.h"
+
+namespace shtn {
+
+typedef long double ld;
+static const ld kPi = 3.141592653589793238462643383279502884L;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Legendre P_N and P_{N-1} at x by the Bonnet recurrence (Sec. 2.1).
+static void legendre_pair(int N, ld x, ld& pn, ld& pn1)
+{
+    ld p0 = 1, p1 = x;
+    if (N == 0) { pn = 1; pn1 = 0; return; }
+    for (int n = 2; n <= N; n++) {
+        ld p2 = ((2 * n - 1) * x * p1 - (n - 1) * p0) / n;
+        p0 = p1;
+        p1 = p2;
+    }
+    pn = p1;
+    pn1 = p0;
+}
+
+// Gauss-Legendre rule (Sec. 2.3, eq. gauss) by Newton iteration on the
+// colatitude theta (long double): f(theta) = P_N(cos theta),
+// f'(theta) = -N (P_{N-1} - x P_N) / sin theta.  Working in theta keeps
+// sin(theta) accurate at the poles, where it sets the P_m^m start values.
+// Weight w = 2 sin^2 / (N^2 (P_{N-1} - x P_N)^2) (= 2/((1-x^2) P_N'^2)).
+static void gauss_rule(int N, std::vector<ld>& theta, std::vector<ld>& w)
+{
+    theta.assign(N, 0);
+    w.assign(N, 0);
+    for (int i = 0; i < (N + 1) / 2; i++) {
+        ld t;
+        if ((N & 1) && i == N / 2) {
+            t = kPi / 2;
+        } else {
+            t = kPi * ((ld)i + 0.75L) / ((ld)N + 0.5L);
+            for (int it = 0; it < 100; it++) {
+                ld x = cosl(t), s = sinl(t), pn, pn1;
+                legendre_pair(N, x, pn, pn1);
+                ld d = -N * (pn1 - x * pn) / s;
+                ld dt = pn / d;
+                t -= dt;
+                if (fabsl(dt) <= 4 * LDBL_EPSILON * t) {
+                    x = cosl(t); s = sinl(t);
+                    legendre_pair(N, x, pn, pn1);
+                    d = -N * (pn1 - x * pn) / s;
+                    t -= pn / d;
+                    break;
+                }
+            }
+        }
+        ld x = cosl(t), s = sinl(t), pn, pn1;
+        if ((N & 1) && i == N / 2) x = 0;
+        legendre_pair(N, x, pn, pn1);
+        ld dd = N * (pn1 - x * pn);
+        ld wi = 2 * s * s / (dd * dd);
+        theta[i] = t;
+        w[i] = wi;
+        theta[N - 1 - i] = kPi - t;
+        w[N - 1 - i] = wi;
+    }
+}
+
+static int log2_floor(ld v)
+{
+    int e;
+    frexpl(v, &e);  // v = f 2^e, f in [0.5, 1)
+    return e - 1;
+}
+
+Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
+{
+    if (L < 0 || M < 0 || M > L) { err = "need 0 <= mmax <= lmax"; return nullptr; }
+    if (nlat < 1) { err = "need nlat >= 1"; return nullptr; }
+    if (nphi < 1 || nphi <= 2 * M) { err = "need nphi > 2*mmax (no aliasing of order mmax)"; return nullptr; }
+    if (L > 16383 || nlat > 32768 || nphi > (1 << 16)) { err = "size beyond the supported range"; return nullptr; }
+    Plan* p = new Plan();
+    p->L = L; p->M = M; p->nlat = nlat; p->nphi = nphi;
+    p->npair = (nlat + 1) / 2;
+    p->K = nphi / 2 > 0 ? nphi / 2 : 1;
+    p->nlm = (long)(M + 1) * (L + 1) - (long)M * (M + 1) / 2;
+    const int np = p->npair;
+
+    // ---- grid ----
+    std::vector<ld> th, wl;
+    gauss_rule(nlat, th, wl);
+    p->x.resize(nlat); p->w.resize(nlat);
+    for (int i = 0; i < nlat; i++) {
+        p->x[i] = (double)((nlat & 1) && i == nlat / 2 ? 0.0L : cosl(th[i]));
+        p->w[i] = (double)wl[i];
+    }
+    p->xp.resize(np); p->sp.resize(np); p->wq.resize(np); p->wfull.resize(np);
+    for (int i = 0; i < np; i++) {
+        p->xp[i] = p->x[i];
+        p->sp[i] = (double)sinl(th[i]);
+        p->wfull[i] = p->w[i];
+        bool middle = (nlat & 1) && i == nlat / 2;
+        p->wq[i] = middle ? 0.5 * p->w[i] : p->w[i];
+    }
+
+    // ---- rescaled recurrence tables (Sec. 3.2, eq. rec) ----
+    p->beta.resize(p->nlm); p->gamma.resize(p->nlm);
+    p->segoff.resize(M + 2);
+    int nseg_total = 0;
+    for (int m = 0; m <= M; m++) {
+        p->segoff[m] = nseg_total;
+        nseg_total += (L - m + 1 + kSegLen - 1) / kSegLen;
+    }
+    p->segoff[M + 1] = nseg_total;
+    p->segexp.assign(nseg_total, 0);
+    for (int m = 0; m <= M; m++) {
+        long base = lm_index(L, m, m);
+        ld alpha = 1;
+        int E = 0;
+        for (int n = m; n <= L; n++) {
+            int j = n - m;
+            if (n > m) {
+                ld a = sqrtl((ld)(4.0L * n * n - 1) / ((ld)n * n - (ld)m * m));
+                alpha *= a;
+            }
+            if (j > 0 && j % kSegLen == 0) {
+                int En = log2_floor(alpha);
+                p->segexp[p->segoff[m] + j / kSegLen] = En - E;
+                E = En;
+            }
+            double b;
+            if (j == 0) b = 1.0;        // u_m = 1 * (start value) with u_{m-1} = 0
+            else if (j == 1) b = 0.0;   // u_{m+1} = x u_m
+            else {
+                long long num = (long long)(n - 1 - m) * (n - 1 + m);
+                long long den = (long long)(2 * n - 1) * (2 * n - 3);
+                b = (double)(-(ld)num / (ld)den);
+            }
+            p->beta[base + j] = b;
+            p->gamma[base + j] = (double)ldexpl(alpha, -E);
+        }
+    }
+
+    // ---- P_m^m start values with scaled exponents (Sec. 3.2 and 3.5) ----
+    // P_m^m(x) = (-1)^m sqrt(prod_{k<=m}(2k+1)/(2k) / (4 pi)) sin^m(theta),
+    // kept as mantissa * 2^e (long double, renormalised every step), then
+    // split as w * 2^{-256 k} with k >= 0 minimal such that |w| >= 2^-256.
+    p->start_y.assign((size_t)(M + 1) * np, 0.0);
+    p->start_k.assign((size_t)(M + 1) * np, 0);
+    for (int i = 0; i < np; i++) {
+        ld s = sinl(th[i]);
+        ld v = sqrtl(1.0L / (4 * kPi));
+        long e = 0;
+        for (int m = 0; m <= M; m++) {
+            if (m > 0) {
+                v *= -sqrtl((ld)(2 * m + 1) / (ld)(2 * m)) * s;
+                int ei;
+                v = frexpl(v, &ei);
+                e += ei;
+            }
+            // value = v 2^e, |v| in [0.5, 1) (or exactly 1/sqrt(4 pi) at m = 0)
+            long k = 0;
+            long ee = e;
+            // |value| < 2^{e}; need |value| 2^{256 k} >= 2^{-256} for the minimal k
+            while (ee + (long)kGuardUnit * k < -(long)kGuardUnit + 1) k++;
+            p->start_y[(size_t)m * np + i] = (double)ldexpl(v, (int)(ee + (long)kGuardUnit * k));
+            p->start_k[(size_t)m * np + i] = (int)k;
+        }
+    }
+
+    // ---- FFT twiddles ----
+    const int K = p->K;
+    p->tw.resize(2 * (size_t)K);
+    for (int t = 0; t < K; t++) {
+        ld a = 2 * kPi * (ld)t / (ld)K;
+        p->tw[2 * t] = (double)cosl(a);
+        p->tw[2 * t + 1] = (double)(-sinl(a));
+    }
+    p->rtw.resize(2 * (size_t)(K + 1));
+    for (int m = 0; m <= K; m++) {
+        ld a = kPi * (ld)m / (ld)K;  // 2 pi m / (2K)
+        p->rtw[2 * m] = (double)cosl(a);
+        p->rtw[2 * m + 1] = (double)sinl(a);
+    }
+
+    // default tiling: enough synthesis waves to fill the chip at large sizes;
+    // one analysis wave covers every latitude pair of its order
+    p->tiling.synth_lp = np >= 512 ? 2 : 1;
+    p->tiling.analys_lp = 1;
+    while (64 * p->tiling.analys_lp < np && p->tiling.analys_lp < 8) p->tiling.analys_lp *= 2;
+    if (rebuild_units(*p, err)) { delete p; return nullptr; }
+    build_image(*p);
+    return p;
+}
+
+// Emulates the kernels' per-lane recurrence (same operations, same order,
+// fused multiply-adds) from n = m up to the listed restart steps.
+static void restart_states(const Plan& p, int m, const std::vector<int>& j_list,
+                           std::vector<double>& ys, std::vector<int>& ks)
+{
+    const int np = p.npair;
+    const long base = lm_index(p.L, m, m);
+    const int jmax = j_list.empty() ? 0 : j_list.back();
+    ys.assign(j_list.size() * np * 2, 0.0);
+    ks.assign(j_list.size() * np, 0);
+    const double down = std::ldexp(1.0, -kGuardUnit);
+    for (int i = 0; i < np; i++) {
+        double x = p.xp[i];
+        double ua = p.start_y[(size_t)m * np + i], ub = 0.0;
+        int k = p.start_k[(size_t)m * np + i];
+        size_t r = 0;
+        for (int j = 0; j <= jmax; j += 2) {
+            if (r < j_list.size() && j == j_list[r]) {
+                ys[(r * np + i) * 2] = ua;
+                ys[(r * np + i) * 2 + 1] = ub;
+                ks[r * np + i] = k;
+                r++;
+                if (r == j_list.size()) break;
+            }
+            if (j > 0 && j % kSegLen == 0) {
+                double sc = std::ldexp(1.0, p.segexp[p.segoff[m] + j / kSegLen]);
+                ua *= sc;
+                ub *= sc;
+            }
+            if (j % kGuardEvery == 0 && k > 0 && (std::fabs(ua) >= 1.0 || std::fabs(ub) >= 1.0)) {
+                ua *= down;
+                ub *= down;
+                k -= 1;
+            }
+            ua = std::fma(x, ub, p.beta[base + j] * ua);
+            if (j + 1 <= p.L - m) ub = std::fma(x, ua, p.beta[base + j + 1] * ub);
+        }
+    }
+}
+
+int rebuild_units(Plan& p, std::string& err)
+{
+    const Tiling& t = p.tiling;
+    const int np = p.npair, L = p.L, M = p.M;
+    // ---- synthesis units: (m [, mmax - m]) x latitude-pair block ----
+    p.synth_units.clear();
+    const int blk = 64 * t.synth_lp;
+    const int nblk = (np + blk - 1) / blk;
+    std::vector<std::pair<int, int>> mpairs;
+    for (int m = 0; m <= M; m++) {
+        if (t.m_pairing) {
+            int m2 = M - m;
+            if (m < m2) mpairs.push_back({m, m2});
+            else if (m == m2) mpairs.push_back({m, -1});
+        } else {
+            mpairs.push_back({m, -1});
+        }
+    }
+    for (auto& mp : mpairs)
+        for (int b = 0; b < nblk; b++) {
+            int u[kUnitInts] = {0, t.fw, 0, mp.first, mp.second, b * blk, 0, -1};
+            p.synth_units.insert(p.synth_units.end(), u, u + kUnitInts);
+        }
+
+    // ---- analysis units: (m, degree range) pieces, longest first ----
+    int S = t.split;
+    if (S <= 0) {
+        long target = (p.nlm + 2047) / 2048;  // about two waves per SIMD at large sizes
+        S = (int)std::max<long>(64, ((target + kSegLen - 1) / kSegLen) * kSegLen);
+    }
+    if (S % kSegLen) { err = "split must be a multiple of 32"; return -1; }
+    p.split_used = S;
+    struct AU { int m, j0, j1, rst; };
+    std::vector<AU> au;
+    std::vector<std::vector<int>> rj(M + 1);
+    int nrst = 0;
+    std::vector<int> rbase(M + 1, 0);
+    for (int m = 0; m <= M; m++) {
+        int nj = L - m + 1;
+        rbase[m] = nrst;
+        for (int j0 = 0; j0 < nj; j0 += S) {
+            int r = -1;
+            if (j0 > 0) { r = nrst++; rj[m].push_back(j0); }
+            au.push_back({m, j0, std::min(j0 + S, nj), r});
+        }
+    }
+    std::stable_sort(au.begin(), au.end(),
+                     [](const AU& a, const AU& b) { return (a.j1 - a.j0) > (b.j1 - b.j0); });
+    p.analys_units.clear();
+    for (auto& a : au) {
+        int u[kUnitInts] = {0, t.fw, 0, a.m, -1, a.j0, a.j1, a.rst};
+        p.analys_units.insert(p.analys_units.end(), u, u + kUnitInts);
+    }
+    p.rst_y.assign((size_t)nrst * np * 2, 0.0);
+    p.rst_k.assign((size_t)nrst * np, 0);
+    // restart states, orders split over host threads
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned tid = 0; tid < nth; tid++) {
+        pool.emplace_back([&, tid]() {
+            std::vector<double> ys;
+            std::vector<int> ks;
+            for (int m = (int)tid; m <= M; m += (int)nth) {
+                if (rj[m].empty()) continue;
+                restart_states(p, m, rj[m], ys, ks);
+                std::memcpy(&p.rst_y[(size_t)rbase[m] * np * 2], ys.data(), ys.size() * sizeof(double));
+                std::memcpy(&p.rst_k[(size_t)rbase[m] * np], ks.data(), ks.size() * sizeof(int));
+            }
+        });
+    }
+    for (auto& th : pool) th.join();
+    return 0;
+}
+
+template <typename T>
+static size_t put(std::vector<unsigned char>& img, size_t off, const std::vector<T>& v)
+{
+    size_t bytes = v.size() * sizeof(T);
+    if (img.size() < off + bytes) img.resize(off + bytes);
+    if (bytes) std::memcpy(img.data() + off, v.data(), bytes);
+    return align256(off + bytes);
+}
+
+void build_image(Plan& p)
+{
+    p.image.clear();
+    p.table_off.assign(16, 0);
+    size_t off = align256(sizeof(DevPlan));
+    p.image.resize(off, 0);
+    int t = 0;
+    p.table_off[t++] = off; off = put(p.image, off, p.xp);
+    p.table_off[t++] = off; off = put(p.image, off, p.wq);
+    p.table_off[t++] = off; off = put(p.image, off, p.wfull);
+    p.table_off[t++] = off; off = put(p.image, off, p.beta);
+    p.table_off[t++] = off; off = put(p.image, off, p.gamma);
+    p.table_off[t++] = off; off = put(p.image, off, p.start_y);
+    p.table_off[t++] = off; off = put(p.image, off, p.start_k);
+    p.table_off[t++] = off; off = put(p.image, off, p.segexp);
+    p.table_off[t++] = off; off = put(p.image, off, p.segoff);
+    p.table_off[t++] = off; off = put(p.image, off, p.rst_y);
+    p.table_off[t++] = off; off = put(p.image, off, p.rst_k);
+    p.table_off[t++] = off; off = put(p.image, off, p.tw);
+    p.table_off[t++] = off; off = put(p.image, off, p.rtw);
+    p.table_off[t++] = off; off = put(p.image, off, p.synth_units);
+    p.table_off[t++] = off; off = put(p.image, off, p.analys_units);
+    p.image.resize(off, 0);
+}
+
+WorkLayout work_layout(const Plan& p, int nfields)
+{
+    WorkLayout w;
+    w.f_bytes = align256((size_t)nfields * (p.M + 1) * p.nlat * 16);
+    w.q_bytes = align256((size_t)nfields * p.nlm * 16);
+    w.total = w.f_bytes + w.q_bytes;
+    return w;
+}
+
+}  // namespace shtn

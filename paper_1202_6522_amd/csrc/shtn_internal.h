@@ -1,0 +1,152 @@
+// Internal structures shared by the host plan code, the C-ABI layer and the
+// HIP kernels.  Not part of the public interface (include/shtn.h).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace shtn {
+
+// Rescaled recurrence (Sec. 3.2, eq. rec, divided through by
+// alpha_n = prod_{j=m+1}^{n} a_j^m):
+//   y_n = x y_{n-1} + beta_n y_{n-2},  beta_n = -((n-1)^2 - m^2)/((2n-1)(2n-3)),
+//   P_n^m(x) = alpha_n y_n.
+// The kernels carry u_n = y_n 2^{E_s} where E_s is constant over a segment of
+// kSegLen consecutive degrees, so u stays within the range of P; at a segment
+// start both recurrence states are multiplied by 2^{E_s - E_{s-1}} (exact).
+// gamma_n = alpha_n 2^{-E_s} maps u back to P.
+constexpr int kSegLen = 32;
+// Underflow guard (Sec. 3.5): a lane keeps (w, k) with u = w 2^{-kGuardUnit k}.
+// While k > 0 the value is treated as 0 in the sums but the recurrence goes on;
+// every kGuardEvery steps, if |w| >= 1 the lane rescales w by 2^{-kGuardUnit}
+// and decrements k.
+constexpr int kGuardUnit = 256;
+constexpr int kGuardEvery = 4;
+// Analysis accumulates kChunk consecutive degrees per lane before a
+// cross-lane reduction.
+constexpr int kChunk = 16;
+// Largest latitude-pair count one analysis wave covers (64 lanes x 8 pairs).
+constexpr int kMaxAnalysPairs = 512;
+
+// One work unit of a Legendre kernel = one wave (8 ints).
+enum UnitField {
+    U_FIELD = 0,  // first field of the unit (relative; plus blockIdx.y * fw for plan calls)
+    U_NF = 1,     // number of fields in the unit (<= fw)
+    U_PLAN = 2,   // plan index (batch) or 0
+    U_M0 = 3,     // first order m
+    U_M1 = 4,     // second order (m pairing) or -1
+    U_PB = 5,     // synthesis: first latitude pair of the block; analysis: first step j0
+    U_J1 = 6,     // analysis: one past the last step (n = m + j)
+    U_RST = 7,    // analysis: restart slot or -1 (start at n = m)
+};
+constexpr int kUnitInts = 8;
+
+// Device-resident view of a plan (stored at the start of its device buffer).
+struct DevPlan {
+    const double* xp;      // [npair] x = cos(theta) of the northern node of each pair
+    const double* wq;      // [npair] analysis weight per pair (middle node of odd nlat halved)
+    const double* wfull;   // [npair] Gauss weight per pair
+    const double* beta;    // [nlm] rescaled recurrence coefficient, m-major
+    const double* gamma;   // [nlm] output scale gamma_n
+    const double* start_y; // [(M+1) * npair] mantissa of P_m^m(x) (scaled by 2^{256 k})
+    const int* start_k;    // [(M+1) * npair] guard exponent of P_m^m
+    const int* segexp;     // per (m, segment s >= 1): E_s - E_{s-1}
+    const int* segoff;     // [M+2] index of (m, s=0) in segexp
+    const double* rst_y;   // [nrst * npair * 2] analysis restart states (ua, ub)
+    const int* rst_k;      // [nrst * npair]
+    const double* tw;      // [K] complex e^{-2 pi i t / K}
+    const double* rtw;     // [K+1] complex e^{+2 pi i m / (2K)}
+    const int* synth_units;
+    const int* analys_units;
+    int L, M, nlat, nphi, npair, K;
+    long nlm;
+    int n_synth_units, n_analys_units;
+    int synth_lp, analys_lp, fw, pad0;
+};
+
+struct Tiling {
+    int synth_lp = 2;
+    int analys_lp = 8;
+    int fw = 1;
+    int m_pairing = 1;
+    int split = 0;  // 0 = automatic
+};
+
+struct Plan {
+    int L = 0, M = 0, nlat = 0, nphi = 0, npair = 0, K = 0;
+    long nlm = 0;
+    Tiling tiling;
+    int split_used = 0;
+    // host tables
+    std::vector<double> x, w;                 // full grid
+    std::vector<double> xp, sp, wq, wfull;    // per pair
+    std::vector<double> beta, gamma;          // nlm
+    std::vector<double> start_y;              // (M+1) x npair
+    std::vector<int> start_k;
+    std::vector<int> segexp, segoff;
+    std::vector<double> rst_y;
+    std::vector<int> rst_k;
+    std::vector<double> tw, rtw;
+    std::vector<int> synth_units, analys_units;
+    // device image
+    std::vector<unsigned char> image;  // staged device buffer contents
+    std::vector<size_t> table_off;     // byte offsets of each table inside the image
+    void* dev = nullptr;               // caller's device buffer after upload
+    bool uploaded = false;
+};
+
+// Host plan construction (plan.cpp).
+Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err);
+int rebuild_units(Plan& p, std::string& err);     // units + restart states for the tiling
+void build_image(Plan& p);                        // lays out the device buffer
+inline long lm_index(int L, int n, int m) { return (long)m * (2 * L + 1 - m) / 2 + n; }
+size_t align256(size_t v);
+
+// Workspace layout of a plan call with nfields fields.
+struct WorkLayout {
+    size_t f_bytes;   // F: nfields x (M+1) x nlat complex
+    size_t q_bytes;   // rescaled spectrum: nfields x nlm complex
+    size_t total;
+};
+WorkLayout work_layout(const Plan& p, int nfields);
+
+// Kernel launchers (legendre.hip, fft.hip).  Return a hipError_t as int.
+struct LegLaunch {
+    const DevPlan* plans;  // device array of plans
+    const int* units;      // device unit array
+    int nunits;
+    int grid_y;            // blockIdx.y extent (field groups), 1 for batches
+    const long* q_off;     // per-field offset (doubles) of the spectrum, or null (f * 2 nlm)
+    const long* f_off;     // per-field offset (doubles) of F, or null (f * 2 (M+1) nlat)
+    const double* in;
+    double* out;
+    int nfields;
+    int adjoint;           // 0 forward transform, 1 adjoint variant
+    int lp, fw;            // template selection
+};
+// Qs = gamma * Q per field; q_off/s_off/fplan per field (device) or null.
+int launch_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int* fplan,
+                    const double* Q, double* Qs, long max_nlm, int nfields, void* stream);
+int launch_legendre_synth(const LegLaunch& a, void* stream);
+int launch_legendre_analys(const LegLaunch& a, void* stream);
+
+struct FftLaunch {
+    const DevPlan* plans;     // device plan array
+    const int* rowblocks;     // device: per block {field, plan, row0, nrows} or null
+    int nblocks;
+    int grid_y;
+    int K;                    // for plan calls (all fields same K)
+    int rows_per_block;
+    const long* g_off;        // per-field grid offset (doubles) or null
+    const long* f_off;        // per-field F offset (doubles) or null
+    const double* in;
+    double* out;
+    int nfields;
+    double scale;             // r2c: output scale (2 pi/nphi or 1)
+};
+int launch_c2r(const FftLaunch& a, void* stream);
+int launch_r2c(const FftLaunch& a, void* stream);
+
+}  // namespace shtn

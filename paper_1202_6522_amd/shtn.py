@@ -1,0 +1,337 @@
+"""ctypes binding of libshtn (include/shtn.h): argument marshalling only.
+
+The functions below carry the C names and signatures; every transform step
+runs in the HIP kernels of the library.  `Plan` adds torch plumbing (device
+buffers for the plan tables and the workspace, the current HIP stream).
+
+Importing this module does not load the library; the first call does, and it
+raises if libshtn.so has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshtn.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "shtn.h")
+
+SHTN_OK = 0
+SHTN_EINVAL = -1
+SHTN_EUNSUPPORTED = -2
+SHTN_ESTATE = -3
+SHTN_EHIP = -4
+SHTN_ENOMEM = -5
+
+_lib = None
+
+_c = ctypes
+_vp = _c.c_void_p
+_dp = _c.POINTER(_c.c_double)
+_sz = _c.c_size_t
+_SIGS = {
+    "shtn_plan": (_vp, [_c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "shtn_plan_destroy": (None, [_vp]),
+    "shtn_plan_device_bytes": (_sz, [_vp]),
+    "shtn_plan_upload": (_c.c_int, [_vp, _vp, _vp]),
+    "shtn_work_bytes": (_sz, [_vp, _c.c_int]),
+    "shtn_synth": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_analys": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_synth_adj": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_analys_adj": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_nlm": (_c.c_long, [_vp]),
+    "shtn_lm_index": (_c.c_long, [_vp, _c.c_int, _c.c_int]),
+    "shtn_get_grid": (_c.c_int, [_vp, _dp, _dp]),
+    "shtn_legendre_flops": (_c.c_double, [_vp]),
+    "shtn_plan_table": (_c.c_long, [_vp, _c.c_int, _vp, _sz]),
+    "shtn_plan_set_tiling": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "shtn_batch": (_vp, [_c.c_int, _c.POINTER(_vp)]),
+    "shtn_batch_destroy": (None, [_vp]),
+    "shtn_batch_offsets": (_c.c_int, [_vp, _c.POINTER(_sz), _c.POINTER(_sz)]),
+    "shtn_batch_device_bytes": (_sz, [_vp]),
+    "shtn_batch_work_bytes": (_sz, [_vp]),
+    "shtn_batch_upload": (_c.c_int, [_vp, _vp, _vp]),
+    "shtn_batch_synth": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "shtn_batch_analys": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "shtn_batch_set_tiling": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "shtn_profile_enable": (_c.c_int, [_c.c_int]),
+    "shtn_profile_read": (_c.c_int, [_c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_long)]),
+    "shtn_profile_reset": (None, []),
+    "shtn_strerror": (_c.c_char_p, [_c.c_int]),
+    "shtn_last_error_detail": (_c.c_char_p, []),
+}
+
+
+class ShtnError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        lib = load_library()
+        msg = "%s: %s (%s)" % (where, lib.shtn_strerror(code).decode(),
+                               lib.shtn_last_error_detail().decode())
+        super().__init__(msg)
+
+
+def load_library():
+    """Loads libshtn.so (built by paper_1202_6522_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libshtn.so is not built: run `python -m paper_1202_6522_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def declared_functions():
+    """Names of the functions declared in include/shtn.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(shtn_\w+)\s*\(", text)))
+
+
+def check(code, where):
+    if code != SHTN_OK:
+        raise ShtnError(code, where)
+    return code
+
+
+# --- thin wrappers with the C names ---------------------------------------
+
+def shtn_plan(lmax, mmax, nlat, nphi):
+    lib = load_library()
+    h = lib.shtn_plan(lmax, mmax, nlat, nphi)
+    if not h:
+        raise ValueError("shtn_plan(%d, %d, %d, %d): %s" % (
+            lmax, mmax, nlat, nphi, lib.shtn_last_error_detail().decode()))
+    return h
+
+
+def shtn_plan_destroy(h):
+    load_library().shtn_plan_destroy(h)
+
+
+def shtn_plan_device_bytes(h):
+    return load_library().shtn_plan_device_bytes(h)
+
+
+def shtn_plan_upload(h, dev_ptr, stream):
+    return check(load_library().shtn_plan_upload(h, dev_ptr, stream), "shtn_plan_upload")
+
+
+def shtn_work_bytes(h, nfields):
+    return load_library().shtn_work_bytes(h, nfields)
+
+
+def shtn_synth(h, Q, grid, nfields, work, stream):
+    return check(load_library().shtn_synth(h, Q, grid, nfields, work, stream), "shtn_synth")
+
+
+def shtn_analys(h, grid, Q, nfields, work, stream):
+    return check(load_library().shtn_analys(h, grid, Q, nfields, work, stream), "shtn_analys")
+
+
+def shtn_synth_adj(h, grid, Q, nfields, work, stream):
+    return check(load_library().shtn_synth_adj(h, grid, Q, nfields, work, stream), "shtn_synth_adj")
+
+
+def shtn_analys_adj(h, Q, grid, nfields, work, stream):
+    return check(load_library().shtn_analys_adj(h, Q, grid, nfields, work, stream),
+                 "shtn_analys_adj")
+
+
+def shtn_nlm(h):
+    return load_library().shtn_nlm(h)
+
+
+def shtn_lm_index(h, n, m):
+    return load_library().shtn_lm_index(h, n, m)
+
+
+def shtn_get_grid(h, nlat):
+    x = np.zeros(nlat)
+    w = np.zeros(nlat)
+    check(load_library().shtn_get_grid(h, x.ctypes.data_as(_dp), w.ctypes.data_as(_dp)),
+          "shtn_get_grid")
+    return x, w
+
+
+def shtn_legendre_flops(h):
+    return load_library().shtn_legendre_flops(h)
+
+
+_TABLE_DTYPES = {0: np.float64, 1: np.float64, 2: np.float64, 3: np.float64, 4: np.float64,
+                 5: np.float64, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.float64,
+                 10: np.int32, 11: np.int32, 12: np.int32, 13: np.int32}
+
+
+def shtn_plan_table(h, which):
+    lib = load_library()
+    n = lib.shtn_plan_table(h, which, None, 0)
+    if n < 0:
+        raise ShtnError(int(n), "shtn_plan_table")
+    dt = _TABLE_DTYPES[which]
+    out = np.zeros(n // np.dtype(dt).itemsize, dtype=dt)
+    if n:
+        lib.shtn_plan_table(h, which, out.ctypes.data, n)
+    return out
+
+
+def shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split=0):
+    return check(load_library().shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split),
+                 "shtn_plan_set_tiling")
+
+
+PROFILE_KINDS = {0: "prescale", 1: "legendre_synth", 2: "legendre_analys", 3: "c2r", 4: "r2c"}
+
+
+def shtn_profile_enable(on):
+    return check(load_library().shtn_profile_enable(1 if on else 0), "shtn_profile_enable")
+
+
+def shtn_profile_read(kind):
+    ms = _c.c_double()
+    n = _c.c_long()
+    check(load_library().shtn_profile_read(kind, _c.byref(ms), _c.byref(n)), "shtn_profile_read")
+    return ms.value, n.value
+
+
+def shtn_profile_reset():
+    load_library().shtn_profile_reset()
+
+
+def shtn_strerror(code):
+    return load_library().shtn_strerror(code).decode()
+
+
+def shtn_last_error_detail():
+    return load_library().shtn_last_error_detail().decode()
+
+
+# --- torch plumbing --------------------------------------------------------
+
+def _stream_ptr(torch, device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A transform plan whose tables live in a torch-owned device buffer."""
+
+    def __init__(self, lmax, mmax=None, nlat=None, nphi=None, device="cuda", tiling=None):
+        import torch
+        self.lmax = int(lmax)
+        self.mmax = int(lmax if mmax is None else mmax)
+        self.nlat = int(self.lmax + 1 if nlat is None else nlat)
+        self.nphi = int(2 * (self.lmax + 1) if nphi is None else nphi)
+        self.device = torch.device(device)
+        self.handle = shtn_plan(self.lmax, self.mmax, self.nlat, self.nphi)
+        self.nlm = int(shtn_nlm(self.handle))
+        self.npair = (self.nlat + 1) // 2
+        self._work = {}
+        self._dev = None
+        if tiling is not None:
+            self.set_tiling(**tiling)
+        else:
+            self._upload()
+
+    def _upload(self):
+        import torch
+        nbytes = shtn_plan_device_bytes(self.handle)
+        self._dev = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._dev.data_ptr()
+        off = (-ptr) % 256
+        shtn_plan_upload(self.handle, ptr + off, _stream_ptr(torch, self.device))
+
+    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=1, split=0):
+        shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, fw, m_pairing, split)
+        self._upload()
+
+    def tiling(self):
+        t = shtn_plan_table(self.handle, 13)
+        return dict(synth_lp=int(t[0]), analys_lp=int(t[1]), fw=int(t[2]), m_pairing=int(t[3]),
+                    split=int(t[4]))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                shtn_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def grid(self):
+        return shtn_get_grid(self.handle, self.nlat)
+
+    def legendre_flops(self):
+        return shtn_legendre_flops(self.handle)
+
+    def lm_index(self, n, m):
+        return shtn_lm_index(self.handle, n, m)
+
+    def workspace(self, nfields):
+        import torch
+        w = self._work.get(nfields)
+        if w is None:
+            nb = shtn_work_bytes(self.handle, nfields)
+            w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self._work[nfields] = w
+        return w.data_ptr() + ((-w.data_ptr()) % 256)
+
+    # shape checks + calls
+    def _spec_in(self, Q):
+        import torch
+        if Q.dtype != torch.complex128 or Q.device.type != "cuda" or Q.shape[-1] != self.nlm:
+            raise ValueError("spectrum must be a complex128 CUDA tensor [..., %d]" % self.nlm)
+        return Q.contiguous()
+
+    def _grid_in(self, g):
+        import torch
+        if g.dtype != torch.float64 or g.device.type != "cuda" or \
+                tuple(g.shape[-2:]) != (self.nlat, self.nphi):
+            raise ValueError("grid must be a float64 CUDA tensor [..., %d, %d]" % (self.nlat, self.nphi))
+        return g.contiguous()
+
+    def _to_grid(self, fn, Q):
+        import torch
+        Q = self._spec_in(Q)
+        lead = Q.shape[:-1]
+        nf = int(np.prod(lead)) if len(lead) else 1
+        out = torch.empty(lead + (self.nlat, self.nphi), dtype=torch.float64, device=Q.device)
+        fn(self.handle, Q.data_ptr(), out.data_ptr(), nf, self.workspace(nf),
+           _stream_ptr(torch, Q.device))
+        return out
+
+    def _to_spec(self, fn, g):
+        import torch
+        g = self._grid_in(g)
+        lead = g.shape[:-2]
+        nf = int(np.prod(lead)) if len(lead) else 1
+        out = torch.empty(lead + (self.nlm,), dtype=torch.complex128, device=g.device)
+        fn(self.handle, g.data_ptr(), out.data_ptr(), nf, self.workspace(nf),
+           _stream_ptr(torch, g.device))
+        return out
+
+    def synth(self, Q):
+        """Synthesis S Q: [..., nlm] complex128 -> [..., nlat, nphi] float64."""
+        return self._to_grid(shtn_synth, Q)
+
+    def analys(self, g):
+        """Analysis A g: [..., nlat, nphi] float64 -> [..., nlm] complex128."""
+        return self._to_spec(shtn_analys, g)
+
+    def synth_adj(self, g):
+        """Adjoint of the synthesis S^T g (gradient convention dRe + i dIm)."""
+        return self._to_spec(shtn_synth_adj, g)
+
+    def analys_adj(self, h):
+        """Adjoint of the analysis A^T h."""
+        return self._to_grid(shtn_analys_adj, h)

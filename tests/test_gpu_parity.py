@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C interface) against the CPU oracle.
+
+Bar (written per test): max |gpu - oracle| / max |oracle| over each output
+array <= 1e-11 for lmax <= 255 and <= 1e-9 at lmax = 1023.  At lmax = 1023 the
+oracle is evaluated on sampled rows / orders; the round trip
+analysis(synthesis(Q)) = Q is checked in full.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_6522_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1202_6522_amd import shtn
+    shtn.load_library()
+    return torch.device("cuda:0")
+
+
+def make_plan(L, M, nlat, nphi, dev, **tiling):
+    from paper_1202_6522_amd.shtn import Plan
+    return Plan(L, M, nlat, nphi, device=dev, tiling=tiling or None)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_scalar_cases_full(case, dev):
+    p, Q = inputs.scalar_case(case)
+    L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+    plan = make_plan(L, M, nlat, nphi, dev)
+    g = plan.synth(to_dev(Q, dev)).cpu().numpy()
+    gref = oracle.synth(Q, L, M, nlat, nphi)
+    assert rel(g, gref) <= 1e-11
+    # analysis of the oracle's grid
+    R = plan.analys(to_dev(gref, dev)).cpu().numpy()
+    Rref = oracle.analys(gref, L, M, nlat, nphi)
+    assert rel(R, Rref) <= 1e-11
+    assert np.all(R[:, :L + 1].imag == 0)
+    # round trip on the GPU
+    R2 = plan.analys(plan.synth(to_dev(Q, dev))).cpu().numpy()
+    assert rel(R2, Q) <= 1e-11
+
+
+def test_lmax1023_sampled(dev):
+    p, Q = inputs.scalar_case(2)
+    L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Qd = to_dev(Q, dev)
+    g = plan.synth(Qd)
+    # sampled rows, both hemispheres, poles and equator included
+    rows = np.array([0, 1, 2, 17, 100, 255, 511, 512, 700, 1000, 1021, 1022, 1023])
+    gref = oracle.synth(Q, L, M, nlat, nphi, rows=rows)
+    gs = g.cpu().numpy()[0][rows]
+    assert rel(gs, gref[0]) <= 1e-9
+    # round trip in full, with the error by degree
+    R = plan.analys(g).cpu().numpy()[0]
+    err = np.abs(R - Q[0])
+    assert err.max() / np.abs(Q).max() <= 1e-9
+    n_all, _ = inputs.degree_order(L, M)
+    by_deg = np.zeros(L + 1)
+    np.maximum.at(by_deg, n_all, err)
+    print("lmax=1023 round trip: max err %.3e, worst degree %d (%.3e)"
+          % (err.max(), int(np.argmax(by_deg)), by_deg.max()))
+    # analysis of an independent non-band-limited grid on sampled orders
+    grid = inputs.random_grid(5, 1, nlat, nphi)[0]
+    A = plan.analys(to_dev(grid, dev)).cpu().numpy()
+    ms = [0, 1, 2, 63, 300, 511, 512, 777, 1000, 1022, 1023]
+    Aref = oracle.analys(grid, L, M, nlat, nphi, mlist=ms)
+    _, m_all = inputs.degree_order(L, M)
+    sel = np.isin(m_all, ms)
+    assert rel(A[sel], Aref[sel]) <= 1e-9
+
+
+EDGE = [
+    (0, 0, 1, 2),
+    (1, 1, 2, 4),
+    (1, 0, 3, 2),
+    (5, 3, 7, 16),
+    (12, 12, 13, 32),
+    (40, 33, 51, 128),
+    (64, 64, 65, 256),
+    (30, 30, 45, 64),
+    (100, 20, 101, 64),
+    (127, 127, 128, 256),
+]
+
+
+@pytest.mark.parametrize("shape", EDGE)
+def test_edge_shapes_all_transforms(shape, dev):
+    L, M, nlat, nphi = shape
+    rng = np.random.default_rng(sum(shape))
+    nf = 3
+    Q = inputs.draw_spectrum(rng, L, M, 1.0, nf)
+    Q[:, :L + 1] += 0.25j  # must be ignored
+    plan = make_plan(L, M, nlat, nphi, dev)
+    g = plan.synth(to_dev(Q, dev)).cpu().numpy()
+    assert rel(g, oracle.synth(Q, L, M, nlat, nphi)) <= 1e-11
+    grid = rng.standard_normal((nf, nlat, nphi))
+    A = plan.analys(to_dev(grid, dev)).cpu().numpy()
+    assert rel(A, oracle.analys(grid, L, M, nlat, nphi)) <= 1e-11
+    St = plan.synth_adj(to_dev(grid, dev)).cpu().numpy()
+    assert rel(St, oracle.synth_adj(grid, L, M, nlat, nphi)) <= 1e-11
+    At = plan.analys_adj(to_dev(Q, dev)).cpu().numpy()
+    assert rel(At, oracle.analys_adj(Q, L, M, nlat, nphi)) <= 1e-11
+
+
+@pytest.mark.parametrize("tiling", [
+    dict(synth_lp=1, analys_lp=4, fw=1, m_pairing=0),
+    dict(synth_lp=2, analys_lp=8, fw=1, m_pairing=1, split=64),
+    dict(synth_lp=4, analys_lp=4, fw=2, m_pairing=1),
+    dict(synth_lp=1, analys_lp=4, fw=2, m_pairing=0, split=32),
+    dict(synth_lp=8, analys_lp=8, fw=1, m_pairing=1, split=96),
+])
+def test_tilings_agree(tiling, dev):
+    L, M, nlat, nphi = 255, 255, 256, 512
+    rng = np.random.default_rng(3)
+    Q = inputs.draw_spectrum(rng, L, M, 1.5, 3)
+    base = make_plan(L, M, nlat, nphi, dev)
+    plan = make_plan(L, M, nlat, nphi, dev, **tiling)
+    Qd = to_dev(Q, dev)
+    g0 = base.synth(Qd).cpu().numpy()
+    g1 = plan.synth(Qd).cpu().numpy()
+    # the per-lane synthesis arithmetic does not depend on the tiling
+    np.testing.assert_array_equal(g0, g1)
+    gd = to_dev(g0, dev)
+    a0 = base.analys(gd).cpu().numpy()
+    a1 = plan.analys(gd).cpu().numpy()
+    assert rel(a1, a0) <= 1e-13
+    assert rel(a1, Q) <= 1e-11
+
+
+def test_adjoint_dot_products(dev):
+    L, M, nlat, nphi = 200, 180, 211, 512
+    rng = np.random.default_rng(12)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Q = inputs.draw_spectrum(rng, L, M, 0.5, 2)
+    h = inputs.draw_spectrum(rng, L, M, 0.5, 2)
+    g = rng.standard_normal((2, nlat, nphi))
+    f = rng.standard_normal((2, nlat, nphi))
+    SQ = plan.synth(to_dev(Q, dev)).cpu().numpy()
+    Stg = plan.synth_adj(to_dev(g, dev)).cpu().numpy()
+    lhs = np.sum(SQ * g)
+    rhs = np.sum(Q.real * Stg.real + Q.imag * Stg.imag)
+    assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(SQ * g))
+    Af = plan.analys(to_dev(f, dev)).cpu().numpy()
+    Ath = plan.analys_adj(to_dev(h, dev)).cpu().numpy()
+    lhs = np.sum(Af.real * h.real + Af.imag * h.imag)
+    rhs = np.sum(f * Ath)
+    assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(f * Ath))
+
+
+def test_paper_accuracy_protocol(dev):
+    # Sec. 3.5: coefficients uniform in [-1, 1], backward then forward
+    # transform; eps_max < 1e-11 for N < 2048.
+    for L in (255, 1023):
+        rng = np.random.default_rng(L)
+        Q = inputs.draw_spectrum(rng, L, L, 0.0, 1, dist="uniform")
+        plan = make_plan(L, L, L + 1, 2 * (L + 1), dev)
+        R = plan.analys(plan.synth(to_dev(Q, dev))).cpu().numpy()
+        eps_max = np.max(np.abs(R - Q))
+        eps_rms = np.sqrt(2.0 / ((L + 1) * (L + 2)) * np.sum(np.abs(R - Q) ** 2))
+        print("paper protocol L=%d: eps_max %.3e eps_rms %.3e" % (L, eps_max, eps_rms))
+        assert eps_max < 1e-11
+
+
+def test_deterministic_repeats(dev):
+    p, Q = inputs.scalar_case(1)
+    plan = make_plan(p["L"], p["M"], p["nlat"], p["nphi"], dev)
+    Qd = to_dev(Q, dev)
+    g0 = plan.synth(Qd)
+    a0 = plan.analys(g0)
+    for _ in range(5):
+        assert torch.equal(plan.synth(Qd), g0)
+        assert torch.equal(plan.analys(g0), a0)
+
+
+def test_nan_propagates(dev):
+    L = 31
+    plan = make_plan(L, L, 32, 64, dev)
+    Q = inputs.draw_spectrum(np.random.default_rng(0), L, L, 1.0)
+    Q[0, oracle.lm_index(L, 5, 3)] = np.nan
+    g = plan.synth(to_dev(Q, dev)).cpu().numpy()
+    assert np.isnan(g).any()
+    torch.cuda.synchronize()
+
+
+def test_bad_calls_raise(dev):
+    from paper_1202_6522_amd import shtn as S
+    plan = make_plan(31, 31, 32, 64, dev)
+    with pytest.raises(ValueError):
+        plan.synth(torch.zeros(10, dtype=torch.complex128, device=dev))
+    with pytest.raises(ValueError):
+        plan.analys(torch.zeros(32, 64, dtype=torch.float32, device=dev))
+    big = make_plan(1100, 1100, 1101, 4096, dev)
+    with pytest.raises(S.ShtnError):
+        big.analys(torch.zeros(1101, 4096, dtype=torch.float64, device=dev))

@@ -1,0 +1,407 @@
+"""Host-side tests of libshtn: exported symbols, argument validation and the
+plan tables, with a numpy emulation of the kernels' rescaled recurrence and
+underflow guard checked against the oracle.  No GPU is needed: plan
+construction is host code and no transform is called here.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_6522_amd import inputs
+from paper_1202_6522_amd import shtn as S
+
+T_XP, T_SP, T_WQ, T_BETA, T_GAMMA, T_STY, T_STK, T_SEGE, T_SEGO, T_RSTY, T_RSTK, T_AU, T_SU, T_TIL = range(14)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return S.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = S.declared_functions()
+    assert len(names) >= 25
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("args,why", [
+    ((-1, 0, 4, 8), "lmax<0"),
+    ((4, 5, 5, 16), "mmax>lmax"),
+    ((4, 4, 0, 16), "nlat<1"),
+    ((4, 4, 5, 8), "nphi<=2mmax"),
+    ((4, 4, 5, 12), "nphi not a power of two"),
+    ((0, 0, 1, 1), "nphi<2"),
+])
+def test_plan_rejects_bad_arguments(lib, args, why):
+    assert not lib.shtn_plan(*args), why
+    assert S.shtn_last_error_detail()
+
+
+def test_calls_before_upload_and_null_pointers(lib):
+    h = S.shtn_plan(8, 8, 9, 32)
+    try:
+        one = ctypes.c_void_p(16)
+        assert lib.shtn_synth(h, one, ctypes.c_void_p(32), 1, one, None) == S.SHTN_ESTATE
+        assert lib.shtn_synth(None, one, one, 1, one, None) == S.SHTN_EINVAL
+        assert lib.shtn_work_bytes(h, 0) == 0
+        assert lib.shtn_lm_index(h, 3, 4) == -1
+        assert lib.shtn_lm_index(h, 8, 8) == S.shtn_nlm(h) - 1
+        assert lib.shtn_plan_set_tiling(h, 3, 1, 1, 1, 0) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 1, 1, 1, 1, 40) == S.SHTN_EINVAL
+        assert S.shtn_strerror(S.SHTN_EUNSUPPORTED) == "unsupported configuration"
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+@pytest.mark.parametrize("nlat", [2, 7, 32, 255, 1024])
+def test_plan_grid_matches_oracle(nlat):
+    h = S.shtn_plan(nlat - 1, nlat - 1, nlat, 1 << int(np.ceil(np.log2(2 * nlat))))
+    try:
+        x, w = S.shtn_get_grid(h, nlat)
+        xo, wo = oracle.gauss(nlat, precision="ld")
+        # the plan's long-double Newton in theta and the oracle's long-double
+        # Newton in x agree to rounding
+        assert np.max(np.abs(x - xo)) <= 2.3e-16
+        assert np.max(np.abs(w / wo - 1)) < 1e-14
+        sp = S.shtn_plan_table(h, T_SP)
+        npair = (nlat + 1) // 2
+        xs = x[:npair]
+        tol = 1.2e-16 / (1 - np.abs(xs)) + 1e-15  # sin from rounded x vs the exact node
+        assert np.all(np.abs(sp / np.sqrt((1 - xs) * (1 + xs)) - 1) < tol)
+        assert abs(S.shtn_legendre_flops(h) - 8 * npair * S.shtn_nlm(h)) == 0
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def _tables(h):
+    return {k: S.shtn_plan_table(h, k) for k in range(14)}
+
+
+def test_beta_gamma_tables():
+    L, M = 70, 60
+    h = S.shtn_plan(L, M, L + 1, 256)
+    try:
+        t = _tables(h)
+        n_all, m_all = inputs.degree_order(L, M)
+        j = n_all - m_all
+        beta = t[T_BETA]
+        assert np.all(beta[j == 0] == 1) and np.all(beta[j == 1] == 0)
+        sel = j >= 2
+        n, m = n_all[sel], m_all[sel]
+        ref = -((n - 1.0) ** 2 - m**2) / ((2 * n - 1.0) * (2 * n - 3.0))
+        np.testing.assert_allclose(beta[sel], ref, rtol=2e-16)
+        # gamma_n = alpha_n 2^{-E}: gamma_n / gamma_{n-1} = a_n^m within a segment
+        g = t[T_GAMMA]
+        a = np.sqrt(np.abs(4.0 * n_all**2 - 1) / np.maximum(n_all**2 - m_all**2, 1))
+        inseg = (j >= 1) & (j % 32 != 0)
+        idx = np.nonzero(inseg)[0]
+        np.testing.assert_allclose(g[idx] / g[idx - 1], a[idx], rtol=1e-15)
+        assert np.all(g[j == 0] == 1)
+        assert np.all(g >= 1) and np.max(g) < 2.0**200
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def test_start_values_scaled_exponents():
+    # P_m^m(x) = w 2^{-256 k}: compare with log2 of the closed form
+    L, nlat = 2047, 2048
+    h = S.shtn_plan(L, L, nlat, 4096)
+    try:
+        t = _tables(h)
+        npair = nlat // 2
+        sy = t[T_STY].reshape(L + 1, npair)
+        sk = t[T_STK].reshape(L + 1, npair)
+        sp = t[T_SP]
+        m = np.arange(L + 1)[:, None]
+        logamm = 0.5 * (np.concatenate([[0.0], np.cumsum(np.log2((2 * np.arange(1, L + 1) + 1) /
+                                                                (2.0 * np.arange(1, L + 1))))])
+                        - np.log2(4 * np.pi))
+        ref = logamm[:, None] + m * np.log2(sp)[None, :]
+        got = np.log2(np.abs(sy)) - 256.0 * sk
+        assert np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))) < 1e-12
+        assert np.all(np.sign(sy) == (-1.0) ** m)
+        pos = sk > 0
+        assert np.all(np.abs(sy[pos]) < 1) and np.all(np.abs(sy[pos]) >= 2.0**-256)
+        assert np.all(np.abs(sy[~pos]) >= 2.0**-256)
+        # small-m values are plain doubles that match the oracle
+        # (the oracle takes sin(theta) from its rounded x, which near the pole
+        # carries ~1e-16/(1-x) relative error per power of sin)
+        x = S.shtn_plan_table(h, T_XP)[:8]
+        P = oracle.plm(4, 4, x)
+        for mm in range(5):
+            tol = mm * 1.2e-16 / (1 - x) + 1e-14
+            assert np.all(np.abs(sy[mm, :8] / P[oracle.lm_index(4, mm, mm)] - 1) < tol)
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def emulate_legendre(t, L, M, nlat, Q=None, F=None, adjoint=False, track=None):
+    """numpy emulation of the kernels' per-lane algorithm: rescaled recurrence,
+    segment rescaling, underflow guard with zero contribution while k > 0,
+    mirror fold.  Synthesis if Q is given (returns F[m][lat]), analysis if F is
+    given (returns Q).  Vectorised over latitude pairs."""
+    npair = (nlat + 1) // 2
+    xp, wq, beta, gamma = t[T_XP], t[T_WQ], t[T_BETA], t[T_GAMMA]
+    sy = t[T_STY].reshape(M + 1, npair)
+    sk = t[T_STK].reshape(M + 1, npair)
+    sege, sego = t[T_SEGE], t[T_SEGO]
+    nlm = len(beta)
+    out = np.zeros((M + 1, nlat), complex) if Q is not None else np.zeros(nlm, complex)
+    pairs = np.arange(npair)
+    south = nlat - 1 - pairs
+    for m in range(M + 1):
+        base = oracle.lm_index(L, m, m)
+        nj = L - m + 1
+        ua = sy[m].copy()
+        ub = np.zeros(npair)
+        k = sk[m].copy()
+        if Q is not None:
+            qs = gamma[base:base + nj] * Q[base:base + nj]
+            E = np.zeros(npair, complex)
+            O = np.zeros(npair, complex)
+        else:
+            fe = wq * (F[m, pairs] + F[m, south])
+            fo = wq * (F[m, pairs] - F[m, south])
+        for j in range(0, nj, 2):
+            if j > 0 and j % 32 == 0:
+                sc = 2.0 ** sege[sego[m] + j // 32]
+                ua *= sc
+                ub *= sc
+            if j % 4 == 0:
+                msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
+                ua[msk] *= 2.0**-256
+                ub[msk] *= 2.0**-256
+                k[msk] -= 1
+            ua = xp * ub + beta[base + j] * ua
+            va = np.where(k == 0, ua, 0.0)
+            if track is not None:
+                track.append(np.abs(ua[k == 0]))
+            if Q is not None:
+                E += qs[j] * va
+            else:
+                out[base + j] = gamma[base + j] * np.sum(fe * va)
+            if j + 1 < nj:
+                ub = xp * ua + beta[base + j + 1] * ub
+                vb = np.where(k == 0, ub, 0.0)
+                if Q is not None:
+                    O += qs[j + 1] * vb
+                else:
+                    out[base + j + 1] = gamma[base + j + 1] * np.sum(fo * vb)
+        if Q is not None:
+            out[m, pairs] = E + O
+            out[m, south] = E - O
+        elif m == 0:
+            out[base:base + nj] = out[base:base + nj].real
+    return out
+
+
+@pytest.mark.parametrize("L,M,nlat", [(40, 40, 41), (63, 50, 70), (30, 30, 33)])
+def test_emulated_recurrence_matches_oracle(L, M, nlat):
+    h = S.shtn_plan(L, M, nlat, 256)
+    try:
+        t = _tables(h)
+        x, w = S.shtn_get_grid(h, nlat)
+        rng = np.random.default_rng(L + M)
+        Q = inputs.draw_spectrum(rng, L, M, 1.0)[0]
+        F = emulate_legendre(t, L, M, nlat, Q=Q)
+        P = oracle.plm(L, M, x)
+        n_all, m_all = inputs.degree_order(L, M)
+        ref = np.zeros((M + 1, nlat), complex)
+        np.add.at(ref, m_all, Q[:, None] * P)
+        assert np.max(np.abs(F - ref)) < 1e-13 * np.max(np.abs(ref))
+        # analysis: Q_n^m = sum_i w_i P_n^m(x_i) F_m(theta_i)
+        G = rng.standard_normal((M + 1, nlat)) + 1j * rng.standard_normal((M + 1, nlat))
+        got = emulate_legendre(t, L, M, nlat, F=G)
+        refq = np.sum(P * w[None, :] * G[m_all], axis=1)
+        refq[m_all == 0] = refq[m_all == 0].real
+        assert np.max(np.abs(got - refq)) < 1e-13 * np.max(np.abs(refq))
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def test_emulated_guard_at_high_degree():
+    # At L = 2047 some starts underflow double precision although the
+    # functions later reach significant values: the guard must recover them.
+    # Reference: the long-double oracle restricted to a few orders.
+    L, nlat, nphi = 2047, 2048, 4096
+    h = S.shtn_plan(L, L, nlat, nphi)
+    try:
+        t = _tables(h)
+        x, _ = S.shtn_get_grid(h, nlat)
+        ms = [900, 1100, 1500]
+        Mx = max(ms)
+        # emulate only the listed orders: zero spectrum elsewhere
+        rng = np.random.default_rng(1)
+        Q = np.zeros(S.shtn_nlm(h), complex)
+        n_all, m_all = inputs.degree_order(L, L)
+        sel = np.isin(m_all, ms)
+        Q[sel] = (rng.standard_normal(sel.sum()) + 1j * rng.standard_normal(sel.sum()))
+        t2 = dict(t)
+        F = _emulate_orders(t2, L, L, nlat, Q, ms)
+        rows = np.arange(0, nlat // 2, 7)
+        gref = oracle.synth(Q, L, L, nlat, nphi, mlist=ms, rows=rows, precision="ld")
+        phi = 2 * np.pi * np.arange(nphi) / nphi
+        g = np.zeros((rows.size, nphi))
+        for m in ms:
+            g += 2 * np.real(F[m][rows][:, None] * np.exp(1j * m * phi)[None, :])
+        assert np.max(np.abs(g - gref)) < 1e-11 * np.max(np.abs(gref))
+        # and double precision without rescaling loses the rows whose starts underflow
+        sk = t[T_STK].reshape(L + 1, nlat // 2)
+        assert np.any(sk[ms][:, rows] > 0)
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def _emulate_orders(t, L, M, nlat, Q, ms):
+    """emulate_legendre restricted to a few orders (returns {m: F_m[lat]})."""
+    npair = (nlat + 1) // 2
+    xp, beta, gamma = t[T_XP], t[T_BETA], t[T_GAMMA]
+    sy = t[T_STY].reshape(M + 1, npair)
+    sk = t[T_STK].reshape(M + 1, npair)
+    sege, sego = t[T_SEGE], t[T_SEGO]
+    pairs = np.arange(npair)
+    out = {}
+    for m in ms:
+        base = oracle.lm_index(L, m, m)
+        nj = L - m + 1
+        ua, ub, k = sy[m].copy(), np.zeros(npair), sk[m].copy()
+        qs = gamma[base:base + nj] * Q[base:base + nj]
+        E = np.zeros(npair, complex)
+        O = np.zeros(npair, complex)
+        for j in range(0, nj, 2):
+            if j > 0 and j % 32 == 0:
+                sc = 2.0 ** sege[sego[m] + j // 32]
+                ua *= sc
+                ub *= sc
+            if j % 4 == 0:
+                msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
+                ua[msk] *= 2.0**-256
+                ub[msk] *= 2.0**-256
+                k[msk] -= 1
+            ua = xp * ub + beta[base + j] * ua
+            E += qs[j] * np.where(k == 0, ua, 0.0)
+            if j + 1 < nj:
+                ub = xp * ua + beta[base + j + 1] * ub
+                O += qs[j + 1] * np.where(k == 0, ub, 0.0)
+        F = np.zeros(nlat, complex)
+        F[pairs] = E + O
+        F[nlat - 1 - pairs] = E - O
+        out[m] = F
+    return out
+
+
+def test_emulated_values_stay_in_range():
+    # with k = 0 the carried values never approach under- or overflow
+    L = 1023
+    h = S.shtn_plan(L, L, L + 1, 2048)
+    try:
+        t = _tables(h)
+        npair = (L + 2) // 2
+        sub = {}
+        for key in (T_XP, T_WQ):
+            sub[key] = t[key]
+        track = []
+        ms = [0, 1, 300, 700, 1000, 1023]
+        Q = np.ones(S.shtn_nlm(h), complex)
+        _ = _emulate_orders(t, L, L, L + 1, Q, ms)
+        # range check directly on the recurrence of the extreme orders
+        for m in ms:
+            base = oracle.lm_index(L, m, m)
+            sy = t[T_STY].reshape(L + 1, npair)[m]
+            sk = t[T_STK].reshape(L + 1, npair)[m]
+            ua, ub, k = sy.copy(), np.zeros(npair), sk.copy()
+            lo, hi = np.inf, 0.0
+            for j in range(0, L - m + 1):
+                if j % 2 == 0:
+                    if j > 0 and j % 32 == 0:
+                        sc = 2.0 ** t[T_SEGE][t[T_SEGO][m] + j // 32]
+                        ua *= sc
+                        ub *= sc
+                    if j % 4 == 0:
+                        msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
+                        ua[msk] *= 2.0**-256
+                        ub[msk] *= 2.0**-256
+                        k[msk] -= 1
+                    ua = t[T_XP] * ub + t[T_BETA][base + j] * ua
+                    v = np.abs(ua[(k == 0) & (ua != 0)])
+                else:
+                    ub = t[T_XP] * ua + t[T_BETA][base + j] * ub
+                    v = np.abs(ub[(k == 0) & (ub != 0)])
+                if v.size:
+                    lo, hi = min(lo, v.min()), max(hi, v.max())
+            assert hi < 1e3, (m, hi)
+            assert lo > 2.0**-900, (m, lo)
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def test_restart_states_match_recurrence():
+    L = 255
+    h = S.shtn_plan(L, L, 256, 512)
+    try:
+        t = _tables(h)
+        til = t[T_TIL]
+        split = int(til[4])
+        au = t[T_AU].reshape(-1, 8)
+        npair = 128
+        # every order's degree range is covered exactly once
+        cover = {}
+        for u in au:
+            m, j0, j1, r = u[3], u[5], u[6], u[7]
+            cover.setdefault(int(m), []).append((int(j0), int(j1)))
+            assert (r < 0) == (j0 == 0)
+            assert j0 % split == 0
+        for m in range(L + 1):
+            segs = sorted(cover[m])
+            assert segs[0][0] == 0 and segs[-1][1] == L - m + 1
+            assert all(a[1] == b[0] for a, b in zip(segs, segs[1:]))
+        lens = au[:, 6] - au[:, 5]
+        assert np.all(np.diff(lens) <= 0), "units are ordered longest first"
+        # a restart state equals the recurrence run from the start value
+        ry = t[T_RSTY].reshape(-1, npair, 2)
+        rk = t[T_RSTK].reshape(-1, npair)
+        u = au[(au[:, 7] >= 0)][0]
+        m, j0, r = int(u[3]), int(u[5]), int(u[7])
+        base = oracle.lm_index(L, m, m)
+        sy = t[T_STY].reshape(L + 1, npair)[m]
+        sk = t[T_STK].reshape(L + 1, npair)[m]
+        ua, ub, k = sy.copy(), np.zeros(npair), sk.copy()
+        for j in range(0, j0, 2):
+            if j > 0 and j % 32 == 0:
+                sc = 2.0 ** t[T_SEGE][t[T_SEGO][m] + j // 32]
+                ua *= sc
+                ub *= sc
+            if j % 4 == 0:
+                msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
+                ua[msk] *= 2.0**-256
+                ub[msk] *= 2.0**-256
+                k[msk] -= 1
+            ua = t[T_XP] * ub + t[T_BETA][base + j] * ua
+            ub = t[T_XP] * ua + t[T_BETA][base + j + 1] * ub
+        # (numpy rounds the products separately; the host uses fused multiply-adds)
+        np.testing.assert_allclose(ry[r, :, 0], ua, rtol=0, atol=1e-13 * np.max(np.abs(ua)))
+        np.testing.assert_allclose(ry[r, :, 1], ub, rtol=0, atol=1e-13 * np.max(np.abs(ub)))
+        np.testing.assert_array_equal(rk[r], k)
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def test_synthesis_units_cover_all_work():
+    for (L, M, nlat, pairing) in [(31, 31, 32, 1), (40, 33, 51, 1), (40, 33, 51, 0)]:
+        h = S.shtn_plan(L, M, nlat, 128)
+        try:
+            S.shtn_plan_set_tiling(h, 1, 1, 1, pairing, 0)
+            su = S.shtn_plan_table(h, T_SU).reshape(-1, 8)
+            npair = (nlat + 1) // 2
+            seen = np.zeros((M + 1, npair), int)
+            for u in su:
+                for mm in (u[3], u[4]):
+                    if mm >= 0:
+                        pb = u[5]
+                        seen[mm, pb:min(pb + 64, npair)] += 1
+            assert np.all(seen == 1)
+        finally:
+            S.shtn_plan_destroy(h)
