@@ -118,20 +118,23 @@ double shtn_legendre_flops(shtn_plan_t plan);
  * 5 start mantissa ((mmax+1) x npair), 6 start exponent (int32, same shape),
  * 7 segment exponent shifts (int32), 8 segment offsets per m (int32, mmax+2),
  * 9 restart states (double, nrestart x npair x 2), 10 restart exponents
- * (int32, nrestart x npair), 11 analysis units (int32 x 4 each),
- * 12 synthesis units (int32 x 4 each), 13 tiling (int32 x 8).
+ * (int32, nrestart x npair), 11 analysis units (int32 x 8 each),
+ * 12 synthesis units (int32 x 8 each), 13 tiling (int32 x 8: synth_lp,
+ * analys_lp, fw, m_pairing, split, fft_rows, segment length, guard unit),
+ * 14 first latitude pair kept by the static polar cut, per m (int32).
  * Returns the table size in bytes; copies only if dst != NULL and
  * bytes >= size.  Negative on error. */
 long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
 
 /* Tiling of the Legendre kernels (the runtime-tuning knob of Sec. 3.2):
- * synth_lp / analys_lp latitude pairs per lane (1, 2, 4, 8), fields per
+ * synth_lp (1, 2, 4) / analys_lp (1, 2, 4, 8) latitude pairs per lane, fields per
  * wave fw (1, 2; fw = 2 needs lp <= 4), m_pairing (0/1: one wave takes orders m and mmax-m),
- * split (analysis n-range piece length, a multiple of 32; 0 = automatic).
- * Changing the split rebuilds the restart tables: re-upload afterwards.
+ * split (analysis n-range piece length, a multiple of 32; 0 = automatic),
+ * fft_rows (latitude rows per FFT workgroup, 0 = automatic).
+ * Rebuilds the unit lists and restart tables: re-upload afterwards.
  * Returns SHTN_EINVAL for unsupported values. */
 int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
-                         int split);
+                         int split, int fft_rows);
 
 /* ---- batches of fields with different truncations (one launch per stage) ---- */
 typedef struct shtn_batch_s* shtn_batch_t;

@@ -2,6 +2,7 @@
 // the launch sequences of the four transforms.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -39,10 +40,19 @@ const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.de
 
 int rows_per_block(const Plan& p)
 {
-    int r = 4096 / p.K;
-    if (r < 1) r = 1;
+    const int cap = std::max(1, 4096 / p.K);  // 64 KB of LDS per workgroup
+    int r = p.tiling.fft_rows > 0 ? p.tiling.fft_rows : cap;
+    if (r > cap) r = cap;
     if (r > p.nlat) r = p.nlat;
     return r;
+}
+
+// Latitude blocks of the same orders share a workgroup (and its scalar cache).
+int synth_wpg(const Plan& p)
+{
+    const int blk = 64 * p.tiling.synth_lp;
+    const int nblk = (p.npair + blk - 1) / blk;
+    return nblk <= 8 ? nblk : 1;
 }
 
 int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, const void* work)
@@ -82,6 +92,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     l.adjoint = adjoint;
     l.lp = p.tiling.synth_lp;
     l.fw = p.tiling.fw;
+    l.wpg = synth_wpg(p);
     {
         ProfScope ps(PK_LEG_SYNTH, stream);
         e = launch_legendre_synth(l, stream);
@@ -315,7 +326,7 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     const void* src = nullptr;
     size_t n = 0;
     int tiling[8] = {p.tiling.synth_lp, p.tiling.analys_lp, p.tiling.fw, p.tiling.m_pairing,
-                     p.split_used, kSegLen, kGuardUnit, kChunk};
+                     p.split_used, rows_per_block(p), kSegLen, kGuardUnit};
     switch (which) {
     case 0: src = p.xp.data(); n = p.xp.size() * 8; break;
     case 1: src = p.sp.data(); n = p.sp.size() * 8; break;
@@ -331,6 +342,7 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     case 11: src = p.analys_units.data(); n = p.analys_units.size() * 4; break;
     case 12: src = p.synth_units.data(); n = p.synth_units.size() * 4; break;
     case 13: src = tiling; n = sizeof(tiling); break;
+    case 14: src = p.first_pair.data(); n = p.first_pair.size() * 4; break;
     default: return fail(SHTN_EINVAL, "unknown table");
     }
     if (dst && bytes >= n && n) std::memcpy(dst, src, n);
@@ -338,24 +350,27 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
 }
 
 int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
-                         int split)
+                         int split, int fft_rows)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
     Plan& p = *plan->p;
     auto okl = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
     if (!okl(synth_lp) || !okl(analys_lp)) return fail(SHTN_EINVAL, "lp must be 1, 2, 4 or 8");
+    if (synth_lp > 4) return fail(SHTN_EINVAL, "synth_lp must be 1, 2 or 4");
     if (!(fw == 1 || fw == 2)) return fail(SHTN_EINVAL, "fw must be 1 or 2");
     if (fw == 2 && synth_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs synth_lp <= 4");
     if (fw == 2 && analys_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs analys_lp <= 4");
     if (64 * analys_lp < p.npair && p.npair <= kMaxAnalysPairs)
         return fail(SHTN_EINVAL, "analys_lp too small: one analysis wave must cover all latitude pairs");
     if (split < 0 || split % kSegLen) return fail(SHTN_EINVAL, "split must be a multiple of 32");
+    if (fft_rows < 0) return fail(SHTN_EINVAL, "fft_rows must be >= 0");
     Tiling old = p.tiling;
     p.tiling.synth_lp = synth_lp;
     p.tiling.analys_lp = analys_lp;
     p.tiling.fw = fw;
     p.tiling.m_pairing = m_pairing ? 1 : 0;
     p.tiling.split = split;
+    p.tiling.fft_rows = fft_rows;
     std::string err;
     if (rebuild_units(p, err)) {
         p.tiling = old;

@@ -11,7 +11,9 @@
 // FMA), with P_n^m = gamma_n u_n; gamma is folded into the spectrum before the
 // synthesis and applied after the reduction in the analysis.  Recurrence
 // coefficients and spectra are wave-uniform and are read with scalar loads
-// into SGPRs, so every lane's FMAs take them as operands for free.
+// into SGPRs, in blocks of several degrees, so every lane's FMAs take them as
+// operands for free.  The tables are padded past their last entry so a block
+// load at the end of an order stays in bounds.
 //
 // One work unit = one wave of 64 lanes, LP latitude pairs per lane and FW
 // fields that share the plan.
@@ -35,6 +37,8 @@ struct LegArgs {
     double* out;
     int nfields;
     int adjoint;
+    int nunits;
+    int wpg;  // waves (units) per workgroup
 };
 
 __device__ __forceinline__ long field_q_off(const LegArgs& a, int f, long nlm)
@@ -70,6 +74,23 @@ k_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int
     }
 }
 
+// Per-lane vector loads that warm L2 ahead of the scalar loads (synthesis).
+constexpr int kPrefetchSlots = 2;
+
+// Blocks of scalar operands.
+struct D4 {
+    double v[4];
+};
+struct D8 {
+    double v[8];
+};
+struct D16 {
+    double v[16];
+};
+typedef const __attribute__((address_space(4))) D4* cd4p;
+typedef const __attribute__((address_space(4))) D8* cd8p;
+typedef const __attribute__((address_space(4))) D16* cd16p;
+
 // ---------------------------------------------------------------------------
 // Synthesis: F_m(theta) for one order, LP pairs per lane, FW fields.
 // ---------------------------------------------------------------------------
@@ -77,104 +98,121 @@ template <int LP, int FW>
 struct SynthState {
     double x[LP], ua[LP], ub[LP];
     int k[LP];
+    double z[LP];  // 1 while the lane's value is live (k == 0), 0 while scaled
     double er[LP][FW], ei[LP][FW], orr[LP][FW], oi[LP][FW];
 };
 
-// One even step (degree n = m + j) and one odd step (n + 1), unmasked.
-template <int LP, int FW>
-__device__ __forceinline__ void synth_pair_step(SynthState<LP, FW>& s, double b0, double b1,
-                                                const double (&q0)[FW][2],
-                                                const double (&q1)[FW][2], bool odd)
+// beta and the rescaled spectrum (re, im per field) for four degrees
+template <int FW>
+struct SBlock {
+    D4 b;
+    D8 q[FW];
+};
+
+template <int FW>
+__device__ __forceinline__ void load_block(SBlock<FW>& B, cdp bet, const cdp (&qs)[FW], int j)
 {
+    cd4p pb = (cd4p)(bet + j);
 #pragma unroll
-    for (int p = 0; p < LP; p++) s.ua[p] = fma(s.x[p], s.ub[p], b0 * s.ua[p]);
+    for (int i = 0; i < 4; i++) B.b.v[i] = pb->v[i];
 #pragma unroll
-    for (int p = 0; p < LP; p++)
+    for (int f = 0; f < FW; f++) {
+        cd8p pq = (cd8p)(qs[f] + 2 * j);
 #pragma unroll
-        for (int f = 0; f < FW; f++) {
-            s.er[p][f] = fma(q0[f][0], s.ua[p], s.er[p][f]);
-            s.ei[p][f] = fma(q0[f][1], s.ua[p], s.ei[p][f]);
-        }
-    if (odd) {
-#pragma unroll
-        for (int p = 0; p < LP; p++) s.ub[p] = fma(s.x[p], s.ua[p], b1 * s.ub[p]);
-#pragma unroll
-        for (int p = 0; p < LP; p++)
-#pragma unroll
-            for (int f = 0; f < FW; f++) {
-                s.orr[p][f] = fma(q1[f][0], s.ub[p], s.orr[p][f]);
-                s.oi[p][f] = fma(q1[f][1], s.ub[p], s.oi[p][f]);
-            }
+        for (int i = 0; i < 8; i++) B.q[f].v[i] = pq->v[i];
     }
 }
 
-// Same, with lanes whose guard exponent k > 0 contributing zero.
-template <int LP, int FW>
-__device__ __forceinline__ void synth_pair_step_masked(SynthState<LP, FW>& s, double b0,
-                                                       double b1, const double (&q0)[FW][2],
-                                                       const double (&q1)[FW][2], bool odd)
+// Step t of a block (degree offset j + t).  Even t advance ua and feed the
+// even (E) sums, odd t advance ub and feed the odd (O) sums.  MASKED
+// multiplies the value by the lane's live flag z.
+template <bool MASKED, int LP, int FW>
+__device__ __forceinline__ void synth_step(SynthState<LP, FW>& s, const SBlock<FW>& B, int t)
 {
+    const double b = B.b.v[t];
+    if ((t & 1) == 0) {
 #pragma unroll
-    for (int p = 0; p < LP; p++) s.ua[p] = fma(s.x[p], s.ub[p], b0 * s.ua[p]);
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        const double v = s.k[p] ? 0.0 : s.ua[p];
-#pragma unroll
-        for (int f = 0; f < FW; f++) {
-            s.er[p][f] = fma(q0[f][0], v, s.er[p][f]);
-            s.ei[p][f] = fma(q0[f][1], v, s.ei[p][f]);
-        }
-    }
-    if (odd) {
-#pragma unroll
-        for (int p = 0; p < LP; p++) s.ub[p] = fma(s.x[p], s.ua[p], b1 * s.ub[p]);
+        for (int p = 0; p < LP; p++) s.ua[p] = fma(s.x[p], s.ub[p], b * s.ua[p]);
 #pragma unroll
         for (int p = 0; p < LP; p++) {
-            const double v = s.k[p] ? 0.0 : s.ub[p];
+            const double v = MASKED ? s.ua[p] * s.z[p] : s.ua[p];
 #pragma unroll
             for (int f = 0; f < FW; f++) {
-                s.orr[p][f] = fma(q1[f][0], v, s.orr[p][f]);
-                s.oi[p][f] = fma(q1[f][1], v, s.oi[p][f]);
+                s.er[p][f] = fma(B.q[f].v[2 * t], v, s.er[p][f]);
+                s.ei[p][f] = fma(B.q[f].v[2 * t + 1], v, s.ei[p][f]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < LP; p++) s.ub[p] = fma(s.x[p], s.ua[p], b * s.ub[p]);
+#pragma unroll
+        for (int p = 0; p < LP; p++) {
+            const double v = MASKED ? s.ub[p] * s.z[p] : s.ub[p];
+#pragma unroll
+            for (int f = 0; f < FW; f++) {
+                s.orr[p][f] = fma(B.q[f].v[2 * t], v, s.orr[p][f]);
+                s.oi[p][f] = fma(B.q[f].v[2 * t + 1], v, s.oi[p][f]);
             }
         }
     }
 }
 
+// Four steps; `lim` = number of valid steps (4 for a full block).
+template <bool MASKED, int LP, int FW>
+__device__ __forceinline__ void synth_block4(SynthState<LP, FW>& s, const SBlock<FW>& B, int lim)
+{
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+        if (t < lim) synth_step<MASKED>(s, B, t);
+}
+
+// Guard check (every kGuardEvery degrees): a scaled lane whose value reached
+// 1 is brought down by 2^-256 and its exponent decremented; z follows k.
 template <int LP, int FW>
-__device__ __forceinline__ void guard_check(SynthState<LP, FW>& s)
+__device__ __forceinline__ bool guard_check(SynthState<LP, FW>& s)
 {
     const double down = 0x1p-256;
+    bool any = false;
 #pragma unroll
     for (int p = 0; p < LP; p++) {
-        const bool big = fabs(s.ua[p]) >= 1.0 || fabs(s.ub[p]) >= 1.0;
-        if (s.k[p] > 0 && big) {
+        if (s.k[p] > 0 && (fabs(s.ua[p]) >= 1.0 || fabs(s.ub[p]) >= 1.0)) {
             s.ua[p] *= down;
             s.ub[p] *= down;
             s.k[p] -= 1;
+            s.z[p] = s.k[p] ? 0.0 : 1.0;
         }
+        any |= s.k[p] > 0;
     }
-}
-
-template <int LP, int FW>
-__device__ __forceinline__ bool any_scaled(const SynthState<LP, FW>& s)
-{
-    bool any = false;
-#pragma unroll
-    for (int p = 0; p < LP; p++) any |= s.k[p] > 0;
     return wave_any(any);
 }
 
 template <int LP, int FW>
-__global__ void __launch_bounds__(64) k_legendre_synth(LegArgs a)
+__device__ __forceinline__ void rescale(SynthState<LP, FW>& s, int sh)
 {
-    cip U = (cip)a.units + (size_t)blockIdx.x * kUnitInts;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        s.ua[p] = __builtin_amdgcn_ldexp(s.ua[p], sh);
+        s.ub[p] = __builtin_amdgcn_ldexp(s.ub[p], sh);
+    }
+}
+
+// One wave per unit; a workgroup holds `wpg` consecutive units (the latitude
+// blocks of the same orders), which then share scalar-cache lines.
+template <int LP, int FW>
+__global__ void __launch_bounds__(512) k_legendre_synth(LegArgs a)
+{
+    // wave-uniform for the compiler, so unit data and coefficients stay in SGPRs
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int unit = blockIdx.x * a.wpg + wave;
+    if (unit >= a.nunits) return;
+    cip U = (cip)a.units + (size_t)unit * kUnitInts;
     const int field0 = U[U_FIELD] + blockIdx.y * FW;
     if (field0 >= a.nfields) return;
     const int nf = min(U[U_NF], a.nfields - field0);
     cplan P = (cplan)a.plans + U[U_PLAN];
     const int L = P->L, M = P->M, nlat = P->nlat, npair = P->npair;
     const long nlm = P->nlm;
-    const int lane = threadIdx.x;
     const int pb = U[U_PB];
 
     long qoff[FW];
@@ -185,10 +223,28 @@ __global__ void __launch_bounds__(64) k_legendre_synth(LegArgs a)
         qoff[f] = field_q_off(a, ff, nlm);
         foff[f] = field_f_off(a, ff, M, nlat);
     }
+    unsigned sink = 0;  // prefetched words; consumed once at the end
 
     for (int pass = 0; pass < 2; pass++) {
         const int m = pass == 0 ? U[U_M0] : U[U_M1];
         if (m < 0) break;
+        if ((U[U_RST] >> pass) & 1) {
+            // block entirely inside the polar cut of this order: F_m = 0 there
+#pragma unroll
+            for (int p = 0; p < LP; p++) {
+                const int pair = pb + p * 64 + lane;
+                if (pair >= npair) continue;
+                const int is = nlat - 1 - pair;
+#pragma unroll
+                for (int f = 0; f < FW; f++) {
+                    if (f >= nf) continue;
+                    double* F = a.out + foff[f] + 2 * ((size_t)m * nlat);
+                    *(double2*)(F + 2 * pair) = make_double2(0.0, 0.0);
+                    *(double2*)(F + 2 * is) = make_double2(0.0, 0.0);
+                }
+            }
+            continue;
+        }
         const long base = (long)m * (2 * L + 1 - m) / 2 + m;
         const int nj = L - m + 1;
         cdp bet = (cdp)P->beta + base;
@@ -198,6 +254,7 @@ __global__ void __launch_bounds__(64) k_legendre_synth(LegArgs a)
         cip segexp = (cip)P->segexp + ((cip)P->segoff)[m];
 
         SynthState<LP, FW> s;
+        bool any = false;
 #pragma unroll
         for (int p = 0; p < LP; p++) {
             const int pair = pb + p * 64 + lane;
@@ -207,80 +264,107 @@ __global__ void __launch_bounds__(64) k_legendre_synth(LegArgs a)
             s.ua[p] = act ? P->start_y[(size_t)m * npair + pc] : 0.0;
             s.ub[p] = 0.0;
             s.k[p] = act ? P->start_k[(size_t)m * npair + pc] : 0;
+            s.z[p] = s.k[p] ? 0.0 : 1.0;
+            any |= s.k[p] > 0;
 #pragma unroll
             for (int f = 0; f < FW; f++) s.er[p][f] = s.ei[p][f] = s.orr[p][f] = s.oi[p][f] = 0.0;
         }
-        bool guard = any_scaled(s);
+        bool guard = wave_any(any);
 
+        // Warm L2 with this order's beta and spectrum: the workgroup's lanes
+        // touch one word per 64-byte line with vector loads into registers
+        // that are consumed only after the order is done.  They are issued
+        // after the start values above have arrived and no other vector load
+        // follows before the end, so no wave waits on them (the scalar loads
+        // are counted apart).  The scalar loads of the segments then find
+        // these lines in L2.
+        __builtin_amdgcn_sched_barrier(0);
+        unsigned pf[kPrefetchSlots];
+        {
+            const int nthr = a.wpg * 64;
+            const int gi = wave * 64 + lane;
+            const int lb = (nj * 8 + 63) / 64;   // beta lines
+            const int lq = (nj * 16 + 63) / 64;  // spectrum lines per field
+            const char* pb = (const char*)(P->beta + base);
+#pragma unroll
+            for (int k = 0; k < kPrefetchSlots; k++) {
+                int li = gi + k * nthr;
+                const char* addr = pb;
+                if (li < lb) {
+                    addr = pb + li * 64;
+                } else {
+                    li -= lb;
+#pragma unroll
+                    for (int f = 0; f < FW; f++) {
+                        if (li >= 0 && li < lq) addr = (const char*)(a.in + qoff[f] + 2 * base) + li * 64;
+                        li -= lq;
+                    }
+                }
+                pf[k] = *(const unsigned*)addr;
+            }
+        }
+
+        // One segment (kSegLen degrees) per iteration.  The segment rescale is
+        // applied unconditionally (segment 0 has shift 0): a branch here is
+        // if-converted by the compiler into selects on every block.
         for (int js = 0; js < nj; js += kSegLen) {
             const int je = min(js + kSegLen, nj);
-            if (js > 0) {
-                const double sc = __builtin_amdgcn_ldexp(1.0, segexp[js / kSegLen]);
-#pragma unroll
-                for (int p = 0; p < LP; p++) {
-                    s.ua[p] *= sc;
-                    s.ub[p] *= sc;
-                }
-            }
+            rescale(s, segexp[js / kSegLen]);
             if (guard) {
-                for (int j = js; j < je; j += 2) {
-                    if ((j & (kGuardEvery - 1)) == 0) guard_check(s);
-                    double q0[FW][2], q1[FW][2];
-                    const bool odd = j + 1 < je;
-                    const int jn = odd ? j + 1 : j;  // never index past the order's last degree
-#pragma unroll
-                    for (int f = 0; f < FW; f++) {
-                        q0[f][0] = qs[f][2 * j];
-                        q0[f][1] = qs[f][2 * j + 1];
-                        q1[f][0] = qs[f][2 * jn];
-                        q1[f][1] = qs[f][2 * jn + 1];
-                    }
-                    synth_pair_step_masked(s, bet[j], bet[jn], q0, q1, odd);
-                }
-                guard = any_scaled(s);
-            } else if (je - js == kSegLen) {
-#pragma unroll 4
+                // some lanes still carry scaled (negligible) values: they are
+                // masked out of the sums (Sec. 3.5 dynamic polar skip)
+                // (full blocks take a compile-time step count: a runtime
+                // bound is if-converted into selects on every state register)
                 for (int j = js; j < je; j += 8) {
-                    double b[8];
-                    double q[FW][8][2];
-#pragma unroll
-                    for (int t = 0; t < 8; t++) {
-                        b[t] = bet[j + t];
-#pragma unroll
-                        for (int f = 0; f < FW; f++) {
-                            q[f][t][0] = qs[f][2 * (j + t)];
-                            q[f][t][1] = qs[f][2 * (j + t) + 1];
+                    SBlock<FW> b0, b1;
+                    load_block(b0, bet, qs, j);
+                    load_block(b1, bet, qs, j + 4);
+                    guard = guard_check(s);
+                    if (j + 8 <= je) {
+                        synth_block4<true>(s, b0, 4);
+                        guard = guard_check(s);
+                        synth_block4<true>(s, b1, 4);
+                    } else {
+                        synth_block4<true>(s, b0, je - j);
+                        if (j + 4 < je) {
+                            guard = guard_check(s);
+                            synth_block4<true>(s, b1, je - j - 4);
                         }
                     }
+                }
+            } else if (je - js == kSegLen) {
+                // full segment, straight-line
 #pragma unroll
-                    for (int t = 0; t < 8; t += 2) {
-                        double q0[FW][2], q1[FW][2];
-#pragma unroll
-                        for (int f = 0; f < FW; f++) {
-                            q0[f][0] = q[f][t][0];
-                            q0[f][1] = q[f][t][1];
-                            q1[f][0] = q[f][t + 1][0];
-                            q1[f][1] = q[f][t + 1][1];
-                        }
-                        synth_pair_step(s, b[t], b[t + 1], q0, q1, true);
-                    }
+                for (int bk = 0; bk < kSegLen; bk += 8) {
+                    SBlock<FW> b0, b1;
+                    load_block(b0, bet, qs, js + bk);
+                    load_block(b1, bet, qs, js + bk + 4);
+                    synth_block4<false>(s, b0, 4);
+                    synth_block4<false>(s, b1, 4);
                 }
             } else {
-                for (int j = js; j < je; j += 2) {
-                    double q0[FW][2], q1[FW][2];
-                    const bool odd = j + 1 < je;
-                    const int jn = odd ? j + 1 : j;
-#pragma unroll
-                    for (int f = 0; f < FW; f++) {
-                        q0[f][0] = qs[f][2 * j];
-                        q0[f][1] = qs[f][2 * j + 1];
-                        q1[f][0] = qs[f][2 * jn];
-                        q1[f][1] = qs[f][2 * jn + 1];
-                    }
-                    synth_pair_step(s, bet[j], bet[jn], q0, q1, odd);
+                // last, partial segment of the order: full blocks, then one
+                // bounded block
+                int j = js;
+                for (; j + 8 <= je; j += 8) {
+                    SBlock<FW> b0, b1;
+                    load_block(b0, bet, qs, j);
+                    load_block(b1, bet, qs, j + 4);
+                    synth_block4<false>(s, b0, 4);
+                    synth_block4<false>(s, b1, 4);
+                }
+                if (j < je) {
+                    SBlock<FW> b0, b1;
+                    load_block(b0, bet, qs, j);
+                    load_block(b1, bet, qs, j + 4);
+                    synth_block4<false>(s, b0, je - j);
+                    if (j + 4 < je) synth_block4<false>(s, b1, je - j - 4);
                 }
             }
         }
+
+#pragma unroll
+        for (int k = 0; k < kPrefetchSlots; k++) sink ^= pf[k];
 
         // Mirror fold: north = E + O, south = E - O.  For the adjoint of the
         // analysis the output carries (2 pi/nphi) w_i / c_m.
@@ -303,6 +387,8 @@ __global__ void __launch_bounds__(64) k_legendre_synth(LegArgs a)
             }
         }
     }
+    // keeps the prefetch loads alive; nfields is never negative
+    if (a.nfields < 0) a.out[lane] = (double)sink;
 }
 
 // ---------------------------------------------------------------------------
@@ -310,11 +396,113 @@ __global__ void __launch_bounds__(64) k_legendre_synth(LegArgs a)
 // latitude pairs of one order (64 LP >= npair) for a range of degrees.
 // ---------------------------------------------------------------------------
 template <int LP, int FW>
+struct AState {
+    double x[LP], ua[LP], ub[LP];
+    int k[LP];
+    // folded, weighted inputs w (F_N + F_S), w (F_N - F_S); set to 0 while
+    // the lane's value is scaled, so scaled lanes add exactly 0 without masking
+    double ger[LP][FW], gei[LP][FW], gor[LP][FW], goi[LP][FW];
+};
+
+// Where the inputs of an analysis wave come from.
+template <int FW>
+struct AInputs {
+    const double* F[FW];  // F_m(theta) of each field (this order)
+    int nlat, npair, adjoint;
+    const double* wq;
+};
+
+// (Re)loads the folded inputs of every lane, zero for scaled lanes.
+template <int LP, int FW>
+__device__ __forceinline__ void analys_inputs(AState<LP, FW>& s, const AInputs<FW>& in)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        const int pair = p * 64 + lane;
+        const bool act = pair < in.npair;
+        const int pc = act ? pair : 0;
+        const bool middle = (in.nlat & 1) && pc == in.npair - 1;
+        double wt = !act ? 0.0 : (in.adjoint ? (middle ? 0.5 : 1.0) : in.wq[pc]);
+        if (s.k[p]) wt = 0.0;
+#pragma unroll
+        for (int f = 0; f < FW; f++) {
+            const double2 fn = *(const double2*)(in.F[f] + 2 * pc);
+            const double2 fs = *(const double2*)(in.F[f] + 2 * (in.nlat - 1 - pc));
+            s.ger[p][f] = wt * (fn.x + fs.x);
+            s.gei[p][f] = wt * (fn.y + fs.y);
+            s.gor[p][f] = wt * (fn.x - fs.x);
+            s.goi[p][f] = wt * (fn.y - fs.y);
+        }
+    }
+}
+
+// Guard check; returns whether any lane is still scaled and records in
+// `changed` whether some exponent moved.  The inputs are refreshed after the
+// chunk: a lane that just became live carries values near 2^-256, so the few
+// steps it spends with zero inputs drop only contributions below 2^-200 (the
+// polar-cut bound).
+template <int LP, int FW>
+__device__ __forceinline__ bool analys_guard(AState<LP, FW>& s, bool& changed)
+{
+    const double down = 0x1p-256;
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        if (s.k[p] > 0 && (fabs(s.ua[p]) >= 1.0 || fabs(s.ub[p]) >= 1.0)) {
+            s.ua[p] *= down;
+            s.ub[p] *= down;
+            s.k[p] -= 1;
+            changed = true;
+        }
+        any |= s.k[p] > 0;
+    }
+    return wave_any(any);
+}
+
+// One recurrence step (even t: ua and the even inputs, odd t: ub and the odd
+// inputs); returns this lane's partial sum over its pairs, per field.
+template <int LP, int FW>
+__device__ __forceinline__ void analys_step(AState<LP, FW>& s, int t, double b,
+                                            double (&sr)[FW], double (&si)[FW])
+{
+#pragma unroll
+    for (int f = 0; f < FW; f++) sr[f] = si[f] = 0.0;
+    if ((t & 1) == 0) {
+#pragma unroll
+        for (int p = 0; p < LP; p++) {
+            s.ua[p] = fma(s.x[p], s.ub[p], b * s.ua[p]);
+#pragma unroll
+            for (int f = 0; f < FW; f++) {
+                sr[f] = fma(s.ger[p][f], s.ua[p], sr[f]);
+                si[f] = fma(s.gei[p][f], s.ua[p], si[f]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < LP; p++) {
+            s.ub[p] = fma(s.x[p], s.ua[p], b * s.ub[p]);
+#pragma unroll
+            for (int f = 0; f < FW; f++) {
+                sr[f] = fma(s.gor[p][f], s.ub[p], sr[f]);
+                si[f] = fma(s.goi[p][f], s.ub[p], si[f]);
+            }
+        }
+    }
+}
+
+// Each lane's partial sums go straight to LDS, one row of 64 lanes per
+// (degree, field, re/im); every 16/FW degrees one pass sums the 32 rows
+// (padded rows: the column reads are free of bank conflicts).  No
+// accumulators stay in registers.
+template <int LP, int FW>
 __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
 {
-    constexpr int C = kChunk;
-    constexpr int NV = 2 * C * FW;  // reduced values per chunk: 32 or 64
-    static_assert(NV == 32 || NV == 64, "chunk/field combination");
+    constexpr int C = kChunk;       // degrees per beta block load
+    constexpr int SC = kChunk / FW; // degrees per reduction
+    constexpr int NV = 2 * SC * FW; // rows reduced per pass
+    static_assert(NV == 32, "two lanes per row");
+    static_assert(kSegLen % C == 0, "chunks tile a segment");
     __shared__ double red[NV][65];
 
     cip U = (cip)a.units + (size_t)blockIdx.x * kUnitInts;
@@ -340,143 +528,128 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
         foff[f] = field_f_off(a, ff, M, nlat);
     }
 
-    // per-pair inputs: folded, weighted Fourier coefficients
-    double x[LP], ua[LP], ub[LP];
-    int k[LP];
-    double fer[LP][FW], fei[LP][FW], for_[LP][FW], foi[LP][FW];
+    AState<LP, FW> s;
+    AInputs<FW> in;
+#pragma unroll
+    for (int f = 0; f < FW; f++) in.F[f] = a.in + foff[f] + 2 * ((size_t)m * nlat);
+    in.nlat = nlat;
+    in.npair = npair;
+    in.adjoint = a.adjoint;
+    in.wq = P->wq;
+    bool anyk = false;
 #pragma unroll
     for (int p = 0; p < LP; p++) {
         const int pair = p * 64 + lane;
         const bool act = pair < npair;
         const int pc = act ? pair : 0;
-        const bool middle = (nlat & 1) && pc == npair - 1;
-        const double wt = !act ? 0.0 : (a.adjoint ? (middle ? 0.5 : 1.0) : P->wq[pc]);
-        x[p] = act ? P->xp[pc] : 0.0;
+        s.x[p] = act ? P->xp[pc] : 0.0;
         if (rst < 0) {
-            ua[p] = act ? P->start_y[(size_t)m * npair + pc] : 0.0;
-            ub[p] = 0.0;
-            k[p] = act ? P->start_k[(size_t)m * npair + pc] : 0;
+            s.ua[p] = act ? P->start_y[(size_t)m * npair + pc] : 0.0;
+            s.ub[p] = 0.0;
+            s.k[p] = act ? P->start_k[(size_t)m * npair + pc] : 0;
         } else {
             const double2 st = *(const double2*)(P->rst_y + 2 * ((size_t)rst * npair + pc));
-            ua[p] = act ? st.x : 0.0;
-            ub[p] = act ? st.y : 0.0;
-            k[p] = act ? P->rst_k[(size_t)rst * npair + pc] : 0;
+            s.ua[p] = act ? st.x : 0.0;
+            s.ub[p] = act ? st.y : 0.0;
+            s.k[p] = act ? P->rst_k[(size_t)rst * npair + pc] : 0;
         }
-#pragma unroll
-        for (int f = 0; f < FW; f++) {
-            const double* F = a.in + foff[f] + 2 * ((size_t)m * nlat);
-            const double2 fn = *(const double2*)(F + 2 * pc);
-            const double2 fs = *(const double2*)(F + 2 * (nlat - 1 - pc));
-            fer[p][f] = wt * (fn.x + fs.x);
-            fei[p][f] = wt * (fn.y + fs.y);
-            for_[p][f] = wt * (fn.x - fs.x);
-            foi[p][f] = wt * (fn.y - fs.y);
-        }
+        anyk |= s.k[p] > 0;
     }
-    bool anyk = false;
-#pragma unroll
-    for (int p = 0; p < LP; p++) anyk |= k[p] > 0;
+    analys_inputs(s, in);
     bool guard = wave_any(anyk);
+
+    // Warm L2 with the beta entries of this unit (one word per 64-byte line
+    // per lane, consumed at the end; see the synthesis kernel).
+    __builtin_amdgcn_sched_barrier(0);
+    unsigned pf;
+    {
+        const int nbytes = (j1 - j0 + C) * 8;
+        const int off = lane * 64;
+        pf = *(const unsigned*)((const char*)(P->beta + base + j0) + (off < nbytes ? off : 0));
+    }
     const double cm0 = 1.0, cm1 = a.adjoint ? 2.0 : 1.0;
     const double cm = m == 0 ? cm0 : cm1;
-    const double down = 0x1p-256;
 
-    for (int c = j0; c < j1; c += C) {
-        double acc[C][FW][2];
+    // units start on a segment boundary (j0 is a multiple of the split length)
+    for (int js = j0; js < j1; js += kSegLen) {
+        // unconditional segment rescale (shift 0 for segment 0)
+        const int sh = segexp[js / kSegLen];
 #pragma unroll
-        for (int t = 0; t < C; t++)
+        for (int p = 0; p < LP; p++) {
+            s.ua[p] = __builtin_amdgcn_ldexp(s.ua[p], sh);
+            s.ub[p] = __builtin_amdgcn_ldexp(s.ub[p], sh);
+        }
+        const int je = min(js + kSegLen, j1);
+        for (int c = js; c < je; c += C) {
+            // beta for the chunk in one block load (the table is padded).  A
+            // partial last chunk runs all C steps: the extra degrees belong to
+            // no output (their results are not written) and the unit ends here.
+            D16 b;
+            cd16p pbk = (cd16p)(bet + c);
 #pragma unroll
-            for (int f = 0; f < FW; f++) acc[t][f][0] = acc[t][f][1] = 0.0;
-
+            for (int i = 0; i < C; i++) b.v[i] = pbk->v[i];
+            bool changed = false;
 #pragma unroll
-        for (int t = 0; t < C; t++) {
-            const int j = c + t;
-            if (j < j1) {
-                if ((t & 1) == 0) {
-                    if (j > 0 && (j % kSegLen) == 0) {
-                        const double sc = __builtin_amdgcn_ldexp(1.0, segexp[j / kSegLen]);
+            for (int c0 = 0; c0 < C; c0 += SC) {
+                // this lane's output scale, loaded ahead of the steps (clamped
+                // index: lanes past the unit's end write nothing)
+                const int v = lane & 31;
+                const int h = lane >> 5;
+                const int comp = v & 1;
+                const int t_out = (v >> 1) / FW;
+                const int f_out = (v >> 1) % FW;
+                const int j_out = c + c0 + t_out;
+                const double gam = P->gamma[base + min(j_out, je - 1)] * cm;
+                if (guard) {
 #pragma unroll
-                        for (int p = 0; p < LP; p++) {
-                            ua[p] *= sc;
-                            ub[p] *= sc;
-                        }
-                    }
-                    if (guard && (j & (kGuardEvery - 1)) == 0) {
-                        bool any = false;
-#pragma unroll
-                        for (int p = 0; p < LP; p++) {
-                            const bool big = fabs(ua[p]) >= 1.0 || fabs(ub[p]) >= 1.0;
-                            if (k[p] > 0 && big) {
-                                ua[p] *= down;
-                                ub[p] *= down;
-                                k[p] -= 1;
-                            }
-                            any |= k[p] > 0;
-                        }
-                        guard = wave_any(any);
-                    }
-                }
-                const double b = bet[j];
-                if ((t & 1) == 0) {
-#pragma unroll
-                    for (int p = 0; p < LP; p++) {
-                        ua[p] = fma(x[p], ub[p], b * ua[p]);
-                        const double v = k[p] ? 0.0 : ua[p];
+                    for (int t = 0; t < SC; t++) {
+                        if (((c0 + t) & (kGuardEvery - 1)) == 0) guard = analys_guard(s, changed);
+                        double sr[FW], si[FW];
+                        analys_step(s, c0 + t, b.v[c0 + t], sr, si);
 #pragma unroll
                         for (int f = 0; f < FW; f++) {
-                            acc[t][f][0] = fma(fer[p][f], v, acc[t][f][0]);
-                            acc[t][f][1] = fma(fei[p][f], v, acc[t][f][1]);
+                            red[2 * (t * FW + f)][lane] = sr[f];
+                            red[2 * (t * FW + f) + 1][lane] = si[f];
                         }
                     }
                 } else {
 #pragma unroll
-                    for (int p = 0; p < LP; p++) {
-                        ub[p] = fma(x[p], ua[p], b * ub[p]);
-                        const double v = k[p] ? 0.0 : ub[p];
+                    for (int t = 0; t < SC; t++) {
+                        double sr[FW], si[FW];
+                        analys_step(s, c0 + t, b.v[c0 + t], sr, si);
 #pragma unroll
                         for (int f = 0; f < FW; f++) {
-                            acc[t][f][0] = fma(for_[p][f], v, acc[t][f][0]);
-                            acc[t][f][1] = fma(foi[p][f], v, acc[t][f][1]);
+                            red[2 * (t * FW + f)][lane] = sr[f];
+                            red[2 * (t * FW + f) + 1][lane] = si[f];
                         }
                     }
                 }
-            }
-        }
-
-        // cross-lane reduction of the chunk through LDS
+                // row v = lane % 32 summed over the 64 lanes by two lanes,
+                // four independent partial sums each
+                __syncthreads();
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-        for (int t = 0; t < C; t++)
-#pragma unroll
-            for (int f = 0; f < FW; f++) {
-                red[(t * FW + f) * 2 + 0][lane] = acc[t][f][0];
-                red[(t * FW + f) * 2 + 1][lane] = acc[t][f][1];
+                for (int r = 0; r < 32; r += 4) {
+                    s0 += red[v][h * 32 + r];
+                    s1 += red[v][h * 32 + r + 1];
+                    s2 += red[v][h * 32 + r + 2];
+                    s3 += red[v][h * 32 + r + 3];
+                }
+                double sum = (s0 + s1) + (s2 + s3);
+                sum += __shfl_xor(sum, 32);
+                __syncthreads();
+                if (h == 0 && j_out < je && f_out < nf) {
+                    const long idx = base + j_out;
+                    double val = gam * sum;
+                    if (m == 0 && comp == 1) val = 0.0;
+                    a.out[qoff[f_out] + 2 * idx + comp] = val;
+                }
             }
-        __syncthreads();
-        double sum = 0.0;
-        int v;
-        if (NV == 32) {
-            v = lane & 31;
-            const int h = (lane >> 5) * 32;
-#pragma unroll 8
-            for (int r = 0; r < 32; r++) sum += red[v][h + r];
-            sum += __shfl_xor(sum, 32);
-        } else {
-            v = lane;
-#pragma unroll 8
-            for (int r = 0; r < 64; r++) sum += red[v][r];
-        }
-        __syncthreads();
-        const int t = v / (2 * FW);
-        const int f = (v / 2) % FW;
-        const int comp = v & 1;
-        const int j = c + t;
-        if (lane < NV && j < j1 && f < nf) {
-            const long idx = base + j;
-            double val = P->gamma[idx] * sum * cm;
-            if (m == 0 && comp == 1) val = 0.0;
-            a.out[qoff[f] + 2 * idx + comp] = val;
+            if (wave_any(changed)) analys_inputs(s, in);
         }
     }
+    // keeps the prefetch load alive; nfields is never negative
+    if (a.nfields < 0) a.out[lane] = (double)pf;
 }
 
 // ---------------------------------------------------------------------------
@@ -495,16 +668,17 @@ int launch_prescale(const DevPlan* plans, const long* q_off, const long* s_off, 
 template <int LP, int FW>
 static int launch_synth_t(const LegLaunch& l, void* stream)
 {
-    LegArgs a{l.plans, l.units, l.q_off, l.f_off, l.in, l.out, l.nfields, l.adjoint};
-    hipLaunchKernelGGL((k_legendre_synth<LP, FW>), dim3(l.nunits, l.grid_y), dim3(64), 0,
-                       (hipStream_t)stream, a);
+    const int wpg = std::max(1, std::min(l.wpg, 8));
+    LegArgs a{l.plans, l.units, l.q_off, l.f_off, l.in, l.out, l.nfields, l.adjoint, l.nunits, wpg};
+    hipLaunchKernelGGL((k_legendre_synth<LP, FW>), dim3((l.nunits + wpg - 1) / wpg, l.grid_y),
+                       dim3(64 * wpg), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
 template <int LP, int FW>
 static int launch_analys_t(const LegLaunch& l, void* stream)
 {
-    LegArgs a{l.plans, l.units, l.q_off, l.f_off, l.in, l.out, l.nfields, l.adjoint};
+    LegArgs a{l.plans, l.units, l.q_off, l.f_off, l.in, l.out, l.nfields, l.adjoint, l.nunits, 1};
     hipLaunchKernelGGL((k_legendre_analys<LP, FW>), dim3(l.nunits, l.grid_y), dim3(64), 0,
                        (hipStream_t)stream, a);
     return (int)hipGetLastError();
@@ -515,9 +689,8 @@ int launch_legendre_synth(const LegLaunch& l, void* stream)
     if (l.nunits <= 0) return 0;
 #define SHTN_S(LPV, FWV) \
     if (l.lp == LPV && l.fw == FWV) return launch_synth_t<LPV, FWV>(l, stream);
-    SHTN_S(1, 1) SHTN_S(2, 1) SHTN_S(4, 1) SHTN_S(8, 1)
+    SHTN_S(1, 1) SHTN_S(2, 1) SHTN_S(4, 1)
     SHTN_S(1, 2) SHTN_S(2, 2) SHTN_S(4, 2)
-    SHTN_S(1, 4) SHTN_S(2, 4)
 #undef SHTN_S
     return (int)hipErrorInvalidValue;
 }

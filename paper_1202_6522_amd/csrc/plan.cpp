@@ -79,6 +79,67 @@ static int log2_floor(ld v)
     return e - 1;
 }
 
+// For each order m, scans latitude pairs from the pole toward the equator and
+// runs the kernels' rescaled recurrence (same steps, same guard) to find the
+// first pair whose |P_n^m| reaches 2^kPolarLog2 for some n <= lmax; the pairs
+// before it get a zero start value (so they contribute exactly 0 and never
+// hold a wave in the guarded, masked mode).  |P| grows away from the poles, so
+// the first significant pair bounds the cut.
+static void polar_cut(Plan& p)
+{
+    const int L = p.L, M = p.M, np = p.npair;
+    p.first_pair.assign(M + 1, 0);
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned tid = 0; tid < nth; tid++) {
+        pool.emplace_back([&, tid]() {
+            const double down = std::ldexp(1.0, -kGuardUnit);
+            for (int m = (int)tid; m <= M; m += (int)nth) {
+                const long base = lm_index(L, m, m);
+                int i0 = np;
+                for (int i = 0; i < np; i++) {
+                    double x = p.xp[i];
+                    double ua = p.start_y[(size_t)m * np + i], ub = 0.0;
+                    int k = p.start_k[(size_t)m * np + i];
+                    bool sig = false;
+                    int E = 0;  // current segment exponent: P = u * gamma
+                    for (int j = 0; j <= L - m && !sig; j += 2) {
+                        if (j > 0 && j % kSegLen == 0) {
+                            int d = p.segexp[p.segoff[m] + j / kSegLen];
+                            ua = std::ldexp(ua, d);
+                            ub = std::ldexp(ub, d);
+                            E += d;
+                        }
+                        if (j % kGuardEvery == 0 && k > 0 && (std::fabs(ua) >= 1.0 || std::fabs(ub) >= 1.0)) {
+                            ua *= down;
+                            ub *= down;
+                            k -= 1;
+                        }
+                        ua = std::fma(x, ub, p.beta[base + j] * ua);
+                        if (j + 1 <= L - m) ub = std::fma(x, ua, p.beta[base + j + 1] * ub);
+                        // |P| = |u| gamma 2^{-256 k}; gamma >= 1 within a segment
+                        const double v = std::max(std::fabs(ua) * p.gamma[base + j],
+                                                  j + 1 <= L - m ? std::fabs(ub) * p.gamma[base + j + 1] : 0.0);
+                        if (v > 0.0) {
+                            int e;
+                            std::frexp(v, &e);
+                            if (e - (long)kGuardUnit * k >= kPolarLog2) sig = true;
+                        }
+                    }
+                    (void)E;
+                    if (sig) { i0 = i; break; }
+                }
+                p.first_pair[m] = i0;
+                for (int i = 0; i < i0; i++) {
+                    p.start_y[(size_t)m * np + i] = 0.0;
+                    p.start_k[(size_t)m * np + i] = 0;
+                }
+            }
+        });
+    }
+    for (auto& th : pool) th.join();
+}
+
 Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
 {
     if (L < 0 || M < 0 || M > L) { err = "need 0 <= mmax <= lmax"; return nullptr; }
@@ -174,6 +235,9 @@ Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
         }
     }
 
+    // ---- static polar cut (Sec. 3.1) ----
+    polar_cut(*p);
+
     // ---- FFT twiddles ----
     const int K = p->K;
     p->tw.resize(2 * (size_t)K);
@@ -259,7 +323,13 @@ int rebuild_units(Plan& p, std::string& err)
     }
     for (auto& mp : mpairs)
         for (int b = 0; b < nblk; b++) {
-            int u[kUnitInts] = {0, t.fw, 0, mp.first, mp.second, b * blk, 0, -1};
+            // a block lies entirely in the polar cut of an order when all its
+            // pairs come before that order's first kept pair
+            const int bend = std::min((b + 1) * blk, np);
+            int flags = 0;
+            if (bend <= p.first_pair[mp.first]) flags |= 1;
+            if (mp.second >= 0 && bend <= p.first_pair[mp.second]) flags |= 2;
+            int u[kUnitInts] = {0, t.fw, 0, mp.first, mp.second, b * blk, 0, flags};
             p.synth_units.insert(p.synth_units.end(), u, u + kUnitInts);
         }
 
@@ -332,7 +402,12 @@ void build_image(Plan& p)
     p.table_off[t++] = off; off = put(p.image, off, p.xp);
     p.table_off[t++] = off; off = put(p.image, off, p.wq);
     p.table_off[t++] = off; off = put(p.image, off, p.wfull);
-    p.table_off[t++] = off; off = put(p.image, off, p.beta);
+    {
+        // padded: the kernels load beta in blocks that may run past the end
+        std::vector<double> bpad(p.beta);
+        bpad.resize(p.beta.size() + kTablePad, 0.0);
+        p.table_off[t++] = off; off = put(p.image, off, bpad);
+    }
     p.table_off[t++] = off; off = put(p.image, off, p.gamma);
     p.table_off[t++] = off; off = put(p.image, off, p.start_y);
     p.table_off[t++] = off; off = put(p.image, off, p.start_k);
@@ -351,7 +426,7 @@ WorkLayout work_layout(const Plan& p, int nfields)
 {
     WorkLayout w;
     w.f_bytes = align256((size_t)nfields * (p.M + 1) * p.nlat * 16);
-    w.q_bytes = align256((size_t)nfields * p.nlm * 16);
+    w.q_bytes = align256(((size_t)nfields * p.nlm + kTablePad) * 16);  // padded for block loads
     w.total = w.f_bytes + w.q_bytes;
     return w;
 }

@@ -24,9 +24,17 @@ constexpr int kSegLen = 32;
 // and decrements k.
 constexpr int kGuardUnit = 256;
 constexpr int kGuardEvery = 4;
+// Static polar cut (Sec. 3.1, polar optimisation): a latitude whose |P_n^m|
+// stays below 2^kPolarLog2 for every n <= lmax is dropped from order m (its
+// start value is set to 0); every contribution dropped is below 2^-200.
+constexpr int kPolarLog2 = -200;
 // Analysis accumulates kChunk consecutive degrees per lane before a
 // cross-lane reduction.
 constexpr int kChunk = 16;
+// Entries of zero padding after the tables that the kernels read in blocks
+// (beta, the rescaled spectrum): a block starting at an order's last degree
+// stays in bounds.
+constexpr int kTablePad = 32;
 // Largest latitude-pair count one analysis wave covers (64 lanes x 8 pairs).
 constexpr int kMaxAnalysPairs = 512;
 
@@ -39,7 +47,9 @@ enum UnitField {
     U_M1 = 4,     // second order (m pairing) or -1
     U_PB = 5,     // synthesis: first latitude pair of the block; analysis: first step j0
     U_J1 = 6,     // analysis: one past the last step (n = m + j)
-    U_RST = 7,    // analysis: restart slot or -1 (start at n = m)
+    U_RST = 7,    // analysis: restart slot or -1 (start at n = m);
+                  // synthesis: bit 0 / bit 1 set if the block is entirely
+                  // polar-cut for the first / second order (F written as 0)
 };
 constexpr int kUnitInts = 8;
 
@@ -71,7 +81,8 @@ struct Tiling {
     int analys_lp = 8;
     int fw = 1;
     int m_pairing = 1;
-    int split = 0;  // 0 = automatic
+    int split = 0;     // 0 = automatic
+    int fft_rows = 0;  // latitude rows per FFT workgroup, 0 = automatic
 };
 
 struct Plan {
@@ -90,6 +101,7 @@ struct Plan {
     std::vector<int> rst_k;
     std::vector<double> tw, rtw;
     std::vector<int> synth_units, analys_units;
+    std::vector<int> first_pair;              // per m: first latitude pair kept by the polar cut
     // device image
     std::vector<unsigned char> image;  // staged device buffer contents
     std::vector<size_t> table_off;     // byte offsets of each table inside the image
@@ -125,6 +137,7 @@ struct LegLaunch {
     int nfields;
     int adjoint;           // 0 forward transform, 1 adjoint variant
     int lp, fw;            // template selection
+    int wpg;               // synthesis: waves (consecutive units) per workgroup
 };
 // Qs = gamma * Q per field; q_off/s_off/fplan per field (device) or null.
 int launch_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int* fplan,

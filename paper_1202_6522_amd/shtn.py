@@ -47,7 +47,7 @@ _SIGS = {
     "shtn_get_grid": (_c.c_int, [_vp, _dp, _dp]),
     "shtn_legendre_flops": (_c.c_double, [_vp]),
     "shtn_plan_table": (_c.c_long, [_vp, _c.c_int, _vp, _sz]),
-    "shtn_plan_set_tiling": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "shtn_plan_set_tiling": (_c.c_int, [_vp] + [_c.c_int] * 6),
     "shtn_batch": (_vp, [_c.c_int, _c.POINTER(_vp)]),
     "shtn_batch_destroy": (None, [_vp]),
     "shtn_batch_offsets": (_c.c_int, [_vp, _c.POINTER(_sz), _c.POINTER(_sz)]),
@@ -170,7 +170,7 @@ def shtn_legendre_flops(h):
 
 _TABLE_DTYPES = {0: np.float64, 1: np.float64, 2: np.float64, 3: np.float64, 4: np.float64,
                  5: np.float64, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.float64,
-                 10: np.int32, 11: np.int32, 12: np.int32, 13: np.int32}
+                 10: np.int32, 11: np.int32, 12: np.int32, 13: np.int32, 14: np.int32}
 
 
 def shtn_plan_table(h, which):
@@ -185,9 +185,9 @@ def shtn_plan_table(h, which):
     return out
 
 
-def shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split=0):
-    return check(load_library().shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split),
-                 "shtn_plan_set_tiling")
+def shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split=0, fft_rows=0):
+    return check(load_library().shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split,
+                                                     fft_rows), "shtn_plan_set_tiling")
 
 
 PROFILE_KINDS = {0: "prescale", 1: "legendre_synth", 2: "legendre_analys", 3: "c2r", 4: "r2c"}
@@ -250,14 +250,14 @@ class Plan:
         off = (-ptr) % 256
         shtn_plan_upload(self.handle, ptr + off, _stream_ptr(torch, self.device))
 
-    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=1, split=0):
-        shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, fw, m_pairing, split)
+    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=1, split=0, fft_rows=0):
+        shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, fw, m_pairing, split, fft_rows)
         self._upload()
 
     def tiling(self):
         t = shtn_plan_table(self.handle, 13)
         return dict(synth_lp=int(t[0]), analys_lp=int(t[1]), fw=int(t[2]), m_pairing=int(t[3]),
-                    split=int(t[4]))
+                    split=int(t[4]), fft_rows=int(t[5]))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -55,10 +55,15 @@ def test_scalar_cases_full(case, dev):
     assert rel(R2, Q) <= 1e-11
 
 
-def test_lmax1023_sampled(dev):
+@pytest.mark.parametrize("tiling", [
+    None,
+    dict(synth_lp=1, analys_lp=8, m_pairing=0, split=128),
+    dict(synth_lp=4, analys_lp=8, m_pairing=1, split=512, fft_rows=2),
+])
+def test_lmax1023_sampled(tiling, dev):
     p, Q = inputs.scalar_case(2)
     L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
-    plan = make_plan(L, M, nlat, nphi, dev)
+    plan = make_plan(L, M, nlat, nphi, dev, **(tiling or {}))
     Qd = to_dev(Q, dev)
     g = plan.synth(Qd)
     # sampled rows, both hemispheres, poles and equator included
@@ -123,7 +128,7 @@ def test_edge_shapes_all_transforms(shape, dev):
     dict(synth_lp=2, analys_lp=8, fw=1, m_pairing=1, split=64),
     dict(synth_lp=4, analys_lp=4, fw=2, m_pairing=1),
     dict(synth_lp=1, analys_lp=4, fw=2, m_pairing=0, split=32),
-    dict(synth_lp=8, analys_lp=8, fw=1, m_pairing=1, split=96),
+    dict(synth_lp=4, analys_lp=8, fw=1, m_pairing=1, split=96),
 ])
 def test_tilings_agree(tiling, dev):
     L, M, nlat, nphi = 255, 255, 256, 512

@@ -12,7 +12,7 @@ import oracle
 from paper_1202_6522_amd import inputs
 from paper_1202_6522_amd import shtn as S
 
-T_XP, T_SP, T_WQ, T_BETA, T_GAMMA, T_STY, T_STK, T_SEGE, T_SEGO, T_RSTY, T_RSTK, T_AU, T_SU, T_TIL = range(14)
+T_XP, T_SP, T_WQ, T_BETA, T_GAMMA, T_STY, T_STK, T_SEGE, T_SEGO, T_RSTY, T_RSTK, T_AU, T_SU, T_TIL, T_FIRST = range(15)
 
 
 @pytest.fixture(scope="module")
@@ -49,8 +49,8 @@ def test_calls_before_upload_and_null_pointers(lib):
         assert lib.shtn_work_bytes(h, 0) == 0
         assert lib.shtn_lm_index(h, 3, 4) == -1
         assert lib.shtn_lm_index(h, 8, 8) == S.shtn_nlm(h) - 1
-        assert lib.shtn_plan_set_tiling(h, 3, 1, 1, 1, 0) == S.SHTN_EINVAL
-        assert lib.shtn_plan_set_tiling(h, 1, 1, 1, 1, 40) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 3, 1, 1, 1, 0, 0) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 1, 1, 1, 1, 40, 0) == S.SHTN_EINVAL
         assert S.shtn_strerror(S.SHTN_EUNSUPPORTED) == "unsupported configuration"
     finally:
         S.shtn_plan_destroy(h)
@@ -77,7 +77,7 @@ def test_plan_grid_matches_oracle(nlat):
 
 
 def _tables(h):
-    return {k: S.shtn_plan_table(h, k) for k in range(14)}
+    return {k: S.shtn_plan_table(h, k) for k in range(15)}
 
 
 def test_beta_gamma_tables():
@@ -120,12 +120,17 @@ def test_start_values_scaled_exponents():
                                                                 (2.0 * np.arange(1, L + 1))))])
                         - np.log2(4 * np.pi))
         ref = logamm[:, None] + m * np.log2(sp)[None, :]
-        got = np.log2(np.abs(sy)) - 256.0 * sk
-        assert np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))) < 1e-12
-        assert np.all(np.sign(sy) == (-1.0) ** m)
+        first = t[T_FIRST]
+        kept = np.arange(npair)[None, :] >= first[:, None]
+        # pairs inside the static polar cut start at exactly 0
+        assert np.all(sy[~kept] == 0) and np.all(sk[~kept] == 0)
+        got = np.log2(np.abs(np.where(kept, sy, 1.0))) - 256.0 * sk
+        err = np.abs(got - ref) / np.maximum(1, np.abs(ref))
+        assert np.max(err[kept]) < 1e-12
+        assert np.all(np.sign(sy[kept]) == np.broadcast_to((-1.0) ** m, sy.shape)[kept])
         pos = sk > 0
         assert np.all(np.abs(sy[pos]) < 1) and np.all(np.abs(sy[pos]) >= 2.0**-256)
-        assert np.all(np.abs(sy[~pos]) >= 2.0**-256)
+        assert np.all(np.abs(sy[kept & ~pos]) >= 2.0**-256)
         # small-m values are plain doubles that match the oracle
         # (the oracle takes sin(theta) from its rounded x, which near the pole
         # carries ~1e-16/(1-x) relative error per power of sin)
@@ -393,7 +398,7 @@ def test_synthesis_units_cover_all_work():
     for (L, M, nlat, pairing) in [(31, 31, 32, 1), (40, 33, 51, 1), (40, 33, 51, 0)]:
         h = S.shtn_plan(L, M, nlat, 128)
         try:
-            S.shtn_plan_set_tiling(h, 1, 1, 1, pairing, 0)
+            S.shtn_plan_set_tiling(h, 1, 1, 1, pairing, 0, 0)
             su = S.shtn_plan_table(h, T_SU).reshape(-1, 8)
             npair = (nlat + 1) // 2
             seen = np.zeros((M + 1, npair), int)
@@ -405,3 +410,26 @@ def test_synthesis_units_cover_all_work():
             assert np.all(seen == 1)
         finally:
             S.shtn_plan_destroy(h)
+
+
+def test_polar_cut_drops_only_negligible_latitudes():
+    # Sec. 3.1 polar optimisation: the first kept pair per order is where
+    # max_n |P_n^m| first reaches 2^-200; checked with the long-double oracle,
+    # whose range (1e-4951) covers these values.
+    L, nlat = 1023, 1024
+    h = S.shtn_plan(L, L, nlat, 2048)
+    try:
+        first = S.shtn_plan_table(h, T_FIRST)
+        x = S.shtn_plan_table(h, T_XP)
+        assert first[0] == 0 and np.all(np.diff(first) >= 0)
+        for m in (200, 512, 800, 1000):
+            i0 = int(first[m])
+            assert 0 < i0 < nlat // 2
+            xs = np.array([x[i0 - 1], x[i0]])
+            P = oracle.plm(L, m, xs, precision="ld")
+            rows = slice(oracle.lm_index(L, m, m), oracle.lm_index(L, L, m) + 1)
+            Pm = np.abs(P[rows])
+            assert Pm[:, 0].max() < 2.0**-200, m       # dropped pair: negligible
+            assert Pm[:, 1].max() >= 2.0**-201, m      # first kept pair: at the threshold
+    finally:
+        S.shtn_plan_destroy(h)
