@@ -66,12 +66,16 @@ k_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int
     const DevPlan& P = plans[pi];
     const long qo = q_off ? q_off[f] : (long)f * 2 * P.nlm;
     const long so = s_off ? s_off[f] : (long)f * 2 * P.nlm;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < P.nlm;
-         i += (long)gridDim.x * blockDim.x) {
-        const double g = P.gamma[i];
-        const double2 q = *(const double2*)(Q + qo + 2 * i);
-        *(double2*)(Qs + so + 2 * i) = make_double2(g * q.x, g * q.y);
-    }
+    // two coefficients per thread, both loads issued before the stores
+    const long i0 = (long)blockIdx.x * (2 * blockDim.x) + threadIdx.x;
+    const long i1 = i0 + blockDim.x;
+    const bool v0 = i0 < P.nlm, v1 = i1 < P.nlm;
+    double g0 = 0.0, g1 = 0.0;
+    double2 q0 = make_double2(0.0, 0.0), q1 = q0;
+    if (v0) { g0 = P.gamma[i0]; q0 = *(const double2*)(Q + qo + 2 * i0); }
+    if (v1) { g1 = P.gamma[i1]; q1 = *(const double2*)(Q + qo + 2 * i1); }
+    if (v0) *(double2*)(Qs + so + 2 * i0) = make_double2(g0 * q0.x, g0 * q0.y);
+    if (v1) *(double2*)(Qs + so + 2 * i1) = make_double2(g1 * q1.x, g1 * q1.y);
 }
 
 // Per-lane vector loads that warm L2 ahead of the scalar loads (synthesis).
@@ -658,7 +662,7 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
 int launch_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int* fplan,
                     const double* Q, double* Qs, long max_nlm, int nfields, void* stream)
 {
-    const int blocks = (int)std::min<long>(1024, (max_nlm + 255) / 256);
+    const int blocks = (int)((max_nlm + 511) / 512);
     dim3 grid(std::max(1, blocks), nfields);
     hipLaunchKernelGGL(k_prescale, grid, dim3(256), 0, (hipStream_t)stream, plans, q_off, s_off,
                        fplan, Q, Qs, nfields);

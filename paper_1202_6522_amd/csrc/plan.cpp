@@ -253,9 +253,10 @@ Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
         p->rtw[2 * m + 1] = (double)sinl(a);
     }
 
-    // default tiling: enough synthesis waves to fill the chip at large sizes;
-    // one analysis wave covers every latitude pair of its order
-    p->tiling.synth_lp = np >= 512 ? 2 : 1;
+    // default tiling: one pair per synthesis lane, orders unpaired (measured
+    // fastest at lmax 1023); one analysis wave covers every pair of its order
+    p->tiling.synth_lp = 1;
+    p->tiling.m_pairing = 0;
     p->tiling.analys_lp = 1;
     while (64 * p->tiling.analys_lp < np && p->tiling.analys_lp < 8) p->tiling.analys_lp *= 2;
     if (rebuild_units(*p, err)) { delete p; return nullptr; }
@@ -336,8 +337,9 @@ int rebuild_units(Plan& p, std::string& err)
     // ---- analysis units: (m, degree range) pieces, longest first ----
     int S = t.split;
     if (S <= 0) {
-        long target = (p.nlm + 2047) / 2048;  // about two waves per SIMD at large sizes
-        S = (int)std::max<long>(64, ((target + kSegLen - 1) / kSegLen) * kSegLen);
+        // about two units per SIMD at large sizes (256 at lmax 1023)
+        long target = p.nlm / 2048;
+        S = (int)std::max<long>(64, (target / kSegLen) * kSegLen);
     }
     if (S % kSegLen) { err = "split must be a multiple of 32"; return -1; }
     p.split_used = S;

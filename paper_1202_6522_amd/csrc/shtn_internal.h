@@ -77,10 +77,10 @@ struct DevPlan {
 };
 
 struct Tiling {
-    int synth_lp = 2;
+    int synth_lp = 1;
     int analys_lp = 8;
     int fw = 1;
-    int m_pairing = 1;
+    int m_pairing = 0;
     int split = 0;     // 0 = automatic
     int fft_rows = 0;  // latitude rows per FFT workgroup, 0 = automatic
 };
