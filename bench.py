@@ -82,6 +82,63 @@ def copy_calibration(mib, dev):
     torch.cuda.synchronize(dev)
 
 
+def batch_measure(dev, reps):
+    """Mixed-degree batch (64 fields, lmax from {63,127,255,511}): autotuned
+    graph replay of a synthesis + analysis round trip against the same
+    transforms issued as per-field library calls (10 launches per field pair
+    of calls, no host synchronisation in between)."""
+    import torch
+    from paper_1202_6522_amd import inputs
+    from paper_1202_6522_amd import shtn as S
+    shapes, specs = inputs.batch_case()
+    b = S.Batch(shapes, device=dev)
+    Qp = b.pack_spectra(specs)
+    g = b.new_grids()
+    a = b.new_spectra()
+    tune_us = b.tune(Qp, g, a, reps=5)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    views = []
+    for f, s in enumerate(b.shapes):
+        plan = b.plans[s]
+        views.append((plan.handle, b.field_spectrum(Qp, f).data_ptr(), b.field_grid(g, f).data_ptr(),
+                      b.field_spectrum(a, f).data_ptr(), plan.workspace(1)))
+
+    def per_field():
+        for h, q, gg, aa, w in views:
+            S.shtn_synth(h, q, gg, 1, w, stream)
+            S.shtn_analys(h, gg, aa, 1, w, stream)
+
+    def graph():
+        b.replay(0)
+        b.replay(1)
+
+    out = {}
+    for name, fn in (("per_field", per_field), ("graph", graph)):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize(dev)
+        out[name] = 1e3 * e0.elapsed_time(e1) / reps
+    # accuracy of the batched round trip
+    err = float((a - Qp).abs().max() / Qp.abs().max())
+    flops = sum(8.0 * ((nlat + 1) // 2) * inputs.nlm(L, M) for (L, M, nlat, _) in shapes)
+    return {"workload": "64 fields, lmax drawn from {63,127,255,511} (seed 12026525), nlat=lmax+1, "
+                        "nphi=2(lmax+1), synthesis + analysis round trip",
+            "graph_round_trip_us": round(out["graph"], 2),
+            "per_field_round_trip_us": round(out["per_field"], 2),
+            "speedup_vs_per_field": round(out["per_field"] / out["graph"], 3),
+            "transforms_per_s": round(2 * len(shapes) / (out["graph"] * 1e-6), 1),
+            "legendre_tflops_round_trip": round(2 * flops / (out["graph"] * 1e-6) / 1e12, 3),
+            "tiling": b.tiling(), "tuner_best_us": round(tune_us, 2),
+            "round_trip_rel_err": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +227,7 @@ def main():
         "legendre_tflops": {k: round(flops / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
                             for k in ("legendre_synth", "legendre_analys")},
     }
+    out["batch"] = batch_measure(dev, max(10, args.steps // 4))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, M, nlat, nphi, Qh[0])
     print(json.dumps(out))

@@ -136,30 +136,71 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
 int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
                          int split, int fft_rows);
 
-/* ---- batches of fields with different truncations (one launch per stage) ---- */
+/* ---- batches of fields with different truncations (one launch per stage) ----
+ *
+ * Many independent fields, each with its own truncation and grid, transformed
+ * together: every stage of the transform is one kernel launch over all the
+ * fields (the Legendre analysis one launch per class of latitude-pair count,
+ * or a single one, see shtn_batch_set_tiling).  Same mathematics as
+ * shtn_synth / shtn_analys applied field by field (Sec. 2 of the paper);
+ * synthesis results are bitwise equal to the per-field calls at the same
+ * synth_lp, analysis results agree to rounding.  The batching, graph capture
+ * and tiling autotuner are this library's, not the paper's (its runtime
+ * tuning of Sec. 3.2 picks among code variants per size; here the tuner picks
+ * the work decomposition of the whole batch). */
 typedef struct shtn_batch_s* shtn_batch_t;
 
-/* A batch of nfields fields; field f uses plans[f] (plans may repeat; fields
- * sharing a plan are grouped so one wave can serve several of them).  The
- * plans must stay alive and uploaded.  Packed buffers hold the fields back to
- * back in field order: spectra at q_off[f] doubles (2 per coefficient), grids
- * at grid_off[f] doubles. */
+/* A batch of nfields fields; field f is transformed with plans[f] (plans may
+ * repeat).  The plans must stay alive, uploaded and untouched (no
+ * shtn_plan_set_tiling, no re-upload) while the batch is used.  Host only;
+ * NULL on error (shtn_last_error_detail).  Packed buffers hold the fields
+ * back to back in field order: spectra at q_off[f] doubles (2 per
+ * coefficient, m-major as for a plan), grids at grid_off[f] doubles. */
 shtn_batch_t shtn_batch(int nfields, const shtn_plan_t* plans);
 void shtn_batch_destroy(shtn_batch_t batch);
-/* q_off, grid_off: host arrays of nfields+1 offsets in doubles (last = total). */
+/* q_off, grid_off: host arrays of nfields+1 entries, offsets in doubles (the
+ * last entry is the packed total).  Either may be NULL. */
 int shtn_batch_offsets(shtn_batch_t batch, size_t* q_off, size_t* grid_off);
-size_t shtn_batch_device_bytes(shtn_batch_t batch); /* unit/field tables */
+/* Device bytes of the batch tables (largest over every tiling, so one buffer
+ * serves the tuner) and of the workspace of a batched call. */
+size_t shtn_batch_device_bytes(shtn_batch_t batch);
 size_t shtn_batch_work_bytes(shtn_batch_t batch);
+/* Copies the batch tables to dev_buf (caller-owned, 256-byte aligned, at least
+ * shtn_batch_device_bytes) and waits for the copy.  Needed after creation and
+ * after every shtn_batch_set_tiling; drops captured graphs. */
 int shtn_batch_upload(shtn_batch_t batch, void* dev_buf, void* stream);
-/* Batched synthesis / analysis of every field, each stage one launch over all
- * fields (longest work units first).  Same maths as shtn_synth / shtn_analys. */
+/* Batched synthesis / analysis of every field on `stream` (asynchronous).
+ * Errors as for the plan calls; ESTATE if not uploaded. */
 int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpacked, void* work,
                      void* stream);
 int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpacked, void* work,
                       void* stream);
-/* Sets the batch tiling (same meaning as shtn_plan_set_tiling; split is
- * ignored).  Re-upload afterwards. */
-int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int analys_lp, int fw, int m_pairing);
+/* Tiling of the whole batch: synth_lp (1, 2, 4) latitude pairs per synthesis
+ * lane; fw (1, 2) fields of the same plan per wave; m_pairing (0, 1) orders
+ * m and M-m in one synthesis wave; analys_merge (0, 1): 0 launches the
+ * Legendre analysis once per latitude-pair class (64, 128, 256, 512 pairs),
+ * 1 launches it once with the largest class.  Re-upload afterwards. */
+int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int fw, int m_pairing, int analys_merge);
+/* tiling4 = {synth_lp, fw, m_pairing, analys_merge}. */
+int shtn_batch_get_tiling(shtn_batch_t batch, int* tiling4);
+/* Captures the launch sequence of one direction (which = 0 synthesis
+ * in -> out, 1 analysis) into a hipGraph held by the batch, on a private
+ * stream, for these exact buffers.  Replaying it (shtn_batch_replay) on any
+ * stream runs the transform on those buffers.  The graph holds kernel nodes
+ * only (no memset or copy nodes).  Uploading again drops the graphs. */
+int shtn_batch_capture(shtn_batch_t batch, int which, const double* in, double* out, void* work);
+int shtn_batch_replay(shtn_batch_t batch, int which, void* stream);
+/* Autotuner: times a synthesis (Qpacked -> gridpacked) plus analysis
+ * (gridpacked -> Qout) round trip of graph replays for every tiling
+ * (synth_lp 1|2, fw 1|2, m_pairing 0|1, analys_merge 0|1; reps replays each,
+ * default 10 when reps < 1), keeps the fastest, re-uploads and leaves both
+ * graphs captured for these buffers.  Blocks until done.  With cache_path
+ * (may be NULL), a tiling stored there for the same list of field shapes is
+ * used without timing, and a new result is appended.  *best_us (may be NULL)
+ * receives the best round-trip time, or -1 when taken from the cache.  The
+ * batch must be uploaded; Qout must not alias the other buffers. */
+int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacked, double* Qout,
+                    void* work, void* stream, int reps, const char* cache_path, float* best_us);
 
 /* ---- kernel timing for benchmarks ----
  * When enabled, every kernel launched by the library is bracketed by a pair of

@@ -14,29 +14,22 @@
 
 using namespace shtn;
 
-struct shtn_plan_s {
-    Plan* p;
-};
-
 namespace {
 thread_local std::string g_detail;
+}  // namespace
 
-int fail(int code, const std::string& msg)
+namespace shtn {
+int set_error(int code, const std::string& msg)
 {
     g_detail = msg;
     return code;
 }
 
-int hip_fail(int e, const char* where)
+int hip_error(int e, const char* where)
 {
     g_detail = std::string(where) + ": " + hipGetErrorString((hipError_t)e);
     return SHTN_EHIP;
 }
-
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-const DevPlan* dplan(const Plan& p) { return (const DevPlan*)p.dev; }
-const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.dev + p.table_off[t]); }
 
 int rows_per_block(const Plan& p)
 {
@@ -46,6 +39,16 @@ int rows_per_block(const Plan& p)
     if (r > p.nlat) r = p.nlat;
     return r;
 }
+}  // namespace shtn
+
+namespace {
+int fail(int code, const std::string& msg) { return set_error(code, msg); }
+int hip_fail(int e, const char* where) { return hip_error(e, where); }
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+const DevPlan* dplan(const Plan& p) { return (const DevPlan*)p.dev; }
+const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.dev + p.table_off[t]); }
 
 // Latitude blocks of the same orders share a workgroup (and its scalar cache).
 int synth_wpg(const Plan& p)

@@ -1,15 +1,674 @@
-// Batches of fields with different truncations: placeholder entry points,
-// replaced by the batched implementation.
+// Batches of fields with different truncations (include/shtn.h, shtn_batch_*):
+// every stage of a batched transform is one launch over all fields (the
+// analysis stage one launch per pairs-per-lane class), optionally captured in
+// a hipGraph, with the tiling chosen by a timing autotuner.
+//
+// Work units of all fields go into one list per stage.  A unit names its
+// field slot and its plan, so one launch serves fields of any truncation; the
+// per-plan tables (recurrence coefficients, start values, restart states,
+// twiddles) stay in the plans' own device buffers and are reached through a
+// copy of each plan's device descriptor.  Units are ordered longest first so
+// the tail of a launch is made of short units (the greedy longest-processing-
+// time order of the paper's work split over threads, Sec. 3.3, applied to
+// waves).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "shtn.h"
+#include "shtn_internal.h"
+#include "shtn_profile.h"
+
+using namespace shtn;
+
+namespace {
+
+struct BatchTiling {
+    int synth_lp = 1;      // latitude pairs per synthesis lane (block of 64 lp pairs per wave)
+    int fw = 1;            // fields per wave (fields of the same plan)
+    int m_pairing = 0;     // synthesis: orders m and M-m in one wave
+    int analys_merge = 0;  // analysis: 1 = a single launch at the largest pairs-per-lane class
+};
+
+struct AnalysClass {
+    int lp, fw;
+    size_t first;  // first unit (index into analys_units / kUnitInts)
+    int count;
+};
+
+int analys_lp_for(int npair)
+{
+    int lp = 1;
+    while (64 * lp < npair && lp < 8) lp *= 2;
+    return lp;
+}
+
+}  // namespace
+
+struct shtn_batch_s {
+    int nfields = 0;
+    std::vector<shtn_plan_t> field_plan;  // per user field
+    std::vector<Plan*> plans;             // distinct plans
+    std::vector<int> slot_field;          // slot -> user field (slots grouped by plan)
+    std::vector<int> slot_plan;           // slot -> distinct plan index
+    std::vector<size_t> q_off, g_off;     // per user field (+ total), in doubles
+    std::vector<long> slot_q, slot_g, slot_f, slot_s;  // per slot offsets in doubles
+    size_t work_f_doubles = 0, work_total_bytes = 0;
+    long max_nlm = 0;
+    BatchTiling tiling;
+    // unit tables of the current tiling
+    std::vector<int> synth_units, analys_units, rowblocks;
+    std::vector<AnalysClass> classes;
+    int synth_wpg = 1;
+    // device image
+    std::vector<unsigned char> image;
+    size_t off_plans = 0, off_slot_plan = 0, off_q = 0, off_g = 0, off_f = 0, off_s = 0,
+           off_su = 0, off_au = 0, off_rb = 0;
+    size_t max_image = 0;
+    void* dev = nullptr;
+    bool uploaded = false;
+    // captured graphs: 0 synthesis, 1 analysis
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+size_t put_bytes(std::vector<unsigned char>& img, size_t off, const void* src, size_t bytes)
+{
+    if (img.size() < off + bytes) img.resize(off + bytes);
+    if (bytes) std::memcpy(img.data() + off, src, bytes);
+    return align256(off + bytes);
+}
+
+template <typename T>
+size_t put_vec(std::vector<unsigned char>& img, size_t off, const std::vector<T>& v)
+{
+    return put_bytes(img, off, v.data(), v.size() * sizeof(T));
+}
+
+// Builds the unit tables and the device image for tiling t.
+void build_tables(shtn_batch_s& b, const BatchTiling& t)
+{
+    const int ns = (int)b.slot_field.size();
+    // slot ranges per plan (slots of one plan are consecutive)
+    std::vector<std::pair<int, int>> range(b.plans.size(), {ns, 0});
+    for (int s = 0; s < ns; s++) {
+        auto& r = range[b.slot_plan[s]];
+        r.first = std::min(r.first, s);
+        r.second = std::max(r.second, s + 1);
+    }
+
+    // ---- synthesis units ----
+    struct SU {
+        long cost;
+        int u[kUnitInts];
+    };
+    std::vector<SU> su;
+    int maxblk = 1;
+    for (size_t pi = 0; pi < b.plans.size(); pi++) {
+        const Plan& p = *b.plans[pi];
+        const int blk = 64 * t.synth_lp;
+        const int nblk = (p.npair + blk - 1) / blk;
+        maxblk = std::max(maxblk, nblk);
+        for (int fg = range[pi].first; fg < range[pi].second; fg += t.fw) {
+            const int nf = std::min(t.fw, range[pi].second - fg);
+            for (int m = 0; m <= p.M; m++) {
+                int m2 = -1;
+                if (t.m_pairing) {
+                    m2 = p.M - m;
+                    if (m > m2) break;
+                    if (m2 == m) m2 = -1;
+                }
+                const long cost = (long)(p.L - m + 1) + (m2 >= 0 ? (long)(p.L - m2 + 1) : 0);
+                for (int k = 0; k < nblk; k++) {
+                    const int bend = std::min((k + 1) * blk, p.npair);
+                    int flags = 0;
+                    if (bend <= p.first_pair[m]) flags |= 1;
+                    if (m2 >= 0 && bend <= p.first_pair[m2]) flags |= 2;
+                    SU x{cost * t.synth_lp * nf, {fg, nf, (int)pi, m, m2, k * blk, 0, flags}};
+                    su.push_back(x);
+                }
+            }
+        }
+    }
+    std::stable_sort(su.begin(), su.end(), [](const SU& a, const SU& c) { return a.cost > c.cost; });
+    b.synth_units.clear();
+    for (auto& x : su) b.synth_units.insert(b.synth_units.end(), x.u, x.u + kUnitInts);
+    b.synth_wpg = std::min(8, maxblk);
+
+    // ---- analysis units, per pairs-per-lane class ----
+    int lp_max = 1;
+    for (auto* p : b.plans) lp_max = std::max(lp_max, analys_lp_for(p->npair));
+    std::vector<int> lps;
+    if (t.analys_merge) {
+        lps.push_back(lp_max);
+    } else {
+        for (int lp = 8; lp >= 1; lp /= 2)
+            for (auto* p : b.plans)
+                if (analys_lp_for(p->npair) == lp) {
+                    lps.push_back(lp);
+                    break;
+                }
+    }
+    b.analys_units.clear();
+    b.classes.clear();
+    for (int lp : lps) {
+        const int fw = lp >= 8 ? 1 : t.fw;  // no two-field kernel at 8 pairs per lane
+        std::vector<SU> au;
+        for (size_t pi = 0; pi < b.plans.size(); pi++) {
+            const Plan& p = *b.plans[pi];
+            const int need = analys_lp_for(p.npair);
+            if (t.analys_merge ? false : need != lp) continue;
+            for (int fg = range[pi].first; fg < range[pi].second; fg += fw) {
+                const int nf = std::min(fw, range[pi].second - fg);
+                const size_t nu = p.analys_units.size() / kUnitInts;
+                for (size_t i = 0; i < nu; i++) {
+                    const int* pu = &p.analys_units[i * kUnitInts];
+                    SU x{(long)(pu[U_J1] - pu[U_PB]) * nf,
+                         {fg, nf, (int)pi, pu[U_M0], -1, pu[U_PB], pu[U_J1], pu[U_RST]}};
+                    au.push_back(x);
+                }
+            }
+        }
+        std::stable_sort(au.begin(), au.end(), [](const SU& a, const SU& c) { return a.cost > c.cost; });
+        AnalysClass c{lp, fw, b.analys_units.size() / kUnitInts, (int)au.size()};
+        for (auto& x : au) b.analys_units.insert(b.analys_units.end(), x.u, x.u + kUnitInts);
+        b.classes.push_back(c);
+    }
+
+    // ---- FFT row blocks: {slot, plan, first row, rows} ----
+    b.rowblocks.clear();
+    for (int s = 0; s < ns; s++) {
+        const Plan& p = *b.plans[b.slot_plan[s]];
+        const int rpb = rows_per_block(p);
+        for (int r0 = 0; r0 < p.nlat; r0 += rpb) {
+            int rb[4] = {s, b.slot_plan[s], r0, std::min(rpb, p.nlat - r0)};
+            b.rowblocks.insert(b.rowblocks.end(), rb, rb + 4);
+        }
+    }
+
+    // ---- device image ----
+    b.image.clear();
+    size_t off = 0;
+    b.off_plans = off;
+    off = align256(off + b.plans.size() * sizeof(DevPlan));
+    b.image.resize(off, 0);
+    b.off_slot_plan = off; off = put_vec(b.image, off, b.slot_plan);
+    b.off_q = off; off = put_vec(b.image, off, b.slot_q);
+    b.off_g = off; off = put_vec(b.image, off, b.slot_g);
+    b.off_f = off; off = put_vec(b.image, off, b.slot_f);
+    b.off_s = off; off = put_vec(b.image, off, b.slot_s);
+    b.off_su = off; off = put_vec(b.image, off, b.synth_units);
+    b.off_au = off; off = put_vec(b.image, off, b.analys_units);
+    b.off_rb = off; off = put_vec(b.image, off, b.rowblocks);
+    b.image.resize(off, 0);
+}
+
+template <typename T>
+T* dev_at(const shtn_batch_s& b, size_t off)
+{
+    return (T*)((char*)b.dev + off);
+}
+
+void drop_graphs(shtn_batch_s& b)
+{
+    for (auto& e : b.exec) {
+        if (e) (void)hipGraphExecDestroy(e);
+        e = nullptr;
+    }
+}
+
+int check_batch(const shtn_batch_s* b, const void* in, const void* out, const void* work)
+{
+    if (!b) return set_error(SHTN_EINVAL, "null batch");
+    if (!b->uploaded) return set_error(SHTN_ESTATE, "batch not uploaded (call shtn_batch_upload)");
+    if (!in || !out || !work) return set_error(SHTN_EINVAL, "null data or workspace pointer");
+    if (in == out) return set_error(SHTN_EINVAL, "input and output must not alias");
+    for (auto* p : b->plans)
+        if (!p->uploaded) return set_error(SHTN_ESTATE, "a plan of the batch is no longer uploaded");
+    return SHTN_OK;
+}
+
+int run_synth(const shtn_batch_s& b, const double* Q, double* grid, void* work, void* stream)
+{
+    const int ns = (int)b.slot_field.size();
+    double* F = (double*)work;
+    double* Qs = F + b.work_f_doubles;
+    const DevPlan* plans = dev_at<const DevPlan>(b, b.off_plans);
+    int e;
+    {
+        ProfScope ps(PK_PRESCALE, stream);
+        e = launch_prescale(plans, dev_at<const long>(b, b.off_q), dev_at<const long>(b, b.off_s),
+                            dev_at<const int>(b, b.off_slot_plan), Q, Qs, b.max_nlm, ns, stream);
+    }
+    if (e) return hip_error(e, "batch prescale launch");
+    LegLaunch l{};
+    l.plans = plans;
+    l.units = dev_at<const int>(b, b.off_su);
+    l.nunits = (int)(b.synth_units.size() / kUnitInts);
+    l.grid_y = 1;
+    l.q_off = dev_at<const long>(b, b.off_s);
+    l.f_off = dev_at<const long>(b, b.off_f);
+    l.in = Qs;
+    l.out = F;
+    l.nfields = ns;
+    l.adjoint = 0;
+    l.lp = b.tiling.synth_lp;
+    l.fw = b.tiling.fw;
+    l.wpg = b.synth_wpg;
+    {
+        ProfScope ps(PK_LEG_SYNTH, stream);
+        e = launch_legendre_synth(l, stream);
+    }
+    if (e) return hip_error(e, "batch legendre synthesis launch");
+    FftLaunch f{};
+    f.plans = plans;
+    f.rowblocks = dev_at<const int>(b, b.off_rb);
+    f.nblocks = (int)(b.rowblocks.size() / 4);
+    f.grid_y = 1;
+    f.g_off = dev_at<const long>(b, b.off_g);
+    f.f_off = dev_at<const long>(b, b.off_f);
+    f.in = F;
+    f.out = grid;
+    f.nfields = ns;
+    f.scale = 1.0;
+    {
+        ProfScope ps(PK_C2R, stream);
+        e = launch_c2r(f, stream);
+    }
+    if (e) return hip_error(e, "batch c2r launch");
+    return SHTN_OK;
+}
+
+int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work, void* stream)
+{
+    const int ns = (int)b.slot_field.size();
+    double* F = (double*)work;
+    const DevPlan* plans = dev_at<const DevPlan>(b, b.off_plans);
+    FftLaunch f{};
+    f.plans = plans;
+    f.rowblocks = dev_at<const int>(b, b.off_rb);
+    f.nblocks = (int)(b.rowblocks.size() / 4);
+    f.grid_y = 1;
+    f.g_off = dev_at<const long>(b, b.off_g);
+    f.f_off = dev_at<const long>(b, b.off_f);
+    f.in = grid;
+    f.out = F;
+    f.nfields = ns;
+    f.scale = 0.0;  // each field's 2 pi / nphi
+    int e;
+    {
+        ProfScope ps(PK_R2C, stream);
+        e = launch_r2c(f, stream);
+    }
+    if (e) return hip_error(e, "batch r2c launch");
+    for (const auto& c : b.classes) {
+        LegLaunch l{};
+        l.plans = plans;
+        l.units = dev_at<const int>(b, b.off_au) + c.first * kUnitInts;
+        l.nunits = c.count;
+        l.grid_y = 1;
+        l.q_off = dev_at<const long>(b, b.off_q);
+        l.f_off = dev_at<const long>(b, b.off_f);
+        l.in = F;
+        l.out = Q;
+        l.nfields = ns;
+        l.adjoint = 0;
+        l.lp = c.lp;
+        l.fw = c.fw;
+        {
+            ProfScope ps(PK_LEG_ANALYS, stream);
+            e = launch_legendre_analys(l, stream);
+        }
+        if (e) return hip_error(e, "batch legendre analysis launch");
+    }
+    return SHTN_OK;
+}
+
+int upload(shtn_batch_s& b, void* dev_buf, void* stream)
+{
+    // descriptors of the plans as uploaded (device pointers to their tables)
+    for (size_t i = 0; i < b.plans.size(); i++) {
+        const Plan& p = *b.plans[i];
+        if (!p.uploaded) return set_error(SHTN_ESTATE, "plan of the batch not uploaded");
+        DevPlan d;
+        std::memcpy(&d, p.image.data(), sizeof(DevPlan));
+        std::memcpy(b.image.data() + b.off_plans + i * sizeof(DevPlan), &d, sizeof(DevPlan));
+    }
+    hipError_t e = hipMemcpyAsync(dev_buf, b.image.data(), b.image.size(), hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error((int)e, "batch upload copy");
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_error((int)e, "batch upload sync");
+    b.dev = dev_buf;
+    b.uploaded = true;
+    drop_graphs(b);
+    return SHTN_OK;
+}
+
+int capture(shtn_batch_s& b, int which, const double* in, double* out, void* work)
+{
+    int rc = check_batch(&b, in, out, work);
+    if (rc) return rc;
+    if (which != 0 && which != 1) return set_error(SHTN_EINVAL, "which must be 0 (synthesis) or 1 (analysis)");
+    if (!b.cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&b.cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_error((int)e, "capture stream");
+    }
+    if (b.exec[which]) {
+        (void)hipGraphExecDestroy(b.exec[which]);
+        b.exec[which] = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(b.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error((int)e, "begin capture");
+    prof_set_capturing(true);
+    rc = which == 0 ? run_synth(b, in, out, work, b.cap_stream) : run_analys(b, in, out, work, b.cap_stream);
+    prof_set_capturing(false);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b.cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_error((int)e, "end capture");
+    e = hipGraphInstantiate(&b.exec[which], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b.exec[which] = nullptr;
+        return hip_error((int)e, "graph instantiate");
+    }
+    return SHTN_OK;
+}
+
+std::string cache_key(const shtn_batch_s& b)
+{
+    std::ostringstream os;
+    os << "shtn-batch-v1";
+    for (int f = 0; f < b.nfields; f++) {
+        const Plan& p = *b.field_plan[f]->p;
+        os << ' ' << p.L << ',' << p.M << ',' << p.nlat << ',' << p.nphi;
+    }
+    return os.str();
+}
+
+bool cache_lookup(const char* path, const std::string& key, BatchTiling& t)
+{
+    if (!path) return false;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.size() <= key.size() || line.compare(0, key.size(), key) != 0 || line[key.size()] != '|')
+            continue;
+        std::istringstream is(line.substr(key.size() + 1));
+        BatchTiling c;
+        if (is >> c.synth_lp >> c.fw >> c.m_pairing >> c.analys_merge) {
+            t = c;
+            return true;
+        }
+    }
+    return false;
+}
+
+int validate(const BatchTiling& t)
+{
+    if (t.synth_lp != 1 && t.synth_lp != 2 && t.synth_lp != 4)
+        return set_error(SHTN_EINVAL, "synth_lp must be 1, 2 or 4");
+    if (t.fw != 1 && t.fw != 2) return set_error(SHTN_EINVAL, "fw must be 1 or 2");
+    if (t.m_pairing != 0 && t.m_pairing != 1) return set_error(SHTN_EINVAL, "m_pairing must be 0 or 1");
+    if (t.analys_merge != 0 && t.analys_merge != 1)
+        return set_error(SHTN_EINVAL, "analys_merge must be 0 or 1");
+    return SHTN_OK;
+}
+
+}  // namespace
 
 extern "C" {
-shtn_batch_t shtn_batch(int, const shtn_plan_t*) { return nullptr; }
-void shtn_batch_destroy(shtn_batch_t) {}
-int shtn_batch_offsets(shtn_batch_t, size_t*, size_t*) { return SHTN_EUNSUPPORTED; }
-size_t shtn_batch_device_bytes(shtn_batch_t) { return 0; }
-size_t shtn_batch_work_bytes(shtn_batch_t) { return 0; }
-int shtn_batch_upload(shtn_batch_t, void*, void*) { return SHTN_EUNSUPPORTED; }
-int shtn_batch_synth(shtn_batch_t, const double*, double*, void*, void*) { return SHTN_EUNSUPPORTED; }
-int shtn_batch_analys(shtn_batch_t, const double*, double*, void*, void*) { return SHTN_EUNSUPPORTED; }
-int shtn_batch_set_tiling(shtn_batch_t, int, int, int, int) { return SHTN_EUNSUPPORTED; }
+
+shtn_batch_t shtn_batch(int nfields, const shtn_plan_t* plans)
+{
+    if (nfields < 1 || !plans) {
+        set_error(SHTN_EINVAL, "nfields must be >= 1 and plans non-null");
+        return nullptr;
+    }
+    try {
+        auto* b = new shtn_batch_s;
+        b->nfields = nfields;
+        b->field_plan.assign(plans, plans + nfields);
+        std::vector<int> fpi(nfields);
+        for (int f = 0; f < nfields; f++) {
+            if (!plans[f] || !plans[f]->p) {
+                delete b;
+                set_error(SHTN_EINVAL, "null plan in batch");
+                return nullptr;
+            }
+            Plan* p = plans[f]->p;
+            if (p->npair > kMaxAnalysPairs) {
+                delete b;
+                set_error(SHTN_EUNSUPPORTED, "batch fields support at most 1024 latitudes");
+                return nullptr;
+            }
+            auto it = std::find(b->plans.begin(), b->plans.end(), p);
+            if (it == b->plans.end()) {
+                fpi[f] = (int)b->plans.size();
+                b->plans.push_back(p);
+            } else {
+                fpi[f] = (int)(it - b->plans.begin());
+            }
+        }
+        // packed layout in user field order
+        b->q_off.assign(nfields + 1, 0);
+        b->g_off.assign(nfields + 1, 0);
+        for (int f = 0; f < nfields; f++) {
+            const Plan& p = *plans[f]->p;
+            b->q_off[f + 1] = b->q_off[f] + 2 * (size_t)p.nlm;
+            b->g_off[f + 1] = b->g_off[f] + (size_t)p.nlat * p.nphi;
+        }
+        // slots grouped by plan
+        for (size_t pi = 0; pi < b->plans.size(); pi++)
+            for (int f = 0; f < nfields; f++)
+                if (fpi[f] == (int)pi) {
+                    b->slot_field.push_back(f);
+                    b->slot_plan.push_back((int)pi);
+                }
+        // workspace: F then the rescaled spectra, per slot, 256-byte aligned
+        size_t fo = 0;
+        for (int s = 0; s < nfields; s++) {
+            const Plan& p = *b->plans[b->slot_plan[s]];
+            b->slot_q.push_back((long)b->q_off[b->slot_field[s]]);
+            b->slot_g.push_back((long)b->g_off[b->slot_field[s]]);
+            b->slot_f.push_back((long)fo);
+            fo += align256((size_t)(p.M + 1) * p.nlat * 16) / 8;
+            b->max_nlm = std::max(b->max_nlm, p.nlm);
+        }
+        b->work_f_doubles = fo;
+        size_t so = 0;
+        for (int s = 0; s < nfields; s++) {
+            const Plan& p = *b->plans[b->slot_plan[s]];
+            b->slot_s.push_back((long)so);
+            so += align256((size_t)p.nlm * 16) / 8;
+        }
+        so += 2 * (size_t)kTablePad;  // block loads may run past the last field
+        b->work_total_bytes = align256((fo + so) * 8);
+        // the largest image over the tiling space (one field per wave, one
+        // order and one pair per lane, separate analysis classes)
+        BatchTiling worst;
+        build_tables(*b, worst);
+        b->max_image = b->image.size();
+        build_tables(*b, b->tiling);
+        b->max_image = std::max(b->max_image, b->image.size());
+        return b;
+    } catch (const std::bad_alloc&) {
+        set_error(SHTN_ENOMEM, "out of host memory");
+        return nullptr;
+    } catch (...) {
+        set_error(SHTN_EINVAL, "internal error");
+        return nullptr;
+    }
 }
+
+void shtn_batch_destroy(shtn_batch_t batch)
+{
+    if (!batch) return;
+    drop_graphs(*batch);
+    if (batch->cap_stream) (void)hipStreamDestroy(batch->cap_stream);
+    delete batch;
+}
+
+int shtn_batch_offsets(shtn_batch_t batch, size_t* q_off, size_t* grid_off)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    if (q_off) std::memcpy(q_off, batch->q_off.data(), batch->q_off.size() * sizeof(size_t));
+    if (grid_off) std::memcpy(grid_off, batch->g_off.data(), batch->g_off.size() * sizeof(size_t));
+    return SHTN_OK;
+}
+
+size_t shtn_batch_device_bytes(shtn_batch_t batch) { return batch ? batch->max_image : 0; }
+
+size_t shtn_batch_work_bytes(shtn_batch_t batch) { return batch ? batch->work_total_bytes : 0; }
+
+int shtn_batch_upload(shtn_batch_t batch, void* dev_buf, void* stream)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    if (!dev_buf) return set_error(SHTN_EINVAL, "null device buffer");
+    if ((uintptr_t)dev_buf % 256) return set_error(SHTN_EINVAL, "device buffer must be 256-byte aligned");
+    return upload(*batch, dev_buf, stream);
+}
+
+int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpacked, void* work,
+                     void* stream)
+{
+    int rc = check_batch(batch, Qpacked, gridpacked, work);
+    if (rc) return rc;
+    return run_synth(*batch, Qpacked, gridpacked, work, stream);
+}
+
+int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpacked, void* work,
+                      void* stream)
+{
+    int rc = check_batch(batch, gridpacked, Qpacked, work);
+    if (rc) return rc;
+    return run_analys(*batch, gridpacked, Qpacked, work, stream);
+}
+
+int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int fw, int m_pairing, int analys_merge)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    BatchTiling t{synth_lp, fw, m_pairing, analys_merge};
+    int rc = validate(t);
+    if (rc) return rc;
+    try {
+        batch->tiling = t;
+        build_tables(*batch, t);
+    } catch (const std::bad_alloc&) {
+        return set_error(SHTN_ENOMEM, "out of host memory");
+    }
+    batch->uploaded = false;  // the unit tables changed: upload again
+    drop_graphs(*batch);
+    return SHTN_OK;
+}
+
+int shtn_batch_get_tiling(shtn_batch_t batch, int* tiling4)
+{
+    if (!batch || !tiling4) return set_error(SHTN_EINVAL, "null argument");
+    tiling4[0] = batch->tiling.synth_lp;
+    tiling4[1] = batch->tiling.fw;
+    tiling4[2] = batch->tiling.m_pairing;
+    tiling4[3] = batch->tiling.analys_merge;
+    return SHTN_OK;
+}
+
+int shtn_batch_capture(shtn_batch_t batch, int which, const double* in, double* out, void* work)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    return capture(*batch, which, in, out, work);
+}
+
+int shtn_batch_replay(shtn_batch_t batch, int which, void* stream)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    if (which != 0 && which != 1) return set_error(SHTN_EINVAL, "which must be 0 or 1");
+    if (!batch->uploaded || !batch->exec[which])
+        return set_error(SHTN_ESTATE, "no captured graph (call shtn_batch_capture after the upload)");
+    hipError_t e = hipGraphLaunch(batch->exec[which], (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error((int)e, "graph launch");
+    return SHTN_OK;
+}
+
+int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacked, double* Qout,
+                    void* work, void* stream, int reps, const char* cache_path, float* best_us)
+{
+    int rc = check_batch(batch, Qpacked, gridpacked, work);
+    if (rc) return rc;
+    if (!Qout || Qout == Qpacked || (const void*)Qout == (const void*)gridpacked)
+        return set_error(SHTN_EINVAL, "Qout must be a separate buffer");
+    if (reps < 1) reps = 10;
+    shtn_batch_s& b = *batch;
+    void* dev = b.dev;
+    const std::string key = cache_key(b);
+    BatchTiling best = b.tiling;
+    float best_t = -1.f;
+    if (!cache_lookup(cache_path, key, best)) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return hip_error((int)hipGetLastError(), "tuner events");
+        std::vector<BatchTiling> cands;
+        for (int lp : {1, 2})
+            for (int fw : {1, 2})
+                for (int mp : {0, 1})
+                    for (int merge : {0, 1}) cands.push_back(BatchTiling{lp, fw, mp, merge});
+        for (const BatchTiling& t : cands) {
+            build_tables(b, t);
+            b.tiling = t;
+            if ((rc = upload(b, dev, stream))) break;
+            if ((rc = capture(b, 0, Qpacked, gridpacked, work))) break;
+            if ((rc = capture(b, 1, gridpacked, Qout, work))) break;
+            for (int w = 0; w < 2; w++) {
+                (void)hipGraphLaunch(b.exec[0], (hipStream_t)stream);
+                (void)hipGraphLaunch(b.exec[1], (hipStream_t)stream);
+            }
+            (void)hipEventRecord(e0, (hipStream_t)stream);
+            for (int r = 0; r < reps; r++) {
+                (void)hipGraphLaunch(b.exec[0], (hipStream_t)stream);
+                (void)hipGraphLaunch(b.exec[1], (hipStream_t)stream);
+            }
+            (void)hipEventRecord(e1, (hipStream_t)stream);
+            hipError_t he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) {
+                rc = hip_error((int)he, "tuner timing");
+                break;
+            }
+            const float us = 1000.f * ms / reps;
+            if (best_t < 0.f || us < best_t) {
+                best_t = us;
+                best = t;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        if (cache_path) {
+            std::ofstream out(cache_path, std::ios::app);
+            out << key << '|' << best.synth_lp << ' ' << best.fw << ' ' << best.m_pairing << ' '
+                << best.analys_merge << '\n';
+        }
+    }
+    build_tables(b, best);
+    b.tiling = best;
+    if ((rc = upload(b, dev, stream))) return rc;
+    if ((rc = capture(b, 0, Qpacked, gridpacked, work))) return rc;
+    if ((rc = capture(b, 1, gridpacked, Qout, work))) return rc;
+    if (best_us) *best_us = best_t;
+    return SHTN_OK;
+}
+
+}  // extern "C"

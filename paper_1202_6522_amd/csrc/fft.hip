@@ -198,7 +198,8 @@ __global__ void __launch_bounds__(kFftThreads) k_r2c(FftArgs a)
     }
     __syncthreads();
     complex_fft(buf, tw, K, nr, -1);
-    const double sc = a.scale;
+    // scale <= 0: the analysis scale 2 pi / nphi of each field's plan
+    const double sc = a.scale > 0.0 ? a.scale : 2.0 * 3.14159265358979323846 / nphi;
     for (int idx = threadIdx.x; idx < nr * (M + 1); idx += kFftThreads) {
         const int r = idx % nr, m = idx / nr;
         const double2 zm = buf[r * K + m];

@@ -17,6 +17,7 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Pending> g_pending;
 double g_ms[kProfKinds] = {0};
+thread_local bool t_capturing = false;
 long g_n[kProfKinds] = {0};
 
 void drain_locked()
@@ -34,8 +35,11 @@ void drain_locked()
 }
 }  // namespace
 
+void prof_set_capturing(bool on) { t_capturing = on; }
+
 ProfScope::ProfScope(int kind, void* stream) : kind_(kind), stream_(stream)
 {
+    if (t_capturing) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
     hipEvent_t a;

@@ -109,6 +109,12 @@ struct Plan {
     bool uploaded = false;
 };
 
+// Error reporting shared by the C-ABI sources (api.cpp): sets the detail
+// string of shtn_last_error_detail and returns the code.
+int set_error(int code, const std::string& msg);
+int hip_error(int e, const char* where);
+int rows_per_block(const Plan& p);  // FFT rows per workgroup for a plan
+
 // Host plan construction (plan.cpp).
 Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err);
 int rebuild_units(Plan& p, std::string& err);     // units + restart states for the tiling
@@ -163,3 +169,8 @@ int launch_c2r(const FftLaunch& a, void* stream);
 int launch_r2c(const FftLaunch& a, void* stream);
 
 }  // namespace shtn
+
+// Opaque handle behind shtn_plan_t.
+struct shtn_plan_s {
+    shtn::Plan* p;
+};

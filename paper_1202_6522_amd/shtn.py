@@ -57,6 +57,11 @@ _SIGS = {
     "shtn_batch_synth": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "shtn_batch_analys": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "shtn_batch_set_tiling": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "shtn_batch_get_tiling": (_c.c_int, [_vp, _c.POINTER(_c.c_int)]),
+    "shtn_batch_capture": (_c.c_int, [_vp, _c.c_int, _vp, _vp, _vp]),
+    "shtn_batch_replay": (_c.c_int, [_vp, _c.c_int, _vp]),
+    "shtn_batch_tune": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c.c_int, _c.c_char_p,
+                                   _c.POINTER(_c.c_float)]),
     "shtn_profile_enable": (_c.c_int, [_c.c_int]),
     "shtn_profile_read": (_c.c_int, [_c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_long)]),
     "shtn_profile_reset": (None, []),
@@ -190,6 +195,73 @@ def shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split=0, fft_row
                                                      fft_rows), "shtn_plan_set_tiling")
 
 
+def shtn_batch(plan_handles):
+    lib = load_library()
+    arr = (_vp * len(plan_handles))(*plan_handles)
+    h = lib.shtn_batch(len(plan_handles), arr)
+    if not h:
+        raise ValueError("shtn_batch: %s" % lib.shtn_last_error_detail().decode())
+    return h
+
+
+def shtn_batch_destroy(h):
+    load_library().shtn_batch_destroy(h)
+
+
+def shtn_batch_offsets(h, nfields):
+    q = (_sz * (nfields + 1))()
+    g = (_sz * (nfields + 1))()
+    check(load_library().shtn_batch_offsets(h, q, g), "shtn_batch_offsets")
+    return list(q), list(g)
+
+
+def shtn_batch_device_bytes(h):
+    return load_library().shtn_batch_device_bytes(h)
+
+
+def shtn_batch_work_bytes(h):
+    return load_library().shtn_batch_work_bytes(h)
+
+
+def shtn_batch_upload(h, dev_ptr, stream):
+    return check(load_library().shtn_batch_upload(h, dev_ptr, stream), "shtn_batch_upload")
+
+
+def shtn_batch_synth(h, Q, grid, work, stream):
+    return check(load_library().shtn_batch_synth(h, Q, grid, work, stream), "shtn_batch_synth")
+
+
+def shtn_batch_analys(h, grid, Q, work, stream):
+    return check(load_library().shtn_batch_analys(h, grid, Q, work, stream), "shtn_batch_analys")
+
+
+def shtn_batch_set_tiling(h, synth_lp, fw, m_pairing, analys_merge):
+    return check(load_library().shtn_batch_set_tiling(h, synth_lp, fw, m_pairing, analys_merge),
+                 "shtn_batch_set_tiling")
+
+
+def shtn_batch_get_tiling(h):
+    t = (_c.c_int * 4)()
+    check(load_library().shtn_batch_get_tiling(h, t), "shtn_batch_get_tiling")
+    return list(t)
+
+
+def shtn_batch_capture(h, which, inp, out, work):
+    return check(load_library().shtn_batch_capture(h, which, inp, out, work), "shtn_batch_capture")
+
+
+def shtn_batch_replay(h, which, stream):
+    return check(load_library().shtn_batch_replay(h, which, stream), "shtn_batch_replay")
+
+
+def shtn_batch_tune(h, Q, grid, Qout, work, stream, reps=10, cache_path=None):
+    best = _c.c_float(0.0)
+    cp = cache_path.encode() if cache_path else None
+    check(load_library().shtn_batch_tune(h, Q, grid, Qout, work, stream, reps, cp, _c.byref(best)),
+          "shtn_batch_tune")
+    return best.value
+
+
 PROFILE_KINDS = {0: "prescale", 1: "legendre_synth", 2: "legendre_analys", 3: "c2r", 4: "r2c"}
 
 
@@ -250,7 +322,7 @@ class Plan:
         off = (-ptr) % 256
         shtn_plan_upload(self.handle, ptr + off, _stream_ptr(torch, self.device))
 
-    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=1, split=0, fft_rows=0):
+    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=0, split=0, fft_rows=0):
         shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, fw, m_pairing, split, fft_rows)
         self._upload()
 
@@ -335,3 +407,117 @@ class Plan:
     def analys_adj(self, h):
         """Adjoint of the analysis A^T h."""
         return self._to_grid(shtn_analys_adj, h)
+
+
+class Batch:
+    """Fields of different truncations transformed together (shtn_batch_*).
+
+    shapes: list of (lmax, mmax, nlat, nphi), one per field.  Fields sharing a
+    shape share one Plan.  Packed buffers: spectra [total_q // 2] complex128,
+    grids [total_grid] float64, fields back to back in the given order.
+    """
+
+    def __init__(self, shapes, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.plans = {}
+        for s in self.shapes:
+            if s not in self.plans:
+                self.plans[s] = Plan(*s, device=self.device)
+        self.handle = shtn_batch([self.plans[s].handle for s in self.shapes])
+        self.q_off, self.g_off = shtn_batch_offsets(self.handle, len(self.shapes))
+        self._dev = torch.empty(shtn_batch_device_bytes(self.handle) + 256, dtype=torch.uint8,
+                                device=self.device)
+        self._work = torch.empty(shtn_batch_work_bytes(self.handle) + 256, dtype=torch.uint8,
+                                 device=self.device)
+        self.upload()
+
+    @staticmethod
+    def _aligned(t):
+        return t.data_ptr() + ((-t.data_ptr()) % 256)
+
+    def _stream(self):
+        import torch
+        return _stream_ptr(torch, self.device)
+
+    def upload(self):
+        shtn_batch_upload(self.handle, self._aligned(self._dev), self._stream())
+
+    def set_tiling(self, synth_lp=1, fw=1, m_pairing=0, analys_merge=0):
+        shtn_batch_set_tiling(self.handle, synth_lp, fw, m_pairing, analys_merge)
+        self.upload()
+
+    def tiling(self):
+        t = shtn_batch_get_tiling(self.handle)
+        return dict(synth_lp=t[0], fw=t[1], m_pairing=t[2], analys_merge=t[3])
+
+    @property
+    def work(self):
+        return self._aligned(self._work)
+
+    def new_spectra(self):
+        import torch
+        return torch.zeros(self.q_off[-1] // 2, dtype=torch.complex128, device=self.device)
+
+    def new_grids(self):
+        import torch
+        return torch.zeros(self.g_off[-1], dtype=torch.float64, device=self.device)
+
+    def pack_spectra(self, specs):
+        """List of per-field [nlm] complex arrays/tensors -> packed tensor."""
+        import torch
+        out = self.new_spectra()
+        for f, q in enumerate(specs):
+            q = torch.as_tensor(q).to(self.device)
+            out[self.q_off[f] // 2:self.q_off[f + 1] // 2] = q.reshape(-1)
+        return out
+
+    def field_spectrum(self, Qp, f):
+        return Qp[self.q_off[f] // 2:self.q_off[f + 1] // 2]
+
+    def field_grid(self, gp, f):
+        _, _, nlat, nphi = self.shapes[f]
+        return gp[self.g_off[f]:self.g_off[f + 1]].view(nlat, nphi)
+
+    def _check(self, t, n, dtype):
+        import torch
+        if t.dtype != dtype or t.device.type != "cuda" or t.numel() != n or not t.is_contiguous():
+            raise ValueError("expected a contiguous %s CUDA tensor of %d elements" % (dtype, n))
+
+    def synth(self, Qp, out=None):
+        import torch
+        self._check(Qp, self.q_off[-1] // 2, torch.complex128)
+        out = self.new_grids() if out is None else out
+        self._check(out, self.g_off[-1], torch.float64)
+        shtn_batch_synth(self.handle, Qp.data_ptr(), out.data_ptr(), self.work, self._stream())
+        return out
+
+    def analys(self, gp, out=None):
+        import torch
+        self._check(gp, self.g_off[-1], torch.float64)
+        out = self.new_spectra() if out is None else out
+        self._check(out, self.q_off[-1] // 2, torch.complex128)
+        shtn_batch_analys(self.handle, gp.data_ptr(), out.data_ptr(), self.work, self._stream())
+        return out
+
+    def capture(self, which, inp, out):
+        """Captures one direction (0 synthesis, 1 analysis) for these buffers."""
+        shtn_batch_capture(self.handle, which, inp.data_ptr(), out.data_ptr(), self.work)
+
+    def replay(self, which):
+        shtn_batch_replay(self.handle, which, self._stream())
+
+    def tune(self, Qp, gp, Qout, reps=10, cache_path=None):
+        """Autotunes the tiling on these buffers; leaves both graphs captured."""
+        return shtn_batch_tune(self.handle, Qp.data_ptr(), gp.data_ptr(), Qout.data_ptr(),
+                               self.work, self._stream(), reps, cache_path)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                shtn_batch_destroy(h)
+            except Exception:
+                pass
+            self.handle = None

@@ -433,3 +433,42 @@ def test_polar_cut_drops_only_negligible_latitudes():
             assert Pm[:, 1].max() >= 2.0**-201, m      # first kept pair: at the threshold
     finally:
         S.shtn_plan_destroy(h)
+
+
+def test_batch_layout_and_state_errors(lib):
+    shapes = [(63, 63, 64, 128), (31, 31, 32, 64), (63, 63, 64, 128), (20, 10, 25, 32)]
+    hs = {}
+    for s in shapes:
+        if s not in hs:
+            hs[s] = S.shtn_plan(*s)
+    try:
+        b = S.shtn_batch([hs[s] for s in shapes])
+        try:
+            q, g = S.shtn_batch_offsets(b, len(shapes))
+            nq = [2 * inputs.nlm(L, M) for (L, M, _, _) in shapes]
+            ng = [nlat * nphi for (_, _, nlat, nphi) in shapes]
+            assert q == [0] + list(np.cumsum(nq))
+            assert g == [0] + list(np.cumsum(ng))
+            assert S.shtn_batch_device_bytes(b) > 0
+            assert S.shtn_batch_work_bytes(b) >= 8 * (q[-1] + sum(
+                2 * (M + 1) * nlat for (_, M, nlat, _) in shapes))
+            assert S.shtn_batch_get_tiling(b) == [1, 1, 0, 0]
+            # nothing uploaded: every device call is refused before any HIP call
+            fake = ctypes.c_void_p(4096)
+            assert lib.shtn_batch_synth(b, fake, ctypes.c_void_p(8192), fake, None) == S.SHTN_ESTATE
+            assert lib.shtn_batch_analys(b, fake, ctypes.c_void_p(8192), fake, None) == S.SHTN_ESTATE
+            assert lib.shtn_batch_capture(b, 0, fake, ctypes.c_void_p(8192), fake) == S.SHTN_ESTATE
+            assert lib.shtn_batch_replay(b, 0, None) == S.SHTN_ESTATE
+            assert lib.shtn_batch_upload(b, ctypes.c_void_p(4097), None) == S.SHTN_EINVAL
+            for bad in [(3, 1, 0, 0), (1, 3, 0, 0), (1, 1, 2, 0), (1, 1, 0, 2)]:
+                assert lib.shtn_batch_set_tiling(b, *bad) == S.SHTN_EINVAL
+            S.shtn_batch_set_tiling(b, 2, 2, 1, 1)
+            assert S.shtn_batch_get_tiling(b) == [2, 2, 1, 1]
+        finally:
+            S.shtn_batch_destroy(b)
+        assert not lib.shtn_batch(0, None)
+        with pytest.raises(ValueError):
+            S.shtn_batch([hs[shapes[0]], None])
+    finally:
+        for h in hs.values():
+            S.shtn_plan_destroy(h)
