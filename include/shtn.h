@@ -54,10 +54,15 @@ typedef struct shtn_plan_s* shtn_plan_t;
  * the analysis exact, Sec. 2.3), nphi equispaced longitudes with nphi > 2 mmax
  * and nphi a power of two.  Computes the Gauss nodes and weights (Sec. 2.3,
  * eq. gauss), the recurrence tables of Sec. 3.2 (eq. rec) in the rescaled form
- * used by the kernels, the P_m^m start values with their scaled exponents
- * (Sec. 3.5), the restart states that split long orders into balanced work
- * units, the FFT twiddles and the work-unit lists.  Returns NULL on error
- * (see shtn_last_error_detail). */
+ * used by the kernels, and -- by following every (order, latitude) recurrence
+ * from P_m^m in a scaled-exponent form, the underflow guard of Sec. 3.5 run
+ * at plan time -- the step at which each latitude's |P_n^m| first reaches
+ * 2^-200 together with the recurrence state there.  The kernels start each
+ * latitude at that step (before it every term is below 2^-200 and is dropped:
+ * the polar optimisation of Sec. 3.1) and skip the steps in which no latitude
+ * of a wave has started.  Also the restart states that split long orders into
+ * balanced work units, the FFT twiddles and the work-unit lists.  Returns
+ * NULL on error (see shtn_last_error_detail). */
 shtn_plan_t shtn_plan(int lmax, int mmax, int nlat, int nphi);
 void shtn_plan_destroy(shtn_plan_t plan); /* NULL is ignored */
 
@@ -115,20 +120,25 @@ double shtn_legendre_flops(shtn_plan_t plan);
 /* Copies a host-side plan table for inspection (tests, tools).
  * which: 0 x per pair, 1 sin(theta) per pair, 2 weight per pair (the middle
  * node of an odd grid carries half its weight), 3 beta (nlm), 4 gamma (nlm),
- * 5 start mantissa ((mmax+1) x npair), 6 start exponent (int32, same shape),
- * 7 segment exponent shifts (int32), 8 segment offsets per m (int32, mmax+2),
- * 9 restart states (double, nrestart x npair x 2), 10 restart exponents
- * (int32, nrestart x npair), 11 analysis units (int32 x 8 each),
- * 12 synthesis units (int32 x 8 each), 13 tiling (int32 x 8: synth_lp,
- * analys_lp, fw, m_pairing, split, fft_rows, segment length, guard unit),
- * 14 first latitude pair kept by the static polar cut, per m (int32).
+ * 5 P_m^m start mantissa ((mmax+1) x npair), 6 its scaled exponent k (int32,
+ * same shape; value = mantissa 2^{-256 k}), 7 segment exponent shifts
+ * (int32), 8 segment offsets per m (int32, mmax+2), 9 analysis restart
+ * states (double, nrestart x npair x 2), 10 empty (kept for numbering),
+ * 11 analysis units (int32 x 12 each), 12 synthesis units (int32 x 12 each),
+ * 13 tiling (int32 x 8: synth_lp, analys_lp, fw, m_pairing, split, fft_rows,
+ * segment length, start checkpoint spacing), 14 first latitude pair that
+ * ever reaches the polar threshold, per m (int32), 15 start step of every
+ * (order, pair) lane (int32, (mmax+1) x npair; lmax-m+1 = never), 16 the
+ * recurrence state entering that step (double, (mmax+1) x npair x 2).
  * Returns the table size in bytes; copies only if dst != NULL and
  * bytes >= size.  Negative on error. */
 long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
 
 /* Tiling of the Legendre kernels (the runtime-tuning knob of Sec. 3.2):
  * synth_lp (1, 2, 4) / analys_lp (1, 2, 4, 8) latitude pairs per lane, fields per
- * wave fw (1, 2; fw = 2 needs lp <= 4), m_pairing (0/1: one wave takes orders m and mmax-m),
+ * wave fw (1, 2; fw = 2 needs lp <= 4), m_pairing (synthesis: 0 one workgroup per
+ * order, 1 orders m and mmax-m share a workgroup so that all workgroups carry
+ * equal work),
  * split (analysis n-range piece length, a multiple of 32; 0 = automatic),
  * fft_rows (latitude rows per FFT workgroup, 0 = automatic).
  * Rebuilds the unit lists and restart tables: re-upload afterwards.
@@ -176,10 +186,11 @@ int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpack
 int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpacked, void* work,
                       void* stream);
 /* Tiling of the whole batch: synth_lp (1, 2, 4) latitude pairs per synthesis
- * lane; fw (1, 2) fields of the same plan per wave; m_pairing (0, 1) orders
- * m and M-m in one synthesis wave; analys_merge (0, 1): 0 launches the
- * Legendre analysis once per latitude-pair class (64, 128, 256, 512 pairs),
- * 1 launches it once with the largest class.  Re-upload afterwards. */
+ * lane; fw (1, 2) fields of the same plan per wave; m_pairing (0, 1):
+ * synthesis units in longest-first order, or long and short units
+ * alternating; analys_merge (0, 1): 0 launches the Legendre analysis once per
+ * latitude-pair class (64, 128, 256, 512 pairs), 1 launches it once with the
+ * largest class.  Re-upload afterwards. */
 int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int fw, int m_pairing, int analys_merge);
 /* tiling4 = {synth_lp, fw, m_pairing, analys_merge}. */
 int shtn_batch_get_tiling(shtn_batch_t batch, int* tiling4);

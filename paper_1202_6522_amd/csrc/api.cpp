@@ -50,14 +50,6 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 const DevPlan* dplan(const Plan& p) { return (const DevPlan*)p.dev; }
 const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.dev + p.table_off[t]); }
 
-// Latitude blocks of the same orders share a workgroup (and its scalar cache).
-int synth_wpg(const Plan& p)
-{
-    const int blk = 64 * p.tiling.synth_lp;
-    const int nblk = (p.npair + blk - 1) / blk;
-    return nblk <= 8 ? nblk : 1;
-}
-
 int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, const void* work)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
@@ -86,7 +78,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     if (e) return hip_fail(e, "prescale launch");
     LegLaunch l{};
     l.plans = dplan(p);
-    l.units = dev_table_int(p, 13);
+    l.units = dev_table_int(p, TB_SYNTH_UNITS);
     l.nunits = (int)(p.synth_units.size() / kUnitInts);
     l.grid_y = (nfields + p.tiling.fw - 1) / p.tiling.fw;
     l.in = Qs;
@@ -95,7 +87,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     l.adjoint = adjoint;
     l.lp = p.tiling.synth_lp;
     l.fw = p.tiling.fw;
-    l.wpg = synth_wpg(p);
+    l.wpg = p.synth_wpg;
     {
         ProfScope ps(PK_LEG_SYNTH, stream);
         e = launch_legendre_synth(l, stream);
@@ -147,7 +139,7 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     if (e) return hip_fail(e, "r2c launch");
     LegLaunch l{};
     l.plans = dplan(p);
-    l.units = dev_table_int(p, 14);
+    l.units = dev_table_int(p, TB_ANALYS_UNITS);
     l.nunits = (int)(p.analys_units.size() / kUnitInts);
     l.grid_y = (nfields + p.tiling.fw - 1) / p.tiling.fw;
     l.in = F;
@@ -226,22 +218,21 @@ int shtn_plan_upload(shtn_plan_t plan, void* dev_buf, void* stream)
     Plan& p = *plan->p;
     char* base = (char*)dev_buf;
     DevPlan d{};
-    int t = 0;
-    d.xp = (const double*)(base + p.table_off[t++]);
-    d.wq = (const double*)(base + p.table_off[t++]);
-    d.wfull = (const double*)(base + p.table_off[t++]);
-    d.beta = (const double*)(base + p.table_off[t++]);
-    d.gamma = (const double*)(base + p.table_off[t++]);
-    d.start_y = (const double*)(base + p.table_off[t++]);
-    d.start_k = (const int*)(base + p.table_off[t++]);
-    d.segexp = (const int*)(base + p.table_off[t++]);
-    d.segoff = (const int*)(base + p.table_off[t++]);
-    d.rst_y = (const double*)(base + p.table_off[t++]);
-    d.rst_k = (const int*)(base + p.table_off[t++]);
-    d.tw = (const double*)(base + p.table_off[t++]);
-    d.rtw = (const double*)(base + p.table_off[t++]);
-    d.synth_units = (const int*)(base + p.table_off[t++]);
-    d.analys_units = (const int*)(base + p.table_off[t++]);
+    auto at = [&](int tb) { return (const void*)(base + p.table_off[tb]); };
+    d.xp = (const double*)at(TB_XP);
+    d.wq = (const double*)at(TB_WQ);
+    d.wfull = (const double*)at(TB_WFULL);
+    d.beta = (const double*)at(TB_BETA);
+    d.gamma = (const double*)at(TB_GAMMA);
+    d.inj_j = (const int*)at(TB_INJ_J);
+    d.inj_y = (const double*)at(TB_INJ_Y);
+    d.segexp = (const int*)at(TB_SEGEXP);
+    d.segoff = (const int*)at(TB_SEGOFF);
+    d.rst_y = (const double*)at(TB_RST_Y);
+    d.tw = (const double*)at(TB_TW);
+    d.rtw = (const double*)at(TB_RTW);
+    d.synth_units = (const int*)at(TB_SYNTH_UNITS);
+    d.analys_units = (const int*)at(TB_ANALYS_UNITS);
     d.L = p.L;
     d.M = p.M;
     d.nlat = p.nlat;
@@ -329,7 +320,7 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     const void* src = nullptr;
     size_t n = 0;
     int tiling[8] = {p.tiling.synth_lp, p.tiling.analys_lp, p.tiling.fw, p.tiling.m_pairing,
-                     p.split_used, rows_per_block(p), kSegLen, kGuardUnit};
+                     p.split_used, rows_per_block(p), kSegLen, kInject};
     switch (which) {
     case 0: src = p.xp.data(); n = p.xp.size() * 8; break;
     case 1: src = p.sp.data(); n = p.sp.size() * 8; break;
@@ -341,11 +332,13 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     case 7: src = p.segexp.data(); n = p.segexp.size() * 4; break;
     case 8: src = p.segoff.data(); n = p.segoff.size() * 4; break;
     case 9: src = p.rst_y.data(); n = p.rst_y.size() * 8; break;
-    case 10: src = p.rst_k.data(); n = p.rst_k.size() * 4; break;
+    case 10: src = nullptr; n = 0; break;  // no longer used (restart states carry no exponent)
     case 11: src = p.analys_units.data(); n = p.analys_units.size() * 4; break;
     case 12: src = p.synth_units.data(); n = p.synth_units.size() * 4; break;
     case 13: src = tiling; n = sizeof(tiling); break;
     case 14: src = p.first_pair.data(); n = p.first_pair.size() * 4; break;
+    case 15: src = p.inj_j.data(); n = p.inj_j.size() * 4; break;
+    case 16: src = p.inj_y.data(); n = p.inj_y.size() * 8; break;
     default: return fail(SHTN_EINVAL, "unknown table");
     }
     if (dst && bytes >= n && n) std::memcpy(dst, src, n);
@@ -365,13 +358,14 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, 
     if (fw == 2 && analys_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs analys_lp <= 4");
     if (64 * analys_lp < p.npair && p.npair <= kMaxAnalysPairs)
         return fail(SHTN_EINVAL, "analys_lp too small: one analysis wave must cover all latitude pairs");
+    if (m_pairing < 0 || m_pairing > 1) return fail(SHTN_EINVAL, "m_pairing must be 0 or 1");
     if (split < 0 || split % kSegLen) return fail(SHTN_EINVAL, "split must be a multiple of 32");
     if (fft_rows < 0) return fail(SHTN_EINVAL, "fft_rows must be >= 0");
     Tiling old = p.tiling;
     p.tiling.synth_lp = synth_lp;
     p.tiling.analys_lp = analys_lp;
     p.tiling.fw = fw;
-    p.tiling.m_pairing = m_pairing ? 1 : 0;
+    p.tiling.m_pairing = m_pairing;
     p.tiling.split = split;
     p.tiling.fft_rows = fft_rows;
     std::string err;

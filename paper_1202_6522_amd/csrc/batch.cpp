@@ -33,7 +33,7 @@ namespace {
 struct BatchTiling {
     int synth_lp = 1;      // latitude pairs per synthesis lane (block of 64 lp pairs per wave)
     int fw = 1;            // fields per wave (fields of the same plan)
-    int m_pairing = 0;     // synthesis: orders m and M-m in one wave
+    int m_pairing = 0;     // synthesis unit order: 1 = long and short units alternate
     int analys_merge = 0;  // analysis: 1 = a single launch at the largest pairs-per-lane class
 };
 
@@ -121,28 +121,36 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
         for (int fg = range[pi].first; fg < range[pi].second; fg += t.fw) {
             const int nf = std::min(t.fw, range[pi].second - fg);
             for (int m = 0; m <= p.M; m++) {
-                int m2 = -1;
-                if (t.m_pairing) {
-                    m2 = p.M - m;
-                    if (m > m2) break;
-                    if (m2 == m) m2 = -1;
-                }
-                const long cost = (long)(p.L - m + 1) + (m2 >= 0 ? (long)(p.L - m2 + 1) : 0);
+                const int nj = p.L - m + 1;
                 for (int k = 0; k < nblk; k++) {
-                    const int bend = std::min((k + 1) * blk, p.npair);
-                    int flags = 0;
-                    if (bend <= p.first_pair[m]) flags |= 1;
-                    if (m2 >= 0 && bend <= p.first_pair[m2]) flags |= 2;
-                    SU x{cost * t.synth_lp * nf, {fg, nf, (int)pi, m, m2, k * blk, 0, flags}};
+                    int jmin, jmax;
+                    SU x{0, {fg, nf, (int)pi, m, 0, 0, k * blk, 0, -1, 0, 0, 0}};
+                    if (start_range(p, m, k * blk, std::min((k + 1) * blk, p.npair), 0, nj, jmin, jmax)) {
+                        x.u[U_JS] = jmin;
+                        x.u[U_JW] = jmax;
+                        x.cost = (long)(nj - jmin) * t.synth_lp * nf;
+                    } else {
+                        x.u[U_ZERO] = 1;
+                    }
                     su.push_back(x);
                 }
             }
         }
     }
+    // longest first; with m_pairing, long and short units alternate instead
     std::stable_sort(su.begin(), su.end(), [](const SU& a, const SU& c) { return a.cost > c.cost; });
+    if (t.m_pairing) {
+        std::vector<SU> alt;
+        alt.reserve(su.size());
+        for (size_t lo = 0, hi = su.size(); lo < hi;) {
+            alt.push_back(su[lo++]);
+            if (lo < hi) alt.push_back(su[--hi]);
+        }
+        su.swap(alt);
+    }
     b.synth_units.clear();
     for (auto& x : su) b.synth_units.insert(b.synth_units.end(), x.u, x.u + kUnitInts);
-    b.synth_wpg = std::min(8, maxblk);
+    b.synth_wpg = std::min(t.synth_lp == 1 && t.fw == 1 ? 16 : 8, maxblk);
 
     // ---- analysis units, per pairs-per-lane class ----
     int lp_max = 1;
@@ -172,8 +180,11 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
                 const size_t nu = p.analys_units.size() / kUnitInts;
                 for (size_t i = 0; i < nu; i++) {
                     const int* pu = &p.analys_units[i * kUnitInts];
-                    SU x{(long)(pu[U_J1] - pu[U_PB]) * nf,
-                         {fg, nf, (int)pi, pu[U_M0], -1, pu[U_PB], pu[U_J1], pu[U_RST]}};
+                    SU x{(long)(pu[U_J1] - pu[U_JS] + 4) * nf, {}};
+                    std::copy(pu, pu + kUnitInts, x.u);
+                    x.u[U_FIELD] = fg;
+                    x.u[U_NF] = nf;
+                    x.u[U_PLAN] = (int)pi;
                     au.push_back(x);
                 }
             }

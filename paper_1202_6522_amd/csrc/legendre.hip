@@ -4,7 +4,10 @@
 // with P_n^m generated on the fly by the three-term recurrence of Sec. 3.2
 // (eq. rec), the equatorial mirror symmetry of Sec. 3.1 folded in (one lane
 // carries the pair of latitudes x and -x: even degrees n-m add, odd degrees
-// subtract), and the scaled-exponent underflow guard of Sec. 3.5.
+// subtract), and the underflow guard of Sec. 3.5 with the polar threshold of
+// Sec. 3.1 resolved at plan time: every lane starts at the step where its
+// |P_n^m| first matters, from a state stored by the plan, and a wave skips
+// the steps in which none of its lanes has started.
 //
 // The recurrence runs in the rescaled form u_n = x u_{n-1} + beta_n u_{n-2}
 // (two FP64 operations per step: one multiply by an SGPR coefficient and one
@@ -96,13 +99,61 @@ typedef const __attribute__((address_space(4))) D8* cd8p;
 typedef const __attribute__((address_space(4))) D16* cd16p;
 
 // ---------------------------------------------------------------------------
+// Lane starts (shared by both directions).
+// ---------------------------------------------------------------------------
+// Per lane and pair: the step at which the lane starts and the state
+// (u_{j-2}, u_{j-1}) entering it; before that step the lane holds 0.
+template <int LP>
+struct Starts {
+    int j[LP];
+    double ya[LP], yb[LP];
+};
+
+template <int LP>
+__device__ __forceinline__ void load_starts(Starts<LP>& st, cplan P, int m, int pb, int nj)
+{
+    const int lane = threadIdx.x & 63;
+    const int npair = P->npair;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        const int pair = pb + p * 64 + lane;
+        const bool act = pair < npair;
+        const size_t q = (size_t)m * npair + (act ? pair : 0);
+        const double2 y = *(const double2*)(P->inj_y + 2 * q);
+        st.j[p] = act ? P->inj_j[q] : nj;
+        st.ya[p] = y.x;
+        st.yb[p] = y.y;
+    }
+}
+
+// Lanes whose start step is j take their stored state (a select per state).
+template <int LP>
+__device__ __forceinline__ void start_lanes(double (&ua)[LP], double (&ub)[LP], const Starts<LP>& st, int j)
+{
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        const bool go = st.j[p] == j;
+        ua[p] = go ? st.ya[p] : ua[p];
+        ub[p] = go ? st.yb[p] : ub[p];
+    }
+}
+
+template <int LP>
+__device__ __forceinline__ void rescale(double (&ua)[LP], double (&ub)[LP], int sh)
+{
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        ua[p] = __builtin_amdgcn_ldexp(ua[p], sh);
+        ub[p] = __builtin_amdgcn_ldexp(ub[p], sh);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Synthesis: F_m(theta) for one order, LP pairs per lane, FW fields.
 // ---------------------------------------------------------------------------
 template <int LP, int FW>
 struct SynthState {
     double x[LP], ua[LP], ub[LP];
-    int k[LP];
-    double z[LP];  // 1 while the lane's value is live (k == 0), 0 while scaled
     double er[LP][FW], ei[LP][FW], orr[LP][FW], oi[LP][FW];
 };
 
@@ -128,9 +179,8 @@ __device__ __forceinline__ void load_block(SBlock<FW>& B, cdp bet, const cdp (&q
 }
 
 // Step t of a block (degree offset j + t).  Even t advance ua and feed the
-// even (E) sums, odd t advance ub and feed the odd (O) sums.  MASKED
-// multiplies the value by the lane's live flag z.
-template <bool MASKED, int LP, int FW>
+// even (E) sums, odd t advance ub and feed the odd (O) sums.
+template <int LP, int FW>
 __device__ __forceinline__ void synth_step(SynthState<LP, FW>& s, const SBlock<FW>& B, int t)
 {
     const double b = B.b.v[t];
@@ -139,11 +189,10 @@ __device__ __forceinline__ void synth_step(SynthState<LP, FW>& s, const SBlock<F
         for (int p = 0; p < LP; p++) s.ua[p] = fma(s.x[p], s.ub[p], b * s.ua[p]);
 #pragma unroll
         for (int p = 0; p < LP; p++) {
-            const double v = MASKED ? s.ua[p] * s.z[p] : s.ua[p];
 #pragma unroll
             for (int f = 0; f < FW; f++) {
-                s.er[p][f] = fma(B.q[f].v[2 * t], v, s.er[p][f]);
-                s.ei[p][f] = fma(B.q[f].v[2 * t + 1], v, s.ei[p][f]);
+                s.er[p][f] = fma(B.q[f].v[2 * t], s.ua[p], s.er[p][f]);
+                s.ei[p][f] = fma(B.q[f].v[2 * t + 1], s.ua[p], s.ei[p][f]);
             }
         }
     } else {
@@ -151,59 +200,48 @@ __device__ __forceinline__ void synth_step(SynthState<LP, FW>& s, const SBlock<F
         for (int p = 0; p < LP; p++) s.ub[p] = fma(s.x[p], s.ua[p], b * s.ub[p]);
 #pragma unroll
         for (int p = 0; p < LP; p++) {
-            const double v = MASKED ? s.ub[p] * s.z[p] : s.ub[p];
 #pragma unroll
             for (int f = 0; f < FW; f++) {
-                s.orr[p][f] = fma(B.q[f].v[2 * t], v, s.orr[p][f]);
-                s.oi[p][f] = fma(B.q[f].v[2 * t + 1], v, s.oi[p][f]);
+                s.orr[p][f] = fma(B.q[f].v[2 * t], s.ub[p], s.orr[p][f]);
+                s.oi[p][f] = fma(B.q[f].v[2 * t + 1], s.ub[p], s.oi[p][f]);
             }
         }
     }
 }
 
 // Four steps; `lim` = number of valid steps (4 for a full block).
-template <bool MASKED, int LP, int FW>
+template <int LP, int FW>
 __device__ __forceinline__ void synth_block4(SynthState<LP, FW>& s, const SBlock<FW>& B, int lim)
 {
 #pragma unroll
     for (int t = 0; t < 4; t++)
-        if (t < lim) synth_step<MASKED>(s, B, t);
+        if (t < lim) synth_step(s, B, t);
 }
 
-// Guard check (every kGuardEvery degrees): a scaled lane whose value reached
-// 1 is brought down by 2^-256 and its exponent decremented; z follows k.
+// Eight steps from j (bounded by nj).
 template <int LP, int FW>
-__device__ __forceinline__ bool guard_check(SynthState<LP, FW>& s)
+__device__ __forceinline__ void synth_block8(SynthState<LP, FW>& s, cdp bet, const cdp (&qs)[FW], int j, int nj)
 {
-    const double down = 0x1p-256;
-    bool any = false;
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        if (s.k[p] > 0 && (fabs(s.ua[p]) >= 1.0 || fabs(s.ub[p]) >= 1.0)) {
-            s.ua[p] *= down;
-            s.ub[p] *= down;
-            s.k[p] -= 1;
-            s.z[p] = s.k[p] ? 0.0 : 1.0;
-        }
-        any |= s.k[p] > 0;
-    }
-    return wave_any(any);
-}
-
-template <int LP, int FW>
-__device__ __forceinline__ void rescale(SynthState<LP, FW>& s, int sh)
-{
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        s.ua[p] = __builtin_amdgcn_ldexp(s.ua[p], sh);
-        s.ub[p] = __builtin_amdgcn_ldexp(s.ub[p], sh);
+    SBlock<FW> b0, b1;
+    load_block(b0, bet, qs, j);
+    load_block(b1, bet, qs, j + 4);
+    if (j + 8 <= nj) {
+        synth_block4(s, b0, 4);
+        synth_block4(s, b1, 4);
+    } else {
+        synth_block4(s, b0, nj - j);
+        if (j + 4 < nj) synth_block4(s, b1, nj - j - 4);
     }
 }
 
-// One wave per unit; a workgroup holds `wpg` consecutive units (the latitude
-// blocks of the same orders), which then share scalar-cache lines.
+// One wave per unit; a workgroup holds `wpg` consecutive units: the latitude
+// blocks of one order (they share scalar-cache lines), or of the orders m and
+// M-m together so that every workgroup carries the same work.
 template <int LP, int FW>
-__global__ void __launch_bounds__(512) k_legendre_synth(LegArgs a)
+constexpr int synth_max_threads() { return LP == 1 && FW == 1 ? 1024 : 512; }
+
+template <int LP, int FW>
+__global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synth(LegArgs a)
 {
     // wave-uniform for the compiler, so unit data and coefficients stay in SGPRs
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -211,14 +249,16 @@ __global__ void __launch_bounds__(512) k_legendre_synth(LegArgs a)
     const int unit = blockIdx.x * a.wpg + wave;
     if (unit >= a.nunits) return;
     cip U = (cip)a.units + (size_t)unit * kUnitInts;
+    const int m = U[U_M];
+    if (m < 0) return;
     const int field0 = U[U_FIELD] + blockIdx.y * FW;
     if (field0 >= a.nfields) return;
     const int nf = min(U[U_NF], a.nfields - field0);
     cplan P = (cplan)a.plans + U[U_PLAN];
-    const int L = P->L, M = P->M, nlat = P->nlat, npair = P->npair;
+    const int L = P->L, nlat = P->nlat, npair = P->npair;
     const long nlm = P->nlm;
+    const int M = P->M;
     const int pb = U[U_PB];
-
     long qoff[FW];
     long foff[FW];
 #pragma unroll
@@ -227,168 +267,135 @@ __global__ void __launch_bounds__(512) k_legendre_synth(LegArgs a)
         qoff[f] = field_q_off(a, ff, nlm);
         foff[f] = field_f_off(a, ff, M, nlat);
     }
-    unsigned sink = 0;  // prefetched words; consumed once at the end
 
-    for (int pass = 0; pass < 2; pass++) {
-        const int m = pass == 0 ? U[U_M0] : U[U_M1];
-        if (m < 0) break;
-        if ((U[U_RST] >> pass) & 1) {
-            // block entirely inside the polar cut of this order: F_m = 0 there
-#pragma unroll
-            for (int p = 0; p < LP; p++) {
-                const int pair = pb + p * 64 + lane;
-                if (pair >= npair) continue;
-                const int is = nlat - 1 - pair;
-#pragma unroll
-                for (int f = 0; f < FW; f++) {
-                    if (f >= nf) continue;
-                    double* F = a.out + foff[f] + 2 * ((size_t)m * nlat);
-                    *(double2*)(F + 2 * pair) = make_double2(0.0, 0.0);
-                    *(double2*)(F + 2 * is) = make_double2(0.0, 0.0);
-                }
-            }
-            continue;
-        }
-        const long base = (long)m * (2 * L + 1 - m) / 2 + m;
-        const int nj = L - m + 1;
-        cdp bet = (cdp)P->beta + base;
-        cdp qs[FW];
-#pragma unroll
-        for (int f = 0; f < FW; f++) qs[f] = (cdp)(a.in + qoff[f]) + 2 * base;
-        cip segexp = (cip)P->segexp + ((cip)P->segoff)[m];
-
-        SynthState<LP, FW> s;
-        bool any = false;
-#pragma unroll
-        for (int p = 0; p < LP; p++) {
-            const int pair = pb + p * 64 + lane;
-            const bool act = pair < npair;
-            const int pc = act ? pair : 0;
-            s.x[p] = act ? P->xp[pc] : 0.0;
-            s.ua[p] = act ? P->start_y[(size_t)m * npair + pc] : 0.0;
-            s.ub[p] = 0.0;
-            s.k[p] = act ? P->start_k[(size_t)m * npair + pc] : 0;
-            s.z[p] = s.k[p] ? 0.0 : 1.0;
-            any |= s.k[p] > 0;
-#pragma unroll
-            for (int f = 0; f < FW; f++) s.er[p][f] = s.ei[p][f] = s.orr[p][f] = s.oi[p][f] = 0.0;
-        }
-        bool guard = wave_any(any);
-
-        // Warm L2 with this order's beta and spectrum: the workgroup's lanes
-        // touch one word per 64-byte line with vector loads into registers
-        // that are consumed only after the order is done.  They are issued
-        // after the start values above have arrived and no other vector load
-        // follows before the end, so no wave waits on them (the scalar loads
-        // are counted apart).  The scalar loads of the segments then find
-        // these lines in L2.
-        __builtin_amdgcn_sched_barrier(0);
-        unsigned pf[kPrefetchSlots];
-        {
-            const int nthr = a.wpg * 64;
-            const int gi = wave * 64 + lane;
-            const int lb = (nj * 8 + 63) / 64;   // beta lines
-            const int lq = (nj * 16 + 63) / 64;  // spectrum lines per field
-            const char* pb = (const char*)(P->beta + base);
-#pragma unroll
-            for (int k = 0; k < kPrefetchSlots; k++) {
-                int li = gi + k * nthr;
-                const char* addr = pb;
-                if (li < lb) {
-                    addr = pb + li * 64;
-                } else {
-                    li -= lb;
-#pragma unroll
-                    for (int f = 0; f < FW; f++) {
-                        if (li >= 0 && li < lq) addr = (const char*)(a.in + qoff[f] + 2 * base) + li * 64;
-                        li -= lq;
-                    }
-                }
-                pf[k] = *(const unsigned*)addr;
-            }
-        }
-
-        // One segment (kSegLen degrees) per iteration.  The segment rescale is
-        // applied unconditionally (segment 0 has shift 0): a branch here is
-        // if-converted by the compiler into selects on every block.
-        for (int js = 0; js < nj; js += kSegLen) {
-            const int je = min(js + kSegLen, nj);
-            rescale(s, segexp[js / kSegLen]);
-            if (guard) {
-                // some lanes still carry scaled (negligible) values: they are
-                // masked out of the sums (Sec. 3.5 dynamic polar skip)
-                // (full blocks take a compile-time step count: a runtime
-                // bound is if-converted into selects on every state register)
-                for (int j = js; j < je; j += 8) {
-                    SBlock<FW> b0, b1;
-                    load_block(b0, bet, qs, j);
-                    load_block(b1, bet, qs, j + 4);
-                    guard = guard_check(s);
-                    if (j + 8 <= je) {
-                        synth_block4<true>(s, b0, 4);
-                        guard = guard_check(s);
-                        synth_block4<true>(s, b1, 4);
-                    } else {
-                        synth_block4<true>(s, b0, je - j);
-                        if (j + 4 < je) {
-                            guard = guard_check(s);
-                            synth_block4<true>(s, b1, je - j - 4);
-                        }
-                    }
-                }
-            } else if (je - js == kSegLen) {
-                // full segment, straight-line
-#pragma unroll
-                for (int bk = 0; bk < kSegLen; bk += 8) {
-                    SBlock<FW> b0, b1;
-                    load_block(b0, bet, qs, js + bk);
-                    load_block(b1, bet, qs, js + bk + 4);
-                    synth_block4<false>(s, b0, 4);
-                    synth_block4<false>(s, b1, 4);
-                }
-            } else {
-                // last, partial segment of the order: full blocks, then one
-                // bounded block
-                int j = js;
-                for (; j + 8 <= je; j += 8) {
-                    SBlock<FW> b0, b1;
-                    load_block(b0, bet, qs, j);
-                    load_block(b1, bet, qs, j + 4);
-                    synth_block4<false>(s, b0, 4);
-                    synth_block4<false>(s, b1, 4);
-                }
-                if (j < je) {
-                    SBlock<FW> b0, b1;
-                    load_block(b0, bet, qs, j);
-                    load_block(b1, bet, qs, j + 4);
-                    synth_block4<false>(s, b0, je - j);
-                    if (j + 4 < je) synth_block4<false>(s, b1, je - j - 4);
-                }
-            }
-        }
-
-#pragma unroll
-        for (int k = 0; k < kPrefetchSlots; k++) sink ^= pf[k];
-
-        // Mirror fold: north = E + O, south = E - O.  For the adjoint of the
-        // analysis the output carries (2 pi/nphi) w_i / c_m.
-        const double cm = a.adjoint ? (2.0 * M_PI / P->nphi) * (m == 0 ? 1.0 : 0.5) : 1.0;
+    if (U[U_ZERO]) {
+        // no latitude of the block reaches the polar threshold: F_m = 0 there
 #pragma unroll
         for (int p = 0; p < LP; p++) {
             const int pair = pb + p * 64 + lane;
             if (pair >= npair) continue;
-            const double sc = a.adjoint ? cm * P->wfull[pair] : 1.0;
             const int is = nlat - 1 - pair;
 #pragma unroll
             for (int f = 0; f < FW; f++) {
                 if (f >= nf) continue;
                 double* F = a.out + foff[f] + 2 * ((size_t)m * nlat);
-                *(double2*)(F + 2 * pair) =
-                    make_double2(sc * (s.er[p][f] + s.orr[p][f]), sc * (s.ei[p][f] + s.oi[p][f]));
-                if (is != pair)
-                    *(double2*)(F + 2 * is) = make_double2(sc * (s.er[p][f] - s.orr[p][f]),
-                                                           sc * (s.ei[p][f] - s.oi[p][f]));
+                *(double2*)(F + 2 * pair) = make_double2(0.0, 0.0);
+                *(double2*)(F + 2 * is) = make_double2(0.0, 0.0);
             }
+        }
+        return;
+    }
+    const int jstart = U[U_JS], jwin = U[U_JW];
+    const long base = (long)m * (2 * L + 1 - m) / 2 + m;
+    const int nj = L - m + 1;
+    cdp bet = (cdp)P->beta + base;
+    cdp qs[FW];
+#pragma unroll
+    for (int f = 0; f < FW; f++) qs[f] = (cdp)(a.in + qoff[f]) + 2 * base;
+    cip segexp = (cip)P->segexp + ((cip)P->segoff)[m];
+
+    SynthState<LP, FW> s;
+    Starts<LP> st;
+    load_starts(st, P, m, pb, nj);
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        const int pair = pb + p * 64 + lane;
+        const bool act = pair < npair;
+        s.x[p] = act ? P->xp[act ? pair : 0] : 0.0;
+        s.ua[p] = 0.0;
+        s.ub[p] = 0.0;
+#pragma unroll
+        for (int f = 0; f < FW; f++) s.er[p][f] = s.ei[p][f] = s.orr[p][f] = s.oi[p][f] = 0.0;
+    }
+
+    // Warm L2 with this order's beta and spectrum from the first step on: the
+    // waves of the order's latitude blocks touch one word per 64-byte line
+    // with vector loads into registers that are consumed only after the order
+    // is done.  They are issued after the start values above have arrived and
+    // no other vector load follows before the end, so no wave waits on them
+    // (the scalar loads are counted apart).  The scalar loads then find these
+    // lines in L2.
+    __builtin_amdgcn_sched_barrier(0);
+    unsigned pf[kPrefetchSlots];
+    {
+        const int nblk_m = (npair + 64 * LP - 1) / (64 * LP);
+        const int nthr = nblk_m * 64;
+        const int gi = (pb / (64 * LP)) * 64 + lane;
+        const int nrem = nj - jstart;
+        const int lb = (nrem * 8 + 63) / 64;   // beta lines
+        const int lq = (nrem * 16 + 63) / 64;  // spectrum lines per field
+        const char* b0 = (const char*)(P->beta + base + jstart);
+#pragma unroll
+        for (int k = 0; k < kPrefetchSlots; k++) {
+            int li = gi + k * nthr;
+            const char* addr = b0;
+            if (li < lb) {
+                addr = b0 + li * 64;
+            } else {
+                li -= lb;
+#pragma unroll
+                for (int f = 0; f < FW; f++) {
+                    if (li >= 0 && li < lq) addr = (const char*)(a.in + qoff[f] + 2 * (base + jstart)) + li * 64;
+                    li -= lq;
+                }
+            }
+            pf[k] = *(const unsigned*)addr;
+        }
+    }
+
+    // Start window: blocks of kInject steps from the first start, lanes
+    // joining at block boundaries, up to the segment boundary after the last
+    // start.  (The shift is 0 off segment boundaries: an unconditional
+    // ldexp, not a branch, which the compiler would turn into selects.)
+    static_assert(kInject == 8, "the start window advances in blocks of 8 steps");
+    int j = jstart;
+    while (j < nj && (j <= jwin || j % kSegLen != 0)) {
+        rescale(s.ua, s.ub, (j > jstart && j % kSegLen == 0) ? segexp[j / kSegLen] : 0);
+        start_lanes(s.ua, s.ub, st, j);
+        synth_block8(s, bet, qs, j, nj);
+        j += 8;
+    }
+    // Every lane has started: whole segments, straight-line.
+    for (int js = j; js < nj; js += kSegLen) {
+        const int je = min(js + kSegLen, nj);
+        rescale(s.ua, s.ub, segexp[js / kSegLen]);
+        if (je - js == kSegLen) {
+#pragma unroll
+            for (int bk = 0; bk < kSegLen; bk += 8) {
+                SBlock<FW> b0, b1;
+                load_block(b0, bet, qs, js + bk);
+                load_block(b1, bet, qs, js + bk + 4);
+                synth_block4(s, b0, 4);
+                synth_block4(s, b1, 4);
+            }
+        } else {
+            // last, partial segment of the order
+            for (int jj = js; jj < je; jj += 8) synth_block8(s, bet, qs, jj, nj);
+        }
+    }
+
+    unsigned sink = 0;
+#pragma unroll
+    for (int k = 0; k < kPrefetchSlots; k++) sink ^= pf[k];
+
+    // Mirror fold: north = E + O, south = E - O.  For the adjoint of the
+    // analysis the output carries (2 pi/nphi) w_i / c_m.
+    const double cm = a.adjoint ? (2.0 * M_PI / P->nphi) * (m == 0 ? 1.0 : 0.5) : 1.0;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        const int pair = pb + p * 64 + lane;
+        if (pair >= npair) continue;
+        const double sc = a.adjoint ? cm * P->wfull[pair] : 1.0;
+        const int is = nlat - 1 - pair;
+#pragma unroll
+        for (int f = 0; f < FW; f++) {
+            if (f >= nf) continue;
+            double* F = a.out + foff[f] + 2 * ((size_t)m * nlat);
+            *(double2*)(F + 2 * pair) =
+                make_double2(sc * (s.er[p][f] + s.orr[p][f]), sc * (s.ei[p][f] + s.oi[p][f]));
+            if (is != pair)
+                *(double2*)(F + 2 * is) = make_double2(sc * (s.er[p][f] - s.orr[p][f]),
+                                                       sc * (s.ei[p][f] - s.oi[p][f]));
         }
     }
     // keeps the prefetch loads alive; nfields is never negative
@@ -402,66 +409,34 @@ __global__ void __launch_bounds__(512) k_legendre_synth(LegArgs a)
 template <int LP, int FW>
 struct AState {
     double x[LP], ua[LP], ub[LP];
-    int k[LP];
-    // folded, weighted inputs w (F_N + F_S), w (F_N - F_S); set to 0 while
-    // the lane's value is scaled, so scaled lanes add exactly 0 without masking
+    // folded, weighted inputs w (F_N + F_S), w (F_N - F_S)
     double ger[LP][FW], gei[LP][FW], gor[LP][FW], goi[LP][FW];
 };
 
-// Where the inputs of an analysis wave come from.
-template <int FW>
-struct AInputs {
-    const double* F[FW];  // F_m(theta) of each field (this order)
-    int nlat, npair, adjoint;
-    const double* wq;
-};
-
-// (Re)loads the folded inputs of every lane, zero for scaled lanes.
+// Loads the folded inputs of every lane.  A lane that has not started holds a
+// zero state, so it adds exactly 0 whatever its inputs.
 template <int LP, int FW>
-__device__ __forceinline__ void analys_inputs(AState<LP, FW>& s, const AInputs<FW>& in)
+__device__ __forceinline__ void analys_inputs(AState<LP, FW>& s, const double* const (&F)[FW], int nlat,
+                                              int npair, int adjoint, const double* wq)
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int p = 0; p < LP; p++) {
         const int pair = p * 64 + lane;
-        const bool act = pair < in.npair;
+        const bool act = pair < npair;
         const int pc = act ? pair : 0;
-        const bool middle = (in.nlat & 1) && pc == in.npair - 1;
-        double wt = !act ? 0.0 : (in.adjoint ? (middle ? 0.5 : 1.0) : in.wq[pc]);
-        if (s.k[p]) wt = 0.0;
+        const bool middle = (nlat & 1) && pc == npair - 1;
+        const double wt = !act ? 0.0 : (adjoint ? (middle ? 0.5 : 1.0) : wq[pc]);
 #pragma unroll
         for (int f = 0; f < FW; f++) {
-            const double2 fn = *(const double2*)(in.F[f] + 2 * pc);
-            const double2 fs = *(const double2*)(in.F[f] + 2 * (in.nlat - 1 - pc));
+            const double2 fn = *(const double2*)(F[f] + 2 * pc);
+            const double2 fs = *(const double2*)(F[f] + 2 * (nlat - 1 - pc));
             s.ger[p][f] = wt * (fn.x + fs.x);
             s.gei[p][f] = wt * (fn.y + fs.y);
             s.gor[p][f] = wt * (fn.x - fs.x);
             s.goi[p][f] = wt * (fn.y - fs.y);
         }
     }
-}
-
-// Guard check; returns whether any lane is still scaled and records in
-// `changed` whether some exponent moved.  The inputs are refreshed after the
-// chunk: a lane that just became live carries values near 2^-256, so the few
-// steps it spends with zero inputs drop only contributions below 2^-200 (the
-// polar-cut bound).
-template <int LP, int FW>
-__device__ __forceinline__ bool analys_guard(AState<LP, FW>& s, bool& changed)
-{
-    const double down = 0x1p-256;
-    bool any = false;
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        if (s.k[p] > 0 && (fabs(s.ua[p]) >= 1.0 || fabs(s.ub[p]) >= 1.0)) {
-            s.ua[p] *= down;
-            s.ub[p] *= down;
-            s.k[p] -= 1;
-            changed = true;
-        }
-        any |= s.k[p] > 0;
-    }
-    return wave_any(any);
 }
 
 // One recurrence step (even t: ua and the even inputs, odd t: ub and the odd
@@ -507,9 +482,12 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
     constexpr int NV = 2 * SC * FW; // rows reduced per pass
     static_assert(NV == 32, "two lanes per row");
     static_assert(kSegLen % C == 0, "chunks tile a segment");
+    static_assert(SC % kInject == 0, "lanes start at reduction-block boundaries or inside them");
     __shared__ double red[NV][65];
 
     cip U = (cip)a.units + (size_t)blockIdx.x * kUnitInts;
+    const int m = U[U_M];
+    if (m < 0) return;
     const int field0 = U[U_FIELD] + blockIdx.y * FW;
     if (field0 >= a.nfields) return;
     const int nf = min(U[U_NF], a.nfields - field0);
@@ -517,9 +495,9 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
     const int L = P->L, M = P->M, nlat = P->nlat, npair = P->npair;
     const long nlm = P->nlm;
     const int lane = threadIdx.x;
-    const int m = U[U_M0];
-    const int j0 = U[U_PB], j1 = U[U_J1], rst = U[U_RST];
+    const int j0 = U[U_PB], j1 = U[U_J1], js0 = U[U_JS], jwin = U[U_JW], rst = U[U_RST];
     const long base = (long)m * (2 * L + 1 - m) / 2 + m;
+    const int nj = L - m + 1;
     cdp bet = (cdp)P->beta + base;
     cip segexp = (cip)P->segexp + ((cip)P->segoff)[m];
 
@@ -532,57 +510,57 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
         foff[f] = field_f_off(a, ff, M, nlat);
     }
 
-    AState<LP, FW> s;
-    AInputs<FW> in;
+    // degrees before the first started lane: every term is dropped
+    for (int j = j0 + (lane >> 1); j < js0; j += 32) {
 #pragma unroll
-    for (int f = 0; f < FW; f++) in.F[f] = a.in + foff[f] + 2 * ((size_t)m * nlat);
-    in.nlat = nlat;
-    in.npair = npair;
-    in.adjoint = a.adjoint;
-    in.wq = P->wq;
-    bool anyk = false;
+        for (int f = 0; f < FW; f++)
+            if (f < nf) a.out[qoff[f] + 2 * (base + j) + (lane & 1)] = 0.0;
+    }
+    if (js0 >= j1) return;
+
+    AState<LP, FW> s;
+    Starts<LP> st;
+    load_starts(st, P, m, 0, nj);
 #pragma unroll
     for (int p = 0; p < LP; p++) {
         const int pair = p * 64 + lane;
         const bool act = pair < npair;
         const int pc = act ? pair : 0;
         s.x[p] = act ? P->xp[pc] : 0.0;
-        if (rst < 0) {
-            s.ua[p] = act ? P->start_y[(size_t)m * npair + pc] : 0.0;
-            s.ub[p] = 0.0;
-            s.k[p] = act ? P->start_k[(size_t)m * npair + pc] : 0;
-        } else {
-            const double2 st = *(const double2*)(P->rst_y + 2 * ((size_t)rst * npair + pc));
-            s.ua[p] = act ? st.x : 0.0;
-            s.ub[p] = act ? st.y : 0.0;
-            s.k[p] = act ? P->rst_k[(size_t)rst * npair + pc] : 0;
+        s.ua[p] = 0.0;
+        s.ub[p] = 0.0;
+        if (rst >= 0 && js0 == j0) {
+            const double2 r = *(const double2*)(P->rst_y + 2 * ((size_t)rst * npair + pc));
+            s.ua[p] = act ? r.x : 0.0;
+            s.ub[p] = act ? r.y : 0.0;
         }
-        anyk |= s.k[p] > 0;
     }
-    analys_inputs(s, in);
-    bool guard = wave_any(anyk);
+    {
+        const double* F[FW];
+#pragma unroll
+        for (int f = 0; f < FW; f++) F[f] = a.in + foff[f] + 2 * ((size_t)m * nlat);
+        analys_inputs(s, F, nlat, npair, a.adjoint, P->wq);
+    }
 
     // Warm L2 with the beta entries of this unit (one word per 64-byte line
     // per lane, consumed at the end; see the synthesis kernel).
     __builtin_amdgcn_sched_barrier(0);
     unsigned pf;
     {
-        const int nbytes = (j1 - j0 + C) * 8;
+        const int nbytes = (j1 - js0 + C) * 8;
         const int off = lane * 64;
-        pf = *(const unsigned*)((const char*)(P->beta + base + j0) + (off < nbytes ? off : 0));
+        pf = *(const unsigned*)((const char*)(P->beta + base + js0) + (off < nbytes ? off : 0));
     }
-    const double cm0 = 1.0, cm1 = a.adjoint ? 2.0 : 1.0;
-    const double cm = m == 0 ? cm0 : cm1;
+    const double cm = (m == 0 || !a.adjoint) ? 1.0 : 2.0;
+    const int v = lane & 31;   // reduction row of this lane
+    const int h = lane >> 5;   // half of the row it sums
+    const int comp = v & 1;
+    const int t_out = (v >> 1) / FW;
+    const int f_out = (v >> 1) % FW;
 
-    // units start on a segment boundary (j0 is a multiple of the split length)
-    for (int js = j0; js < j1; js += kSegLen) {
-        // unconditional segment rescale (shift 0 for segment 0)
-        const int sh = segexp[js / kSegLen];
-#pragma unroll
-        for (int p = 0; p < LP; p++) {
-            s.ua[p] = __builtin_amdgcn_ldexp(s.ua[p], sh);
-            s.ub[p] = __builtin_amdgcn_ldexp(s.ub[p], sh);
-        }
+    // js0 is a segment start (the plan rounds it down)
+    for (int js = js0; js < j1; js += kSegLen) {
+        rescale(s.ua, s.ub, js > js0 ? segexp[js / kSegLen] : 0);
         const int je = min(js + kSegLen, j1);
         for (int c = js; c < je; c += C) {
             // beta for the chunk in one block load (the table is padded).  A
@@ -592,22 +570,17 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
             cd16p pbk = (cd16p)(bet + c);
 #pragma unroll
             for (int i = 0; i < C; i++) b.v[i] = pbk->v[i];
-            bool changed = false;
+            const bool window = c <= jwin;
 #pragma unroll
             for (int c0 = 0; c0 < C; c0 += SC) {
                 // this lane's output scale, loaded ahead of the steps (clamped
                 // index: lanes past the unit's end write nothing)
-                const int v = lane & 31;
-                const int h = lane >> 5;
-                const int comp = v & 1;
-                const int t_out = (v >> 1) / FW;
-                const int f_out = (v >> 1) % FW;
                 const int j_out = c + c0 + t_out;
                 const double gam = P->gamma[base + min(j_out, je - 1)] * cm;
-                if (guard) {
+                if (window) {
 #pragma unroll
                     for (int t = 0; t < SC; t++) {
-                        if (((c0 + t) & (kGuardEvery - 1)) == 0) guard = analys_guard(s, changed);
+                        if ((c0 + t) % kInject == 0) start_lanes(s.ua, s.ub, st, c + c0 + t);
                         double sr[FW], si[FW];
                         analys_step(s, c0 + t, b.v[c0 + t], sr, si);
 #pragma unroll
@@ -628,8 +601,8 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
                         }
                     }
                 }
-                // row v = lane % 32 summed over the 64 lanes by two lanes,
-                // four independent partial sums each
+                // row v summed over the 64 lanes by two lanes, four
+                // independent partial sums each
                 __syncthreads();
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
@@ -649,7 +622,6 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
                     a.out[qoff[f_out] + 2 * idx + comp] = val;
                 }
             }
-            if (wave_any(changed)) analys_inputs(s, in);
         }
     }
     // keeps the prefetch load alive; nfields is never negative
@@ -672,7 +644,7 @@ int launch_prescale(const DevPlan* plans, const long* q_off, const long* s_off, 
 template <int LP, int FW>
 static int launch_synth_t(const LegLaunch& l, void* stream)
 {
-    const int wpg = std::max(1, std::min(l.wpg, 8));
+    const int wpg = std::max(1, std::min(l.wpg, synth_max_threads<LP, FW>() / 64));
     LegArgs a{l.plans, l.units, l.q_off, l.f_off, l.in, l.out, l.nfields, l.adjoint, l.nunits, wpg};
     hipLaunchKernelGGL((k_legendre_synth<LP, FW>), dim3((l.nunits + wpg - 1) / wpg, l.grid_y),
                        dim3(64 * wpg), 0, (hipStream_t)stream, a);

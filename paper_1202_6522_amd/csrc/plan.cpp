@@ -79,61 +79,78 @@ static int log2_floor(ld v)
     return e - 1;
 }
 
-// For each order m, scans latitude pairs from the pole toward the equator and
-// runs the kernels' rescaled recurrence (same steps, same guard) to find the
-// first pair whose |P_n^m| reaches 2^kPolarLog2 for some n <= lmax; the pairs
-// before it get a zero start value (so they contribute exactly 0 and never
-// hold a wave in the guarded, masked mode).  |P| grows away from the poles, so
-// the first significant pair bounds the cut.
-static void polar_cut(Plan& p)
+// Lane starts (Sec. 3.5 guard and Sec. 3.1 polar threshold, at plan time).
+// For each (order, latitude pair) the recurrence is followed from n = m in the
+// scaled form u = w 2^{-256 k} with the kernels' own steps (same segment
+// shifts, same fused multiply-adds).  The lane starts at the checkpoint
+// (multiple of kInject) that opens the first block of kInject steps in which
+// |P_n^m| reaches 2^kPolarLog2; the state entering that step, converted to a
+// plain double (exact: it is far inside the normal range), is stored.  A lane
+// that never reaches the threshold gets the start step nj = lmax - m + 1.
+static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double& yb)
 {
-    const int L = p.L, M = p.M, np = p.npair;
+    const int nj = p.L - m + 1;
+    const long base = lm_index(p.L, m, m);
+    const double down = std::ldexp(1.0, -kGuardUnit);
+    const double x = p.xp[i];
+    double ua = p.start_y[(size_t)m * p.npair + i], ub = 0.0;
+    int k = p.start_k[(size_t)m * p.npair + i];
+    jst = nj;
+    ya = yb = 0.0;
+    for (int c = 0; c < nj; c += kInject) {
+        if (c > 0 && c % kSegLen == 0) {
+            const int d = p.segexp[p.segoff[m] + c / kSegLen];
+            ua = std::ldexp(ua, d);
+            ub = std::ldexp(ub, d);
+        }
+        const double sa = ua, sb = ub;
+        const int sk = k;
+        bool sig = false;
+        for (int j = c; j < std::min(c + kInject, nj); j += 2) {
+            if (j % kGuardEvery == 0 && k > 0 && (std::fabs(ua) >= 1.0 || std::fabs(ub) >= 1.0)) {
+                ua *= down;
+                ub *= down;
+                k -= 1;
+            }
+            ua = std::fma(x, ub, p.beta[base + j] * ua);
+            if (j + 1 < nj) ub = std::fma(x, ua, p.beta[base + j + 1] * ub);
+            // |P| = |u| gamma 2^{-256 k}
+            const double v = std::max(std::fabs(ua) * p.gamma[base + j],
+                                      j + 1 < nj ? std::fabs(ub) * p.gamma[base + j + 1] : 0.0);
+            if (v > 0.0) {
+                int e;
+                std::frexp(v, &e);
+                if (e - (long)kGuardUnit * k >= kPolarLog2) sig = true;
+            }
+        }
+        if (sig) {
+            jst = c;
+            ya = std::ldexp(sa, -kGuardUnit * sk);
+            yb = std::ldexp(sb, -kGuardUnit * sk);
+            return;
+        }
+    }
+}
+
+static void lane_starts(Plan& p)
+{
+    const int M = p.M, np = p.npair;
+    p.inj_j.assign((size_t)(M + 1) * np, 0);
+    p.inj_y.assign((size_t)(M + 1) * np * 2, 0.0);
     p.first_pair.assign(M + 1, 0);
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
     for (unsigned tid = 0; tid < nth; tid++) {
         pool.emplace_back([&, tid]() {
-            const double down = std::ldexp(1.0, -kGuardUnit);
             for (int m = (int)tid; m <= M; m += (int)nth) {
-                const long base = lm_index(L, m, m);
-                int i0 = np;
+                const int nj = p.L - m + 1;
+                int first = np;
                 for (int i = 0; i < np; i++) {
-                    double x = p.xp[i];
-                    double ua = p.start_y[(size_t)m * np + i], ub = 0.0;
-                    int k = p.start_k[(size_t)m * np + i];
-                    bool sig = false;
-                    int E = 0;  // current segment exponent: P = u * gamma
-                    for (int j = 0; j <= L - m && !sig; j += 2) {
-                        if (j > 0 && j % kSegLen == 0) {
-                            int d = p.segexp[p.segoff[m] + j / kSegLen];
-                            ua = std::ldexp(ua, d);
-                            ub = std::ldexp(ub, d);
-                            E += d;
-                        }
-                        if (j % kGuardEvery == 0 && k > 0 && (std::fabs(ua) >= 1.0 || std::fabs(ub) >= 1.0)) {
-                            ua *= down;
-                            ub *= down;
-                            k -= 1;
-                        }
-                        ua = std::fma(x, ub, p.beta[base + j] * ua);
-                        if (j + 1 <= L - m) ub = std::fma(x, ua, p.beta[base + j + 1] * ub);
-                        // |P| = |u| gamma 2^{-256 k}; gamma >= 1 within a segment
-                        const double v = std::max(std::fabs(ua) * p.gamma[base + j],
-                                                  j + 1 <= L - m ? std::fabs(ub) * p.gamma[base + j + 1] : 0.0);
-                        if (v > 0.0) {
-                            int e;
-                            std::frexp(v, &e);
-                            if (e - (long)kGuardUnit * k >= kPolarLog2) sig = true;
-                        }
-                    }
-                    (void)E;
-                    if (sig) { i0 = i; break; }
+                    const size_t q = (size_t)m * np + i;
+                    lane_start(p, m, i, p.inj_j[q], p.inj_y[2 * q], p.inj_y[2 * q + 1]);
+                    if (p.inj_j[q] < nj && first == np) first = i;
                 }
-                p.first_pair[m] = i0;
-                for (int i = 0; i < i0; i++) {
-                    p.start_y[(size_t)m * np + i] = 0.0;
-                    p.start_k[(size_t)m * np + i] = 0;
-                }
+                p.first_pair[m] = first;
             }
         });
     }
@@ -235,8 +252,8 @@ Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
         }
     }
 
-    // ---- static polar cut (Sec. 3.1) ----
-    polar_cut(*p);
+    // ---- lane starts: guard and polar threshold at plan time ----
+    lane_starts(*p);
 
     // ---- FFT twiddles ----
     const int K = p->K;
@@ -264,75 +281,98 @@ Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
     return p;
 }
 
-// Emulates the kernels' per-lane recurrence (same operations, same order,
-// fused multiply-adds) from n = m up to the listed restart steps.
-static void restart_states(const Plan& p, int m, const std::vector<int>& j_list,
-                           std::vector<double>& ys, std::vector<int>& ks)
+// Analysis restart states: the kernels' recurrence (same operations, same
+// order, fused multiply-adds) run per lane from its start step up to each
+// listed restart step, giving the state entering that step after its segment
+// shift.  Lanes that start at or after a restart step hold 0 there.
+static void restart_states(const Plan& p, int m, const std::vector<int>& j_list, std::vector<double>& ys)
 {
     const int np = p.npair;
+    const int nj = p.L - m + 1;
     const long base = lm_index(p.L, m, m);
-    const int jmax = j_list.empty() ? 0 : j_list.back();
     ys.assign(j_list.size() * np * 2, 0.0);
-    ks.assign(j_list.size() * np, 0);
-    const double down = std::ldexp(1.0, -kGuardUnit);
     for (int i = 0; i < np; i++) {
-        double x = p.xp[i];
-        double ua = p.start_y[(size_t)m * np + i], ub = 0.0;
-        int k = p.start_k[(size_t)m * np + i];
-        size_t r = 0;
-        for (int j = 0; j <= jmax; j += 2) {
-            if (r < j_list.size() && j == j_list[r]) {
-                ys[(r * np + i) * 2] = ua;
-                ys[(r * np + i) * 2 + 1] = ub;
-                ks[r * np + i] = k;
-                r++;
-                if (r == j_list.size()) break;
+        const size_t q = (size_t)m * np + i;
+        const int js = p.inj_j[q];
+        if (js >= nj) continue;
+        const double x = p.xp[i];
+        double ua = p.inj_y[2 * q], ub = p.inj_y[2 * q + 1];
+        int j = js;
+        for (size_t r = 0; r < j_list.size(); r++) {
+            const int jr = j_list[r];
+            if (jr <= js) continue;  // the lane starts by itself in that unit
+            for (; j < jr; j += 2) {
+                if (j > js && j % kSegLen == 0) {
+                    const int d = p.segexp[p.segoff[m] + j / kSegLen];
+                    ua = std::ldexp(ua, d);
+                    ub = std::ldexp(ub, d);
+                }
+                ua = std::fma(x, ub, p.beta[base + j] * ua);
+                if (j + 1 < nj) ub = std::fma(x, ua, p.beta[base + j + 1] * ub);
             }
-            if (j > 0 && j % kSegLen == 0) {
-                double sc = std::ldexp(1.0, p.segexp[p.segoff[m] + j / kSegLen]);
-                ua *= sc;
-                ub *= sc;
-            }
-            if (j % kGuardEvery == 0 && k > 0 && (std::fabs(ua) >= 1.0 || std::fabs(ub) >= 1.0)) {
-                ua *= down;
-                ub *= down;
-                k -= 1;
-            }
-            ua = std::fma(x, ub, p.beta[base + j] * ua);
-            if (j + 1 <= p.L - m) ub = std::fma(x, ua, p.beta[base + j + 1] * ub);
+            // entering jr (a segment start): apply its shift
+            const int d = p.segexp[p.segoff[m] + jr / kSegLen];
+            ys[(r * np + i) * 2] = std::ldexp(ua, d);
+            ys[(r * np + i) * 2 + 1] = std::ldexp(ub, d);
         }
     }
+}
+
+// First / last start step of the lanes [i0, i1) of order m that start in
+// [lo, hi); returns false if none does.
+bool start_range(const Plan& p, int m, int i0, int i1, int lo, int hi, int& jmin, int& jmax)
+{
+    jmin = hi;
+    jmax = lo;
+    bool any = false;
+    for (int i = i0; i < i1; i++) {
+        const int j = p.inj_j[(size_t)m * p.npair + i];
+        if (j < lo || j >= hi) continue;
+        any = true;
+        jmin = std::min(jmin, j);
+        jmax = std::max(jmax, j);
+    }
+    return any;
 }
 
 int rebuild_units(Plan& p, std::string& err)
 {
     const Tiling& t = p.tiling;
     const int np = p.npair, L = p.L, M = p.M;
-    // ---- synthesis units: (m [, mmax - m]) x latitude-pair block ----
+    // ---- synthesis units: order x latitude-pair block ----
+    // m_pairing 0: one workgroup per order (its latitude blocks);
+    // 1: orders m and M-m in the same workgroup (equal work per workgroup).
     p.synth_units.clear();
     const int blk = 64 * t.synth_lp;
     const int nblk = (np + blk - 1) / blk;
-    std::vector<std::pair<int, int>> mpairs;
-    for (int m = 0; m <= M; m++) {
-        if (t.m_pairing) {
-            int m2 = M - m;
-            if (m < m2) mpairs.push_back({m, m2});
-            else if (m == m2) mpairs.push_back({m, -1});
-        } else {
-            mpairs.push_back({m, -1});
+    const int max_wpg = t.synth_lp == 1 && t.fw == 1 ? 16 : 8;
+    auto emit = [&](int m, int b) {
+        int u[kUnitInts] = {0, t.fw, 0, -1, 0, 0, b * blk, 0, -1, 0, 0, 0};
+        if (m >= 0) {
+            const int nj = L - m + 1;
+            int jmin, jmax;
+            u[U_M] = m;
+            if (start_range(p, m, b * blk, std::min((b + 1) * blk, np), 0, nj, jmin, jmax)) {
+                u[U_JS] = jmin;
+                u[U_JW] = jmax;
+            } else {
+                u[U_ZERO] = 1;  // every lane of the block is below the polar threshold
+            }
         }
+        p.synth_units.insert(p.synth_units.end(), u, u + kUnitInts);
+    };
+    if (t.m_pairing && 2 * nblk <= max_wpg) {
+        for (int m = 0; 2 * m <= M; m++) {
+            const int m2 = M - m;
+            for (int b = 0; b < nblk; b++) emit(m, b);
+            for (int b = 0; b < nblk; b++) emit(m2 != m ? m2 : -1, b);
+        }
+        p.synth_wpg = 2 * nblk;
+    } else {
+        for (int m = 0; m <= M; m++)
+            for (int b = 0; b < nblk; b++) emit(m, b);
+        p.synth_wpg = nblk <= max_wpg ? nblk : 1;
     }
-    for (auto& mp : mpairs)
-        for (int b = 0; b < nblk; b++) {
-            // a block lies entirely in the polar cut of an order when all its
-            // pairs come before that order's first kept pair
-            const int bend = std::min((b + 1) * blk, np);
-            int flags = 0;
-            if (bend <= p.first_pair[mp.first]) flags |= 1;
-            if (mp.second >= 0 && bend <= p.first_pair[mp.second]) flags |= 2;
-            int u[kUnitInts] = {0, t.fw, 0, mp.first, mp.second, b * blk, 0, flags};
-            p.synth_units.insert(p.synth_units.end(), u, u + kUnitInts);
-        }
 
     // ---- analysis units: (m, degree range) pieces, longest first ----
     int S = t.split;
@@ -343,7 +383,7 @@ int rebuild_units(Plan& p, std::string& err)
     }
     if (S % kSegLen) { err = "split must be a multiple of 32"; return -1; }
     p.split_used = S;
-    struct AU { int m, j0, j1, rst; };
+    struct AU { int m, j0, j1, js, jw, rst; long cost; };
     std::vector<AU> au;
     std::vector<std::vector<int>> rj(M + 1);
     int nrst = 0;
@@ -352,32 +392,44 @@ int rebuild_units(Plan& p, std::string& err)
         int nj = L - m + 1;
         rbase[m] = nrst;
         for (int j0 = 0; j0 < nj; j0 += S) {
+            const int j1 = std::min(j0 + S, nj);
             int r = -1;
             if (j0 > 0) { r = nrst++; rj[m].push_back(j0); }
-            au.push_back({m, j0, std::min(j0 + S, nj), r});
+            // lanes started before j0 are live from the restart state; the
+            // unit may skip ahead (in whole segments) to its first start
+            int jmin, jmax;
+            bool live0 = start_range(p, m, 0, np, 0, j0 + (j0 == 0 ? 1 : 0), jmin, jmax);
+            int js, jw;
+            if (live0) {
+                js = j0;
+                jw = start_range(p, m, 0, np, j0, j1, jmin, jmax) ? jmax : j0;
+            } else if (start_range(p, m, 0, np, j0, j1, jmin, jmax)) {
+                js = j0 + ((jmin - j0) / kSegLen) * kSegLen;
+                jw = jmax;
+            } else {
+                js = j1;  // nothing starts: the unit only writes zeros
+                jw = j1;
+            }
+            au.push_back({m, j0, j1, js, jw, r, (long)(j1 - js) + 4});
         }
     }
-    std::stable_sort(au.begin(), au.end(),
-                     [](const AU& a, const AU& b) { return (a.j1 - a.j0) > (b.j1 - b.j0); });
+    std::stable_sort(au.begin(), au.end(), [](const AU& a, const AU& b) { return a.cost > b.cost; });
     p.analys_units.clear();
     for (auto& a : au) {
-        int u[kUnitInts] = {0, t.fw, 0, a.m, -1, a.j0, a.j1, a.rst};
+        int u[kUnitInts] = {0, t.fw, 0, a.m, a.js, a.jw, a.j0, a.j1, a.rst, 0, 0, 0};
         p.analys_units.insert(p.analys_units.end(), u, u + kUnitInts);
     }
     p.rst_y.assign((size_t)nrst * np * 2, 0.0);
-    p.rst_k.assign((size_t)nrst * np, 0);
     // restart states, orders split over host threads
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
     for (unsigned tid = 0; tid < nth; tid++) {
         pool.emplace_back([&, tid]() {
             std::vector<double> ys;
-            std::vector<int> ks;
             for (int m = (int)tid; m <= M; m += (int)nth) {
                 if (rj[m].empty()) continue;
-                restart_states(p, m, rj[m], ys, ks);
+                restart_states(p, m, rj[m], ys);
                 std::memcpy(&p.rst_y[(size_t)rbase[m] * np * 2], ys.data(), ys.size() * sizeof(double));
-                std::memcpy(&p.rst_k[(size_t)rbase[m] * np], ks.data(), ks.size() * sizeof(int));
             }
         });
     }
@@ -397,30 +449,32 @@ static size_t put(std::vector<unsigned char>& img, size_t off, const std::vector
 void build_image(Plan& p)
 {
     p.image.clear();
-    p.table_off.assign(16, 0);
+    p.table_off.assign(TB_COUNT, 0);
     size_t off = align256(sizeof(DevPlan));
     p.image.resize(off, 0);
-    int t = 0;
-    p.table_off[t++] = off; off = put(p.image, off, p.xp);
-    p.table_off[t++] = off; off = put(p.image, off, p.wq);
-    p.table_off[t++] = off; off = put(p.image, off, p.wfull);
+    auto place = [&](int tb, const auto& v) {
+        p.table_off[tb] = off;
+        off = put(p.image, off, v);
+    };
+    place(TB_XP, p.xp);
+    place(TB_WQ, p.wq);
+    place(TB_WFULL, p.wfull);
     {
         // padded: the kernels load beta in blocks that may run past the end
         std::vector<double> bpad(p.beta);
         bpad.resize(p.beta.size() + kTablePad, 0.0);
-        p.table_off[t++] = off; off = put(p.image, off, bpad);
+        place(TB_BETA, bpad);
     }
-    p.table_off[t++] = off; off = put(p.image, off, p.gamma);
-    p.table_off[t++] = off; off = put(p.image, off, p.start_y);
-    p.table_off[t++] = off; off = put(p.image, off, p.start_k);
-    p.table_off[t++] = off; off = put(p.image, off, p.segexp);
-    p.table_off[t++] = off; off = put(p.image, off, p.segoff);
-    p.table_off[t++] = off; off = put(p.image, off, p.rst_y);
-    p.table_off[t++] = off; off = put(p.image, off, p.rst_k);
-    p.table_off[t++] = off; off = put(p.image, off, p.tw);
-    p.table_off[t++] = off; off = put(p.image, off, p.rtw);
-    p.table_off[t++] = off; off = put(p.image, off, p.synth_units);
-    p.table_off[t++] = off; off = put(p.image, off, p.analys_units);
+    place(TB_GAMMA, p.gamma);
+    place(TB_INJ_J, p.inj_j);
+    place(TB_INJ_Y, p.inj_y);
+    place(TB_SEGEXP, p.segexp);
+    place(TB_SEGOFF, p.segoff);
+    place(TB_RST_Y, p.rst_y);
+    place(TB_TW, p.tw);
+    place(TB_RTW, p.rtw);
+    place(TB_SYNTH_UNITS, p.synth_units);
+    place(TB_ANALYS_UNITS, p.analys_units);
     p.image.resize(off, 0);
 }
 

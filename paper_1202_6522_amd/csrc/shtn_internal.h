@@ -18,16 +18,22 @@ namespace shtn {
 // start both recurrence states are multiplied by 2^{E_s - E_{s-1}} (exact).
 // gamma_n = alpha_n 2^{-E_s} maps u back to P.
 constexpr int kSegLen = 32;
-// Underflow guard (Sec. 3.5): a lane keeps (w, k) with u = w 2^{-kGuardUnit k}.
-// While k > 0 the value is treated as 0 in the sums but the recurrence goes on;
-// every kGuardEvery steps, if |w| >= 1 the lane rescales w by 2^{-kGuardUnit}
-// and decrements k.
+// Underflow guard (Sec. 3.5), run at plan time: the host follows every
+// (order, latitude pair) recurrence from n = m in a scaled form
+// u = w 2^{-kGuardUnit k} (every kGuardEvery steps a value with k > 0 and
+// |w| >= 1 is multiplied by 2^{-kGuardUnit} and k decremented), so values far
+// below the double range are tracked exactly.
 constexpr int kGuardUnit = 256;
 constexpr int kGuardEvery = 4;
-// Static polar cut (Sec. 3.1, polar optimisation): a latitude whose |P_n^m|
-// stays below 2^kPolarLog2 for every n <= lmax is dropped from order m (its
-// start value is set to 0); every contribution dropped is below 2^-200.
+// Polar threshold (Sec. 3.1, polar optimisation): contributions with
+// |P_n^m| < 2^kPolarLog2 are dropped.  A lane starts at the first checkpoint
+// (a multiple of kInject steps) of the block of kInject steps in which its
+// |P_n^m| first reaches 2^kPolarLog2; before it the lane holds 0, so it adds
+// exactly 0 and the kernels carry no exponent.  The host stores the state
+// (u_{j-2}, u_{j-1}) entering that step as plain doubles.  A latitude that
+// never reaches the threshold for an order never starts.
 constexpr int kPolarLog2 = -200;
+constexpr int kInject = 8;
 // Analysis accumulates kChunk consecutive degrees per lane before a
 // cross-lane reduction.
 constexpr int kChunk = 16;
@@ -38,20 +44,40 @@ constexpr int kTablePad = 32;
 // Largest latitude-pair count one analysis wave covers (64 lanes x 8 pairs).
 constexpr int kMaxAnalysPairs = 512;
 
-// One work unit of a Legendre kernel = one wave (8 ints).
+// One work unit of a Legendre kernel = one wave (kUnitInts ints).  Steps j
+// count degrees from the order: n = m + j.
 enum UnitField {
     U_FIELD = 0,  // first field of the unit (relative; plus blockIdx.y * fw for plan calls)
     U_NF = 1,     // number of fields in the unit (<= fw)
     U_PLAN = 2,   // plan index (batch) or 0
-    U_M0 = 3,     // first order m
-    U_M1 = 4,     // second order (m pairing) or -1
-    U_PB = 5,     // synthesis: first latitude pair of the block; analysis: first step j0
-    U_J1 = 6,     // analysis: one past the last step (n = m + j)
-    U_RST = 7,    // analysis: restart slot or -1 (start at n = m);
-                  // synthesis: bit 0 / bit 1 set if the block is entirely
-                  // polar-cut for the first / second order (F written as 0)
+    U_M = 3,      // order m, or -1 for a unit without work
+    U_JS = 4,     // first step executed (lanes start there or later)
+    U_JW = 5,     // last step at which a lane of the unit starts (injection window)
+    U_PB = 6,     // synthesis: first latitude pair of the block; analysis: first output step j0
+    U_J1 = 7,     // analysis: one past the last output step
+    U_RST = 8,    // analysis: restart slot of j0 or -1 (j0 = 0)
+    U_ZERO = 9,   // synthesis: 1 if no lane of the block ever starts (F written as 0)
 };
-constexpr int kUnitInts = 8;
+constexpr int kUnitInts = 12;
+
+// Tables of a plan's device buffer, in buffer order (Plan::table_off).
+enum DevTable {
+    TB_XP = 0,
+    TB_WQ,
+    TB_WFULL,
+    TB_BETA,
+    TB_GAMMA,
+    TB_INJ_J,
+    TB_INJ_Y,
+    TB_SEGEXP,
+    TB_SEGOFF,
+    TB_RST_Y,
+    TB_TW,
+    TB_RTW,
+    TB_SYNTH_UNITS,
+    TB_ANALYS_UNITS,
+    TB_COUNT
+};
 
 // Device-resident view of a plan (stored at the start of its device buffer).
 struct DevPlan {
@@ -60,12 +86,11 @@ struct DevPlan {
     const double* wfull;   // [npair] Gauss weight per pair
     const double* beta;    // [nlm] rescaled recurrence coefficient, m-major
     const double* gamma;   // [nlm] output scale gamma_n
-    const double* start_y; // [(M+1) * npair] mantissa of P_m^m(x) (scaled by 2^{256 k})
-    const int* start_k;    // [(M+1) * npair] guard exponent of P_m^m
+    const int* inj_j;      // [(M+1) * npair] step at which the lane starts (n = m + j), or > lmax - m
+    const double* inj_y;   // [(M+1) * npair * 2] state (u_{j-2}, u_{j-1}) entering that step
     const int* segexp;     // per (m, segment s >= 1): E_s - E_{s-1}
     const int* segoff;     // [M+2] index of (m, s=0) in segexp
-    const double* rst_y;   // [nrst * npair * 2] analysis restart states (ua, ub)
-    const int* rst_k;      // [nrst * npair]
+    const double* rst_y;   // [nrst * npair * 2] analysis restart states (ua, ub), 0 before a lane starts
     const double* tw;      // [K] complex e^{-2 pi i t / K}
     const double* rtw;     // [K+1] complex e^{+2 pi i m / (2K)}
     const int* synth_units;
@@ -80,7 +105,7 @@ struct Tiling {
     int synth_lp = 1;
     int analys_lp = 8;
     int fw = 1;
-    int m_pairing = 0;
+    int m_pairing = 0;  // synthesis: 1 = orders m and M-m share a workgroup
     int split = 0;     // 0 = automatic
     int fft_rows = 0;  // latitude rows per FFT workgroup, 0 = automatic
 };
@@ -90,15 +115,17 @@ struct Plan {
     long nlm = 0;
     Tiling tiling;
     int split_used = 0;
+    int synth_wpg = 1;  // waves per synthesis workgroup for the unit order
     // host tables
     std::vector<double> x, w;                 // full grid
     std::vector<double> xp, sp, wq, wfull;    // per pair
     std::vector<double> beta, gamma;          // nlm
-    std::vector<double> start_y;              // (M+1) x npair
-    std::vector<int> start_k;
+    std::vector<double> start_y;              // (M+1) x npair: P_m^m mantissa (host emulation only)
+    std::vector<int> start_k;                 // its scaled exponent
+    std::vector<int> inj_j;                   // (M+1) x npair: lane start step
+    std::vector<double> inj_y;                // (M+1) x npair x 2: state entering it
     std::vector<int> segexp, segoff;
     std::vector<double> rst_y;
-    std::vector<int> rst_k;
     std::vector<double> tw, rtw;
     std::vector<int> synth_units, analys_units;
     std::vector<int> first_pair;              // per m: first latitude pair kept by the polar cut
@@ -118,6 +145,9 @@ int rows_per_block(const Plan& p);  // FFT rows per workgroup for a plan
 // Host plan construction (plan.cpp).
 Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err);
 int rebuild_units(Plan& p, std::string& err);     // units + restart states for the tiling
+// First / last start step of the lanes [i0, i1) of order m that start in
+// [lo, hi); false if none does.
+bool start_range(const Plan& p, int m, int i0, int i1, int lo, int hi, int& jmin, int& jmax);
 void build_image(Plan& p);                        // lays out the device buffer
 inline long lm_index(int L, int n, int m) { return (long)m * (2 * L + 1 - m) / 2 + n; }
 size_t align256(size_t v);

@@ -175,7 +175,10 @@ def shtn_legendre_flops(h):
 
 _TABLE_DTYPES = {0: np.float64, 1: np.float64, 2: np.float64, 3: np.float64, 4: np.float64,
                  5: np.float64, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.float64,
-                 10: np.int32, 11: np.int32, 12: np.int32, 13: np.int32, 14: np.int32}
+                 10: np.int32, 11: np.int32, 12: np.int32, 13: np.int32, 14: np.int32,
+                 15: np.int32, 16: np.float64}
+
+UNIT_INTS = 12  # ints per work unit in tables 11 and 12
 
 
 def shtn_plan_table(h, which):
@@ -322,7 +325,7 @@ class Plan:
         off = (-ptr) % 256
         shtn_plan_upload(self.handle, ptr + off, _stream_ptr(torch, self.device))
 
-    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=0, split=0, fft_rows=0):
+    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=2, split=0, fft_rows=0):
         shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, fw, m_pairing, split, fft_rows)
         self._upload()
 

@@ -1,7 +1,8 @@
 """Host-side tests of libshtn: exported symbols, argument validation and the
-plan tables, with a numpy emulation of the kernels' rescaled recurrence and
-underflow guard checked against the oracle.  No GPU is needed: plan
-construction is host code and no transform is called here.
+plan tables, with a numpy emulation of the kernels' algorithm (rescaled
+recurrence, lanes starting from plan-time states) checked against the oracle.
+No GPU is needed: plan construction is host code and no transform is called
+here.
 """
 import ctypes
 
@@ -12,7 +13,11 @@ import oracle
 from paper_1202_6522_amd import inputs
 from paper_1202_6522_amd import shtn as S
 
-T_XP, T_SP, T_WQ, T_BETA, T_GAMMA, T_STY, T_STK, T_SEGE, T_SEGO, T_RSTY, T_RSTK, T_AU, T_SU, T_TIL, T_FIRST = range(15)
+T_XP, T_SP, T_WQ, T_BETA, T_GAMMA, T_STY, T_STK, T_SEGE, T_SEGO, T_RSTY, T_RSTK, T_AU, T_SU, T_TIL, T_FIRST, \
+    T_INJJ, T_INJY = range(17)
+UI = S.UNIT_INTS
+# unit fields
+U_M, U_JS, U_JW, U_PB, U_J1, U_RST, U_ZERO = 3, 4, 5, 6, 7, 8, 9
 
 
 @pytest.fixture(scope="module")
@@ -77,7 +82,7 @@ def test_plan_grid_matches_oracle(nlat):
 
 
 def _tables(h):
-    return {k: S.shtn_plan_table(h, k) for k in range(15)}
+    return {k: S.shtn_plan_table(h, k) for k in range(17)}
 
 
 def test_beta_gamma_tables():
@@ -120,11 +125,8 @@ def test_start_values_scaled_exponents():
                                                                 (2.0 * np.arange(1, L + 1))))])
                         - np.log2(4 * np.pi))
         ref = logamm[:, None] + m * np.log2(sp)[None, :]
-        first = t[T_FIRST]
-        kept = np.arange(npair)[None, :] >= first[:, None]
-        # pairs inside the static polar cut start at exactly 0
-        assert np.all(sy[~kept] == 0) and np.all(sk[~kept] == 0)
-        got = np.log2(np.abs(np.where(kept, sy, 1.0))) - 256.0 * sk
+        kept = np.ones_like(sk, dtype=bool)
+        got = np.log2(np.abs(sy)) - 256.0 * sk
         err = np.abs(got - ref) / np.maximum(1, np.abs(ref))
         assert np.max(err[kept]) < 1e-12
         assert np.all(np.sign(sy[kept]) == np.broadcast_to((-1.0) ** m, sy.shape)[kept])
@@ -143,63 +145,65 @@ def test_start_values_scaled_exponents():
         S.shtn_plan_destroy(h)
 
 
-def emulate_legendre(t, L, M, nlat, Q=None, F=None, adjoint=False, track=None):
-    """numpy emulation of the kernels' per-lane algorithm: rescaled recurrence,
-    segment rescaling, underflow guard with zero contribution while k > 0,
-    mirror fold.  Synthesis if Q is given (returns F[m][lat]), analysis if F is
-    given (returns Q).  Vectorised over latitude pairs."""
-    npair = (nlat + 1) // 2
-    xp, wq, beta, gamma = t[T_XP], t[T_WQ], t[T_BETA], t[T_GAMMA]
-    sy = t[T_STY].reshape(M + 1, npair)
-    sk = t[T_STK].reshape(M + 1, npair)
+def _lane_walk(t, L, M, npair, m, upto=None):
+    """Yields (j, ua or ub, parity) along the kernels' per-lane recurrence for
+    order m: every lane holds 0 until its start step (a multiple of 8), where
+    it takes the state stored by the plan; segment shifts at multiples of 32.
+    Vectorised over latitude pairs."""
+    xp, beta = t[T_XP], t[T_BETA]
     sege, sego = t[T_SEGE], t[T_SEGO]
-    nlm = len(beta)
+    sj = t[T_INJJ].reshape(M + 1, npair)[m]
+    sy = t[T_INJY].reshape(M + 1, npair, 2)[m]
+    base = oracle.lm_index(L, m, m)
+    nj = L - m + 1 if upto is None else upto
+    ua = np.zeros(npair)
+    ub = np.zeros(npair)
+    for j in range(0, nj, 2):
+        if j > 0 and j % 32 == 0:
+            sc = 2.0 ** sege[sego[m] + j // 32]
+            ua *= sc
+            ub *= sc
+        if j % 8 == 0:
+            go = sj == j
+            ua = np.where(go, sy[:, 0], ua)
+            ub = np.where(go, sy[:, 1], ub)
+        ua = xp * ub + beta[base + j] * ua
+        yield j, ua
+        if j + 1 < L - m + 1 and j + 1 < nj:
+            ub = xp * ua + beta[base + j + 1] * ub
+            yield j + 1, ub
+
+
+def emulate_legendre(t, L, M, nlat, Q=None, F=None):
+    """numpy emulation of the kernels' per-lane algorithm: rescaled recurrence,
+    segment rescaling, lanes starting from the plan's stored states, mirror
+    fold.  Synthesis if Q is given (returns F[m][lat]), analysis if F is given
+    (returns Q)."""
+    npair = (nlat + 1) // 2
+    wq, gamma = t[T_WQ], t[T_GAMMA]
+    nlm = len(t[T_BETA])
     out = np.zeros((M + 1, nlat), complex) if Q is not None else np.zeros(nlm, complex)
     pairs = np.arange(npair)
     south = nlat - 1 - pairs
     for m in range(M + 1):
         base = oracle.lm_index(L, m, m)
-        nj = L - m + 1
-        ua = sy[m].copy()
-        ub = np.zeros(npair)
-        k = sk[m].copy()
         if Q is not None:
-            qs = gamma[base:base + nj] * Q[base:base + nj]
             E = np.zeros(npair, complex)
             O = np.zeros(npair, complex)
+            for j, u in _lane_walk(t, L, M, npair, m):
+                if j % 2 == 0:
+                    E += gamma[base + j] * Q[base + j] * u
+                else:
+                    O += gamma[base + j] * Q[base + j] * u
+            out[m, pairs] = E + O
+            out[m, south] = E - O
         else:
             fe = wq * (F[m, pairs] + F[m, south])
             fo = wq * (F[m, pairs] - F[m, south])
-        for j in range(0, nj, 2):
-            if j > 0 and j % 32 == 0:
-                sc = 2.0 ** sege[sego[m] + j // 32]
-                ua *= sc
-                ub *= sc
-            if j % 4 == 0:
-                msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
-                ua[msk] *= 2.0**-256
-                ub[msk] *= 2.0**-256
-                k[msk] -= 1
-            ua = xp * ub + beta[base + j] * ua
-            va = np.where(k == 0, ua, 0.0)
-            if track is not None:
-                track.append(np.abs(ua[k == 0]))
-            if Q is not None:
-                E += qs[j] * va
-            else:
-                out[base + j] = gamma[base + j] * np.sum(fe * va)
-            if j + 1 < nj:
-                ub = xp * ua + beta[base + j + 1] * ub
-                vb = np.where(k == 0, ub, 0.0)
-                if Q is not None:
-                    O += qs[j + 1] * vb
-                else:
-                    out[base + j + 1] = gamma[base + j + 1] * np.sum(fo * vb)
-        if Q is not None:
-            out[m, pairs] = E + O
-            out[m, south] = E - O
-        elif m == 0:
-            out[base:base + nj] = out[base:base + nj].real
+            for j, u in _lane_walk(t, L, M, npair, m):
+                out[base + j] = gamma[base + j] * np.sum((fe if j % 2 == 0 else fo) * u)
+            if m == 0:
+                out[base:base + L + 1] = out[base:base + L + 1].real
     return out
 
 
@@ -263,34 +267,18 @@ def test_emulated_guard_at_high_degree():
 def _emulate_orders(t, L, M, nlat, Q, ms):
     """emulate_legendre restricted to a few orders (returns {m: F_m[lat]})."""
     npair = (nlat + 1) // 2
-    xp, beta, gamma = t[T_XP], t[T_BETA], t[T_GAMMA]
-    sy = t[T_STY].reshape(M + 1, npair)
-    sk = t[T_STK].reshape(M + 1, npair)
-    sege, sego = t[T_SEGE], t[T_SEGO]
+    gamma = t[T_GAMMA]
     pairs = np.arange(npair)
     out = {}
     for m in ms:
         base = oracle.lm_index(L, m, m)
-        nj = L - m + 1
-        ua, ub, k = sy[m].copy(), np.zeros(npair), sk[m].copy()
-        qs = gamma[base:base + nj] * Q[base:base + nj]
         E = np.zeros(npair, complex)
         O = np.zeros(npair, complex)
-        for j in range(0, nj, 2):
-            if j > 0 and j % 32 == 0:
-                sc = 2.0 ** sege[sego[m] + j // 32]
-                ua *= sc
-                ub *= sc
-            if j % 4 == 0:
-                msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
-                ua[msk] *= 2.0**-256
-                ub[msk] *= 2.0**-256
-                k[msk] -= 1
-            ua = xp * ub + beta[base + j] * ua
-            E += qs[j] * np.where(k == 0, ua, 0.0)
-            if j + 1 < nj:
-                ub = xp * ua + beta[base + j + 1] * ub
-                O += qs[j + 1] * np.where(k == 0, ub, 0.0)
+        for j, u in _lane_walk(t, L, M, npair, m):
+            if j % 2 == 0:
+                E += gamma[base + j] * Q[base + j] * u
+            else:
+                O += gamma[base + j] * Q[base + j] * u
         F = np.zeros(nlat, complex)
         F[pairs] = E + O
         F[nlat - 1 - pairs] = E - O
@@ -299,46 +287,61 @@ def _emulate_orders(t, L, M, nlat, Q, ms):
 
 
 def test_emulated_values_stay_in_range():
-    # with k = 0 the carried values never approach under- or overflow
+    # once started, the carried values stay far from under- and overflow
     L = 1023
     h = S.shtn_plan(L, L, L + 1, 2048)
     try:
         t = _tables(h)
         npair = (L + 2) // 2
-        sub = {}
-        for key in (T_XP, T_WQ):
-            sub[key] = t[key]
-        track = []
-        ms = [0, 1, 300, 700, 1000, 1023]
-        Q = np.ones(S.shtn_nlm(h), complex)
-        _ = _emulate_orders(t, L, L, L + 1, Q, ms)
-        # range check directly on the recurrence of the extreme orders
-        for m in ms:
-            base = oracle.lm_index(L, m, m)
-            sy = t[T_STY].reshape(L + 1, npair)[m]
-            sk = t[T_STK].reshape(L + 1, npair)[m]
-            ua, ub, k = sy.copy(), np.zeros(npair), sk.copy()
+        for m in [0, 1, 300, 700, 1000, 1023]:
             lo, hi = np.inf, 0.0
-            for j in range(0, L - m + 1):
-                if j % 2 == 0:
-                    if j > 0 and j % 32 == 0:
-                        sc = 2.0 ** t[T_SEGE][t[T_SEGO][m] + j // 32]
-                        ua *= sc
-                        ub *= sc
-                    if j % 4 == 0:
-                        msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
-                        ua[msk] *= 2.0**-256
-                        ub[msk] *= 2.0**-256
-                        k[msk] -= 1
-                    ua = t[T_XP] * ub + t[T_BETA][base + j] * ua
-                    v = np.abs(ua[(k == 0) & (ua != 0)])
-                else:
-                    ub = t[T_XP] * ua + t[T_BETA][base + j] * ub
-                    v = np.abs(ub[(k == 0) & (ub != 0)])
+            for j, u in _lane_walk(t, L, L, npair, m):
+                v = np.abs(u[u != 0])
                 if v.size:
                     lo, hi = min(lo, v.min()), max(hi, v.max())
             assert hi < 1e3, (m, hi)
             assert lo > 2.0**-900, (m, lo)
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+def test_lane_starts_against_long_double_oracle():
+    # Sec. 3.5 guard and Sec. 3.1 polar threshold at plan time: before its
+    # start step a lane's |P_n^m| stays below 2^-200, the block of 8 steps
+    # from its start reaches it, and the stored state continues the
+    # recurrence onto the true P_n^m (long-double oracle, whose exponent
+    # range covers these values at lmax 1023).
+    L, nlat = 1023, 1024
+    h = S.shtn_plan(L, L, nlat, 2048)
+    try:
+        t = _tables(h)
+        npair = nlat // 2
+        x = t[T_XP]
+        sj = t[T_INJJ].reshape(L + 1, npair)
+        sy = t[T_INJY].reshape(L + 1, npair, 2)
+        first = t[T_FIRST]
+        for m in (0, 5, 200, 512, 800, 1000, 1023):
+            nj = L - m + 1
+            base = oracle.lm_index(L, m, m)
+            i0 = int(first[m])
+            assert np.all(sj[m, :i0] == nj)         # cut pairs never start
+            assert np.all(sj[m, i0:] < nj) and np.all(sj[m, i0:] % 8 == 0)
+            for i in sorted({i0, min(i0 + 1, npair - 1), (i0 + npair) // 2, npair - 1}):
+                j = int(sj[m, i])
+                P = oracle.plm(L, m, np.array([x[i]]), precision="ld")[:, 0]
+                Pm = np.abs(P[base:base + nj])
+                assert np.all(Pm[:j] < 2.0**-200), (m, i)
+                # (the plan compares binary exponents: the threshold is met from 2^-201 on)
+                assert Pm[j:j + 8].max() >= 2.0**-201, (m, i)
+                # two steps from the stored state
+                ua, ub = sy[m, i]
+                ua = x[i] * ub + t[T_BETA][base + j] * ua
+                got = [ua * t[T_GAMMA][base + j]]
+                if j + 1 < nj:
+                    ub = x[i] * ua + t[T_BETA][base + j + 1] * ub
+                    got.append(ub * t[T_GAMMA][base + j + 1])
+                ref = P[base + j:base + j + len(got)]
+                np.testing.assert_allclose(got, ref, rtol=1e-11)
     finally:
         S.shtn_plan_destroy(h)
 
@@ -350,63 +353,73 @@ def test_restart_states_match_recurrence():
         t = _tables(h)
         til = t[T_TIL]
         split = int(til[4])
-        au = t[T_AU].reshape(-1, 8)
+        au = t[T_AU].reshape(-1, UI)
         npair = 128
+        sj = t[T_INJJ].reshape(L + 1, npair)
         # every order's degree range is covered exactly once
         cover = {}
         for u in au:
-            m, j0, j1, r = u[3], u[5], u[6], u[7]
-            cover.setdefault(int(m), []).append((int(j0), int(j1)))
+            m, js, jw, j0, j1, r = (int(v) for v in u[[U_M, U_JS, U_JW, U_PB, U_J1, U_RST]])
+            cover.setdefault(m, []).append((j0, j1))
             assert (r < 0) == (j0 == 0)
             assert j0 % split == 0
+            # the unit starts at a segment boundary no later than its first
+            # started lane, and its window covers every start inside it
+            assert j0 <= js <= j1 and (js - j0) % 32 == 0
+            lanes = sj[m]
+            assert not np.any((lanes >= j0) & (lanes < js)) or js == j0
+            inside = lanes[(lanes >= js) & (lanes < j1)]
+            if inside.size:
+                assert jw >= inside.max()
+            if js > j0:
+                assert not np.any(lanes < js)
         for m in range(L + 1):
             segs = sorted(cover[m])
             assert segs[0][0] == 0 and segs[-1][1] == L - m + 1
             assert all(a[1] == b[0] for a, b in zip(segs, segs[1:]))
-        lens = au[:, 6] - au[:, 5]
-        assert np.all(np.diff(lens) <= 0), "units are ordered longest first"
-        # a restart state equals the recurrence run from the start value
+        cost = au[:, U_J1] - au[:, U_JS]
+        assert np.all(np.diff(cost) <= 0), "units are ordered longest first"
+        # a restart state equals the recurrence run from the lane starts
         ry = t[T_RSTY].reshape(-1, npair, 2)
-        rk = t[T_RSTK].reshape(-1, npair)
-        u = au[(au[:, 7] >= 0)][0]
-        m, j0, r = int(u[3]), int(u[5]), int(u[7])
-        base = oracle.lm_index(L, m, m)
-        sy = t[T_STY].reshape(L + 1, npair)[m]
-        sk = t[T_STK].reshape(L + 1, npair)[m]
-        ua, ub, k = sy.copy(), np.zeros(npair), sk.copy()
-        for j in range(0, j0, 2):
-            if j > 0 and j % 32 == 0:
-                sc = 2.0 ** t[T_SEGE][t[T_SEGO][m] + j // 32]
-                ua *= sc
-                ub *= sc
-            if j % 4 == 0:
-                msk = (k > 0) & ((np.abs(ua) >= 1) | (np.abs(ub) >= 1))
-                ua[msk] *= 2.0**-256
-                ub[msk] *= 2.0**-256
-                k[msk] -= 1
-            ua = t[T_XP] * ub + t[T_BETA][base + j] * ua
-            ub = t[T_XP] * ua + t[T_BETA][base + j + 1] * ub
-        # (numpy rounds the products separately; the host uses fused multiply-adds)
-        np.testing.assert_allclose(ry[r, :, 0], ua, rtol=0, atol=1e-13 * np.max(np.abs(ua)))
-        np.testing.assert_allclose(ry[r, :, 1], ub, rtol=0, atol=1e-13 * np.max(np.abs(ub)))
-        np.testing.assert_array_equal(rk[r], k)
+        assert t[T_RSTK].size == 0
+        for u in au[au[:, U_RST] >= 0][:6]:
+            m, j0, r = int(u[U_M]), int(u[U_PB]), int(u[U_RST])
+            last = {}
+            for j, v in _lane_walk(t, L, L, npair, m, upto=j0):
+                last[j % 2] = v
+            sc = 2.0 ** t[T_SEGE][t[T_SEGO][m] + j0 // 32]
+            live = sj[m] < j0
+            # (numpy rounds the products separately; the host uses fused multiply-adds)
+            for k in (0, 1):
+                want = np.where(live, last[k] * sc, 0.0)
+                np.testing.assert_allclose(ry[r, :, k], want, rtol=0,
+                                           atol=1e-12 * max(np.max(np.abs(want)), 1e-300))
     finally:
         S.shtn_plan_destroy(h)
 
 
 def test_synthesis_units_cover_all_work():
-    for (L, M, nlat, pairing) in [(31, 31, 32, 1), (40, 33, 51, 1), (40, 33, 51, 0)]:
-        h = S.shtn_plan(L, M, nlat, 128)
+    for (L, M, nlat, pairing) in [(31, 31, 32, 1), (40, 33, 51, 1), (40, 33, 51, 0), (300, 300, 301, 1)]:
+        h = S.shtn_plan(L, M, nlat, 1024)
         try:
-            S.shtn_plan_set_tiling(h, 1, 1, 1, pairing, 0, 0)
-            su = S.shtn_plan_table(h, T_SU).reshape(-1, 8)
+            S.shtn_plan_set_tiling(h, 1, 8 if nlat > 256 else 1, 1, pairing, 0, 0)
+            t = _tables(h)
+            su = t[T_SU].reshape(-1, UI)
             npair = (nlat + 1) // 2
+            sj = t[T_INJJ].reshape(M + 1, npair)
             seen = np.zeros((M + 1, npair), int)
             for u in su:
-                for mm in (u[3], u[4]):
-                    if mm >= 0:
-                        pb = u[5]
-                        seen[mm, pb:min(pb + 64, npair)] += 1
+                m = u[U_M]
+                if m < 0:
+                    continue
+                pb = u[U_PB]
+                blk = sj[m, pb:min(pb + 64, npair)]
+                seen[m, pb:min(pb + 64, npair)] += 1
+                started = blk[blk < L - m + 1]
+                if u[U_ZERO]:
+                    assert started.size == 0
+                else:
+                    assert u[U_JS] == started.min() and u[U_JW] == started.max()
             assert np.all(seen == 1)
         finally:
             S.shtn_plan_destroy(h)
