@@ -126,7 +126,7 @@ double shtn_legendre_flops(shtn_plan_t plan);
  * states (double, nrestart x npair x 2), 10 empty (kept for numbering),
  * 11 analysis units (int32 x 12 each), 12 synthesis units (int32 x 12 each),
  * 13 tiling (int32 x 8: synth_lp, analys_lp, fw, m_pairing, split, fft_rows,
- * segment length, start checkpoint spacing), 14 first latitude pair that
+ * analys_waves, start checkpoint spacing), 14 first latitude pair that
  * ever reaches the polar threshold, per m (int32), 15 start step of every
  * (order, pair) lane (int32, (mmax+1) x npair; lmax-m+1 = never), 16 the
  * recurrence state entering that step (double, (mmax+1) x npair x 2).
@@ -135,16 +135,19 @@ double shtn_legendre_flops(shtn_plan_t plan);
 long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
 
 /* Tiling of the Legendre kernels (the runtime-tuning knob of Sec. 3.2):
- * synth_lp (1, 2, 4) / analys_lp (1, 2, 4, 8) latitude pairs per lane, fields per
- * wave fw (1, 2; fw = 2 needs lp <= 4), m_pairing (synthesis: 0 one workgroup per
- * order, 1 orders m and mmax-m share a workgroup so that all workgroups carry
- * equal work),
- * split (analysis n-range piece length, a multiple of 32; 0 = automatic),
- * fft_rows (latitude rows per FFT workgroup, 0 = automatic).
- * Rebuilds the unit lists and restart tables: re-upload afterwards.
- * Returns SHTN_EINVAL for unsupported values. */
-int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
-                         int split, int fft_rows);
+ * synth_lp (1, 2, 4) latitude pairs per synthesis lane; analys_lp (1, 2, 4, 8)
+ * pairs per analysis lane and analys_waves (1, 2, 4) waves per analysis unit,
+ * which together must cover every latitude pair (64 analys_lp analys_waves >=
+ * ceil(nlat/2); built combinations: waves 1 with lp 1-8, 2 with lp 2-8, 4
+ * with lp 4 or 8); fields per wave fw (1, 2; fw = 2 needs synth_lp <= 4,
+ * analys_lp <= 4 and analys_waves <= 2); m_pairing (synthesis: 0 one
+ * workgroup per order, 1 orders m and mmax-m share a workgroup so that all
+ * workgroups carry equal work); split (analysis n-range piece length, a
+ * multiple of 32; 0 = automatic); fft_rows (latitude rows per FFT workgroup,
+ * 0 = as many as fit).  Rebuilds the unit lists and restart tables:
+ * re-upload afterwards.  Returns SHTN_EINVAL for unsupported values. */
+int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int analys_waves, int fw,
+                         int m_pairing, int split, int fft_rows);
 
 /* ---- batches of fields with different truncations (one launch per stage) ----
  *

@@ -33,7 +33,8 @@ int hip_error(int e, const char* where)
 
 int rows_per_block(const Plan& p)
 {
-    const int cap = std::max(1, 4096 / p.K);  // 64 KB of LDS per workgroup
+    // rows of K points that fill one FFT workgroup (1024 points per wave)
+    const int cap = fft_rows_cap(p.K);
     int r = p.tiling.fft_rows > 0 ? p.tiling.fft_rows : cap;
     if (r > cap) r = cap;
     if (r > p.nlat) r = p.nlat;
@@ -119,7 +120,7 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     if (rc) return rc;
     const Plan& p = *plan->p;
     if (p.npair > kMaxAnalysPairs)
-        return fail(SHTN_EUNSUPPORTED, "analysis supports at most 1024 latitudes");
+        return fail(SHTN_EUNSUPPORTED, "analysis supports at most 4096 latitudes");
     double* F = (double*)work;
     FftLaunch f{};
     f.plans = dplan(p);
@@ -147,6 +148,7 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     l.nfields = nfields;
     l.adjoint = adjoint;
     l.lp = p.tiling.analys_lp;
+    l.waves = p.tiling.analys_waves;
     l.fw = p.tiling.fw;
     {
         ProfScope ps(PK_LEG_ANALYS, stream);
@@ -245,6 +247,9 @@ int shtn_plan_upload(shtn_plan_t plan, void* dev_buf, void* stream)
     d.synth_lp = p.tiling.synth_lp;
     d.analys_lp = p.tiling.analys_lp;
     d.fw = p.tiling.fw;
+    const FLayout fl = f_layout(p.M, p.nlat);
+    d.f_ts = fl.ts;
+    d.f_size = fl.size;
     std::memcpy(p.image.data(), &d, sizeof(DevPlan));
     hipError_t e = hipMemcpyAsync(dev_buf, p.image.data(), p.image.size(), hipMemcpyHostToDevice,
                                   (hipStream_t)stream);
@@ -320,7 +325,7 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     const void* src = nullptr;
     size_t n = 0;
     int tiling[8] = {p.tiling.synth_lp, p.tiling.analys_lp, p.tiling.fw, p.tiling.m_pairing,
-                     p.split_used, rows_per_block(p), kSegLen, kInject};
+                     p.split_used, rows_per_block(p), p.tiling.analys_waves, kInject};
     switch (which) {
     case 0: src = p.xp.data(); n = p.xp.size() * 8; break;
     case 1: src = p.sp.data(); n = p.sp.size() * 8; break;
@@ -345,25 +350,32 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     return (long)n;
 }
 
-int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int fw, int m_pairing,
-                         int split, int fft_rows)
+int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int analys_waves, int fw,
+                         int m_pairing, int split, int fft_rows)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
     Plan& p = *plan->p;
     auto okl = [](int v) { return v == 1 || v == 2 || v == 4 || v == 8; };
     if (!okl(synth_lp) || !okl(analys_lp)) return fail(SHTN_EINVAL, "lp must be 1, 2, 4 or 8");
     if (synth_lp > 4) return fail(SHTN_EINVAL, "synth_lp must be 1, 2 or 4");
+    if (!(analys_waves == 1 || analys_waves == 2 || analys_waves == 4))
+        return fail(SHTN_EINVAL, "analys_waves must be 1, 2 or 4");
+    // analysis kernels built: waves 1 (lp 1-8), 2 (lp 2-8), 4 (lp 4, 8); fw 2 with lp <= 4
+    if ((analys_waves == 2 && analys_lp < 2) || (analys_waves == 4 && analys_lp < 4))
+        return fail(SHTN_EINVAL, "analys_lp too small for analys_waves");
     if (!(fw == 1 || fw == 2)) return fail(SHTN_EINVAL, "fw must be 1 or 2");
     if (fw == 2 && synth_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs synth_lp <= 4");
-    if (fw == 2 && analys_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs analys_lp <= 4");
-    if (64 * analys_lp < p.npair && p.npair <= kMaxAnalysPairs)
-        return fail(SHTN_EINVAL, "analys_lp too small: one analysis wave must cover all latitude pairs");
+    if (fw == 2 && (analys_lp > 4 || analys_waves > 2))
+        return fail(SHTN_EINVAL, "fw=2 needs analys_lp <= 4 and analys_waves <= 2");
+    if (64 * analys_lp * analys_waves < p.npair && p.npair <= kMaxAnalysPairs)
+        return fail(SHTN_EINVAL, "analysis unit too small: 64 analys_lp analys_waves must cover all latitude pairs");
     if (m_pairing < 0 || m_pairing > 1) return fail(SHTN_EINVAL, "m_pairing must be 0 or 1");
     if (split < 0 || split % kSegLen) return fail(SHTN_EINVAL, "split must be a multiple of 32");
     if (fft_rows < 0) return fail(SHTN_EINVAL, "fft_rows must be >= 0");
     Tiling old = p.tiling;
     p.tiling.synth_lp = synth_lp;
     p.tiling.analys_lp = analys_lp;
+    p.tiling.analys_waves = analys_waves;
     p.tiling.fw = fw;
     p.tiling.m_pairing = m_pairing;
     p.tiling.split = split;

@@ -38,16 +38,17 @@ struct BatchTiling {
 };
 
 struct AnalysClass {
-    int lp, fw;
+    int lp, waves, fw;
     size_t first;  // first unit (index into analys_units / kUnitInts)
     int count;
 };
 
-int analys_lp_for(int npair)
+// analysis class of a plan: (pairs per lane, waves), encoded as lp * 16 + waves
+int analys_class(int npair)
 {
-    int lp = 1;
-    while (64 * lp < npair && lp < 8) lp *= 2;
-    return lp;
+    int lp, w;
+    analys_shape(npair, lp, w);
+    return lp * 16 + w;
 }
 
 }  // namespace
@@ -67,6 +68,7 @@ struct shtn_batch_s {
     std::vector<int> synth_units, analys_units, rowblocks;
     std::vector<AnalysClass> classes;
     int synth_wpg = 1;
+    int fft_kmax = 1;  // longest FFT rows of the batch (sizes the FFT's LDS)
     // device image
     std::vector<unsigned char> image;
     size_t off_plans = 0, off_slot_plan = 0, off_q = 0, off_g = 0, off_f = 0, off_s = 0,
@@ -152,29 +154,33 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
     for (auto& x : su) b.synth_units.insert(b.synth_units.end(), x.u, x.u + kUnitInts);
     b.synth_wpg = std::min(t.synth_lp == 1 && t.fw == 1 ? 16 : 8, maxblk);
 
-    // ---- analysis units, per pairs-per-lane class ----
-    int lp_max = 1;
-    for (auto* p : b.plans) lp_max = std::max(lp_max, analys_lp_for(p->npair));
-    std::vector<int> lps;
+    // ---- analysis units, per (pairs per lane, waves) class ----
+    int cls_max = 0, npair_max = 0;
+    for (auto* p : b.plans)
+        if (p->npair > npair_max) {
+            npair_max = p->npair;
+            cls_max = analys_class(p->npair);
+        }
+    std::vector<int> classes;
     if (t.analys_merge) {
-        lps.push_back(lp_max);
+        classes.push_back(cls_max);
     } else {
-        for (int lp = 8; lp >= 1; lp /= 2)
-            for (auto* p : b.plans)
-                if (analys_lp_for(p->npair) == lp) {
-                    lps.push_back(lp);
-                    break;
-                }
+        for (auto* p : b.plans) {
+            const int c = analys_class(p->npair);
+            if (std::find(classes.begin(), classes.end(), c) == classes.end()) classes.push_back(c);
+        }
+        std::sort(classes.rbegin(), classes.rend());
     }
     b.analys_units.clear();
     b.classes.clear();
-    for (int lp : lps) {
-        const int fw = lp >= 8 ? 1 : t.fw;  // no two-field kernel at 8 pairs per lane
+    for (int cl : classes) {
+        const int lp = cl / 16, waves = cl % 16;
+        // two-field kernels exist for lp <= 4 and waves <= 2
+        const int fw = (lp >= 8 || waves > 2) ? 1 : t.fw;
         std::vector<SU> au;
         for (size_t pi = 0; pi < b.plans.size(); pi++) {
             const Plan& p = *b.plans[pi];
-            const int need = analys_lp_for(p.npair);
-            if (t.analys_merge ? false : need != lp) continue;
+            if (!t.analys_merge && analys_class(p.npair) != cl) continue;
             for (int fg = range[pi].first; fg < range[pi].second; fg += fw) {
                 const int nf = std::min(fw, range[pi].second - fg);
                 const size_t nu = p.analys_units.size() / kUnitInts;
@@ -190,12 +196,14 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
             }
         }
         std::stable_sort(au.begin(), au.end(), [](const SU& a, const SU& c) { return a.cost > c.cost; });
-        AnalysClass c{lp, fw, b.analys_units.size() / kUnitInts, (int)au.size()};
+        AnalysClass c{lp, waves, fw, b.analys_units.size() / kUnitInts, (int)au.size()};
         for (auto& x : au) b.analys_units.insert(b.analys_units.end(), x.u, x.u + kUnitInts);
         b.classes.push_back(c);
     }
 
     // ---- FFT row blocks: {slot, plan, first row, rows} ----
+    b.fft_kmax = 1;
+    for (auto* p : b.plans) b.fft_kmax = std::max(b.fft_kmax, p->K);
     b.rowblocks.clear();
     for (int s = 0; s < ns; s++) {
         const Plan& p = *b.plans[b.slot_plan[s]];
@@ -283,6 +291,7 @@ int run_synth(const shtn_batch_s& b, const double* Q, double* grid, void* work, 
     FftLaunch f{};
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
+    f.K = b.fft_kmax;
     f.nblocks = (int)(b.rowblocks.size() / 4);
     f.grid_y = 1;
     f.g_off = dev_at<const long>(b, b.off_g);
@@ -307,6 +316,7 @@ int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work,
     FftLaunch f{};
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
+    f.K = b.fft_kmax;
     f.nblocks = (int)(b.rowblocks.size() / 4);
     f.grid_y = 1;
     f.g_off = dev_at<const long>(b, b.off_g);
@@ -334,6 +344,7 @@ int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work,
         l.nfields = ns;
         l.adjoint = 0;
         l.lp = c.lp;
+        l.waves = c.waves;
         l.fw = c.fw;
         {
             ProfScope ps(PK_LEG_ANALYS, stream);
@@ -463,7 +474,7 @@ shtn_batch_t shtn_batch(int nfields, const shtn_plan_t* plans)
             Plan* p = plans[f]->p;
             if (p->npair > kMaxAnalysPairs) {
                 delete b;
-                set_error(SHTN_EUNSUPPORTED, "batch fields support at most 1024 latitudes");
+                set_error(SHTN_EUNSUPPORTED, "batch fields support at most 4096 latitudes");
                 return nullptr;
             }
             auto it = std::find(b->plans.begin(), b->plans.end(), p);
@@ -496,7 +507,7 @@ shtn_batch_t shtn_batch(int nfields, const shtn_plan_t* plans)
             b->slot_q.push_back((long)b->q_off[b->slot_field[s]]);
             b->slot_g.push_back((long)b->g_off[b->slot_field[s]]);
             b->slot_f.push_back((long)fo);
-            fo += align256((size_t)(p.M + 1) * p.nlat * 16) / 8;
+            fo += align256((size_t)f_layout(p.M, p.nlat).size * 16) / 8;
             b->max_nlm = std::max(b->max_nlm, p.nlm);
         }
         b->work_f_doubles = fo;

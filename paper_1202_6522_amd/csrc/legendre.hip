@@ -35,7 +35,7 @@ struct LegArgs {
     const DevPlan* plans;
     const int* units;
     const long* q_off;  // per field: spectrum offset in doubles (null: f * 2 nlm)
-    const long* f_off;  // per field: F offset in doubles (null: f * 2 (M+1) nlat)
+    const long* f_off;  // per field: F offset in doubles (null: f * 2 f_size)
     const double* in;
     double* out;
     int nfields;
@@ -49,12 +49,19 @@ __device__ __forceinline__ long field_q_off(const LegArgs& a, int f, long nlm)
     return a.q_off ? ((clp)a.q_off)[f] : (long)f * 2 * nlm;
 }
 
-__device__ __forceinline__ long field_f_off(const LegArgs& a, int f, int M, int nlat)
+__device__ __forceinline__ long field_f_off(const LegArgs& a, int f, long fsize)
 {
-    return a.f_off ? ((clp)a.f_off)[f] : (long)f * 2 * (M + 1) * nlat;
+    return a.f_off ? ((clp)a.f_off)[f] : (long)f * 2 * fsize;
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
+
+// Complex offset of F_m(theta_i) in a field's longitude coefficients (tiles
+// of kFTile latitudes, see f_layout).
+__device__ __forceinline__ long f_index(long ts, int m, int i)
+{
+    return (long)(i >> kFTileLg) * ts + m * kFTile + (i & (kFTile - 1));
+}
 
 // ---------------------------------------------------------------------------
 // Spectrum rescaling: Qs = gamma * Q (complex), per field.
@@ -256,8 +263,8 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
     const int nf = min(U[U_NF], a.nfields - field0);
     cplan P = (cplan)a.plans + U[U_PLAN];
     const int L = P->L, nlat = P->nlat, npair = P->npair;
+    const long fts = P->f_ts;
     const long nlm = P->nlm;
-    const int M = P->M;
     const int pb = U[U_PB];
     long qoff[FW];
     long foff[FW];
@@ -265,7 +272,7 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
     for (int f = 0; f < FW; f++) {
         const int ff = field0 + min(f, nf - 1);
         qoff[f] = field_q_off(a, ff, nlm);
-        foff[f] = field_f_off(a, ff, M, nlat);
+        foff[f] = field_f_off(a, ff, P->f_size);
     }
 
     if (U[U_ZERO]) {
@@ -278,9 +285,9 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
 #pragma unroll
             for (int f = 0; f < FW; f++) {
                 if (f >= nf) continue;
-                double* F = a.out + foff[f] + 2 * ((size_t)m * nlat);
-                *(double2*)(F + 2 * pair) = make_double2(0.0, 0.0);
-                *(double2*)(F + 2 * is) = make_double2(0.0, 0.0);
+                double* F = a.out + foff[f];
+                *(double2*)(F + 2 * f_index(fts, m, pair)) = make_double2(0.0, 0.0);
+                *(double2*)(F + 2 * f_index(fts, m, is)) = make_double2(0.0, 0.0);
             }
         }
         return;
@@ -390,12 +397,12 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
 #pragma unroll
         for (int f = 0; f < FW; f++) {
             if (f >= nf) continue;
-            double* F = a.out + foff[f] + 2 * ((size_t)m * nlat);
-            *(double2*)(F + 2 * pair) =
+            double* F = a.out + foff[f];
+            *(double2*)(F + 2 * f_index(fts, m, pair)) =
                 make_double2(sc * (s.er[p][f] + s.orr[p][f]), sc * (s.ei[p][f] + s.oi[p][f]));
             if (is != pair)
-                *(double2*)(F + 2 * is) = make_double2(sc * (s.er[p][f] - s.orr[p][f]),
-                                                       sc * (s.ei[p][f] - s.oi[p][f]));
+                *(double2*)(F + 2 * f_index(fts, m, is)) = make_double2(sc * (s.er[p][f] - s.orr[p][f]),
+                                                                        sc * (s.ei[p][f] - s.oi[p][f]));
         }
     }
     // keeps the prefetch loads alive; nfields is never negative
@@ -417,24 +424,25 @@ struct AState {
 // zero state, so it adds exactly 0 whatever its inputs.
 template <int LP, int FW>
 __device__ __forceinline__ void analys_inputs(AState<LP, FW>& s, const double* const (&F)[FW], int nlat,
-                                              int npair, int adjoint, const double* wq)
+                                              long fts, int m, int pb, int npair, int adjoint,
+                                              const double* wq)
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int p = 0; p < LP; p++) {
-        const int pair = p * 64 + lane;
+        const int pair = pb + p * 64 + lane;
         const bool act = pair < npair;
         const int pc = act ? pair : 0;
         const bool middle = (nlat & 1) && pc == npair - 1;
         const double wt = !act ? 0.0 : (adjoint ? (middle ? 0.5 : 1.0) : wq[pc]);
 #pragma unroll
         for (int f = 0; f < FW; f++) {
-            const double2 fn = *(const double2*)(F[f] + 2 * pc);
-            const double2 fs = *(const double2*)(F[f] + 2 * (nlat - 1 - pc));
-            s.ger[p][f] = wt * (fn.x + fs.x);
-            s.gei[p][f] = wt * (fn.y + fs.y);
-            s.gor[p][f] = wt * (fn.x - fs.x);
-            s.goi[p][f] = wt * (fn.y - fs.y);
+            const double2 vn = *(const double2*)(F[f] + 2 * f_index(fts, m, pc));
+            const double2 vs = *(const double2*)(F[f] + 2 * f_index(fts, m, nlat - 1 - pc));
+            s.ger[p][f] = wt * (vn.x + vs.x);
+            s.gei[p][f] = wt * (vn.y + vs.y);
+            s.gor[p][f] = wt * (vn.x - vs.x);
+            s.goi[p][f] = wt * (vn.y - vs.y);
         }
     }
 }
@@ -470,20 +478,24 @@ __device__ __forceinline__ void analys_step(AState<LP, FW>& s, int t, double b,
     }
 }
 
-// Each lane's partial sums go straight to LDS, one row of 64 lanes per
-// (degree, field, re/im); every 16/FW degrees one pass sums the 32 rows
-// (padded rows: the column reads are free of bank conflicts).  No
-// accumulators stay in registers.
-template <int LP, int FW>
-__global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
+// Each lane's partial sums go straight to LDS, one row per (degree, field,
+// re/im) with a column per thread of the workgroup; every 16/FW degrees one
+// pass sums the 32 rows (2W threads per row, padded rows).  No accumulators
+// stay in registers.  A workgroup of W waves covers 64 LP W latitude pairs:
+// wave w takes pairs [64 LP w, 64 LP (w + 1)); a wave none of whose
+// latitudes has started writes zero rows instead of computing.
+template <int LP, int FW, int W>
+__global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
 {
     constexpr int C = kChunk;       // degrees per beta block load
     constexpr int SC = kChunk / FW; // degrees per reduction
     constexpr int NV = 2 * SC * FW; // rows reduced per pass
-    static_assert(NV == 32, "two lanes per row");
+    constexpr int NT = 64 * W;      // threads = columns
+    constexpr int PR = 2 * W;       // threads per row
+    static_assert(NV * PR == NT, "the threads cover the rows");
     static_assert(kSegLen % C == 0, "chunks tile a segment");
     static_assert(SC % kInject == 0, "lanes start at reduction-block boundaries or inside them");
-    __shared__ double red[NV][65];
+    __shared__ double red[NV][NT + 1];
 
     cip U = (cip)a.units + (size_t)blockIdx.x * kUnitInts;
     const int m = U[U_M];
@@ -492,9 +504,13 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
     if (field0 >= a.nfields) return;
     const int nf = min(U[U_NF], a.nfields - field0);
     cplan P = (cplan)a.plans + U[U_PLAN];
-    const int L = P->L, M = P->M, nlat = P->nlat, npair = P->npair;
+    const int L = P->L, nlat = P->nlat, npair = P->npair;
+    const long fts = P->f_ts;
     const long nlm = P->nlm;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int pb = wv * 64 * LP;  // first latitude pair of this wave
     const int j0 = U[U_PB], j1 = U[U_J1], js0 = U[U_JS], jwin = U[U_JW], rst = U[U_RST];
     const long base = (long)m * (2 * L + 1 - m) / 2 + m;
     const int nj = L - m + 1;
@@ -507,39 +523,46 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
     for (int f = 0; f < FW; f++) {
         const int ff = field0 + min(f, nf - 1);
         qoff[f] = field_q_off(a, ff, nlm);
-        foff[f] = field_f_off(a, ff, M, nlat);
+        foff[f] = field_f_off(a, ff, P->f_size);
     }
 
     // degrees before the first started lane: every term is dropped
-    for (int j = j0 + (lane >> 1); j < js0; j += 32) {
+    for (int j = j0 + (tid >> 1); j < js0; j += NT / 2) {
 #pragma unroll
         for (int f = 0; f < FW; f++)
-            if (f < nf) a.out[qoff[f] + 2 * (base + j) + (lane & 1)] = 0.0;
+            if (f < nf) a.out[qoff[f] + 2 * (base + j) + (tid & 1)] = 0.0;
     }
     if (js0 >= j1) return;
 
     AState<LP, FW> s;
     Starts<LP> st;
-    load_starts(st, P, m, 0, nj);
+    load_starts(st, P, m, pb, nj);
+    const bool from_rst = rst >= 0 && js0 == j0;
+    int first = nj;  // first step at which a lane of this wave is live
 #pragma unroll
     for (int p = 0; p < LP; p++) {
-        const int pair = p * 64 + lane;
+        const int pair = pb + p * 64 + lane;
         const bool act = pair < npair;
         const int pc = act ? pair : 0;
         s.x[p] = act ? P->xp[pc] : 0.0;
         s.ua[p] = 0.0;
         s.ub[p] = 0.0;
-        if (rst >= 0 && js0 == j0) {
+        if (from_rst) {
             const double2 r = *(const double2*)(P->rst_y + 2 * ((size_t)rst * npair + pc));
             s.ua[p] = act ? r.x : 0.0;
             s.ub[p] = act ? r.y : 0.0;
         }
+        const bool live0 = from_rst && st.j[p] < j0;
+        first = min(first, live0 ? js0 : st.j[p]);
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o));
+    first = __builtin_amdgcn_readfirstlane(first);
     {
         const double* F[FW];
 #pragma unroll
-        for (int f = 0; f < FW; f++) F[f] = a.in + foff[f] + 2 * ((size_t)m * nlat);
-        analys_inputs(s, F, nlat, npair, a.adjoint, P->wq);
+        for (int f = 0; f < FW; f++) F[f] = a.in + foff[f];
+        analys_inputs(s, F, nlat, fts, m, pb, npair, a.adjoint, P->wq);
     }
 
     // Warm L2 with the beta entries of this unit (one word per 64-byte line
@@ -552,11 +575,12 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
         pf = *(const unsigned*)((const char*)(P->beta + base + js0) + (off < nbytes ? off : 0));
     }
     const double cm = (m == 0 || !a.adjoint) ? 1.0 : 2.0;
-    const int v = lane & 31;   // reduction row of this lane
-    const int h = lane >> 5;   // half of the row it sums
+    const int v = tid / PR;   // reduction row of this thread
+    const int h = tid % PR;   // its part of the row
     const int comp = v & 1;
     const int t_out = (v >> 1) / FW;
     const int f_out = (v >> 1) % FW;
+    const int col = wv * 64 + lane;  // this thread's column
 
     // js0 is a segment start (the plan rounds it down)
     for (int js = js0; js < j1; js += kSegLen) {
@@ -571,13 +595,17 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
 #pragma unroll
             for (int i = 0; i < C; i++) b.v[i] = pbk->v[i];
             const bool window = c <= jwin;
+            const bool idle = c + C <= first;  // wave-uniform: no lane live in the chunk
 #pragma unroll
             for (int c0 = 0; c0 < C; c0 += SC) {
-                // this lane's output scale, loaded ahead of the steps (clamped
-                // index: lanes past the unit's end write nothing)
+                // this thread's output scale, loaded ahead of the steps
+                // (clamped index: rows past the unit's end write nothing)
                 const int j_out = c + c0 + t_out;
                 const double gam = P->gamma[base + min(j_out, je - 1)] * cm;
-                if (window) {
+                if (idle) {
+#pragma unroll
+                    for (int t = 0; t < NV; t++) red[t][col] = 0.0;
+                } else if (window) {
 #pragma unroll
                     for (int t = 0; t < SC; t++) {
                         if ((c0 + t) % kInject == 0) start_lanes(s.ua, s.ub, st, c + c0 + t);
@@ -585,8 +613,8 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
                         analys_step(s, c0 + t, b.v[c0 + t], sr, si);
 #pragma unroll
                         for (int f = 0; f < FW; f++) {
-                            red[2 * (t * FW + f)][lane] = sr[f];
-                            red[2 * (t * FW + f) + 1][lane] = si[f];
+                            red[2 * (t * FW + f)][col] = sr[f];
+                            red[2 * (t * FW + f) + 1][col] = si[f];
                         }
                     }
                 } else {
@@ -596,24 +624,25 @@ __global__ void __launch_bounds__(64) k_legendre_analys(LegArgs a)
                         analys_step(s, c0 + t, b.v[c0 + t], sr, si);
 #pragma unroll
                         for (int f = 0; f < FW; f++) {
-                            red[2 * (t * FW + f)][lane] = sr[f];
-                            red[2 * (t * FW + f) + 1][lane] = si[f];
+                            red[2 * (t * FW + f)][col] = sr[f];
+                            red[2 * (t * FW + f) + 1][col] = si[f];
                         }
                     }
                 }
-                // row v summed over the 64 lanes by two lanes, four
-                // independent partial sums each
+                // row v summed over the NT columns by PR threads (columns
+                // r PR + h), four independent partial sums each
                 __syncthreads();
                 double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
                 for (int r = 0; r < 32; r += 4) {
-                    s0 += red[v][h * 32 + r];
-                    s1 += red[v][h * 32 + r + 1];
-                    s2 += red[v][h * 32 + r + 2];
-                    s3 += red[v][h * 32 + r + 3];
+                    s0 += red[v][(r + 0) * PR + h];
+                    s1 += red[v][(r + 1) * PR + h];
+                    s2 += red[v][(r + 2) * PR + h];
+                    s3 += red[v][(r + 3) * PR + h];
                 }
                 double sum = (s0 + s1) + (s2 + s3);
-                sum += __shfl_xor(sum, 32);
+#pragma unroll
+                for (int o = 1; o < PR; o <<= 1) sum += __shfl_xor(sum, o);
                 __syncthreads();
                 if (h == 0 && j_out < je && f_out < nf) {
                     const long idx = base + j_out;
@@ -651,11 +680,11 @@ static int launch_synth_t(const LegLaunch& l, void* stream)
     return (int)hipGetLastError();
 }
 
-template <int LP, int FW>
+template <int LP, int FW, int W>
 static int launch_analys_t(const LegLaunch& l, void* stream)
 {
     LegArgs a{l.plans, l.units, l.q_off, l.f_off, l.in, l.out, l.nfields, l.adjoint, l.nunits, 1};
-    hipLaunchKernelGGL((k_legendre_analys<LP, FW>), dim3(l.nunits, l.grid_y), dim3(64), 0,
+    hipLaunchKernelGGL((k_legendre_analys<LP, FW, W>), dim3(l.nunits, l.grid_y), dim3(64 * W), 0,
                        (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
@@ -674,10 +703,13 @@ int launch_legendre_synth(const LegLaunch& l, void* stream)
 int launch_legendre_analys(const LegLaunch& l, void* stream)
 {
     if (l.nunits <= 0) return 0;
-#define SHTN_A(LPV, FWV) \
-    if (l.lp == LPV && l.fw == FWV) return launch_analys_t<LPV, FWV>(l, stream);
-    SHTN_A(1, 1) SHTN_A(2, 1) SHTN_A(4, 1) SHTN_A(8, 1)
-    SHTN_A(1, 2) SHTN_A(2, 2) SHTN_A(4, 2)
+#define SHTN_A(LPV, FWV, WV) \
+    if (l.lp == LPV && l.fw == FWV && l.waves == WV) return launch_analys_t<LPV, FWV, WV>(l, stream);
+    SHTN_A(1, 1, 1) SHTN_A(2, 1, 1) SHTN_A(4, 1, 1) SHTN_A(8, 1, 1)
+    SHTN_A(1, 2, 1) SHTN_A(2, 2, 1) SHTN_A(4, 2, 1)
+    SHTN_A(2, 1, 2) SHTN_A(4, 1, 2) SHTN_A(8, 1, 2)
+    SHTN_A(2, 2, 2) SHTN_A(4, 2, 2)
+    SHTN_A(4, 1, 4) SHTN_A(8, 1, 4)
 #undef SHTN_A
     return (int)hipErrorInvalidValue;
 }

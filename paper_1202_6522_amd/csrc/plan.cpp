@@ -274,8 +274,7 @@ Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
     // fastest at lmax 1023); one analysis wave covers every pair of its order
     p->tiling.synth_lp = 1;
     p->tiling.m_pairing = 0;
-    p->tiling.analys_lp = 1;
-    while (64 * p->tiling.analys_lp < np && p->tiling.analys_lp < 8) p->tiling.analys_lp *= 2;
+    analys_shape(np, p->tiling.analys_lp, p->tiling.analys_waves);
     if (rebuild_units(*p, err)) { delete p; return nullptr; }
     build_image(*p);
     return p;
@@ -481,7 +480,7 @@ void build_image(Plan& p)
 WorkLayout work_layout(const Plan& p, int nfields)
 {
     WorkLayout w;
-    w.f_bytes = align256((size_t)nfields * (p.M + 1) * p.nlat * 16);
+    w.f_bytes = align256((size_t)nfields * f_layout(p.M, p.nlat).size * 16);
     w.q_bytes = align256(((size_t)nfields * p.nlm + kTablePad) * 16);  // padded for block loads
     w.total = w.f_bytes + w.q_bytes;
     return w;

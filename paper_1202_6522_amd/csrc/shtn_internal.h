@@ -41,8 +41,20 @@ constexpr int kChunk = 16;
 // (beta, the rescaled spectrum): a block starting at an order's last degree
 // stays in bounds.
 constexpr int kTablePad = 32;
-// Largest latitude-pair count one analysis wave covers (64 lanes x 8 pairs).
-constexpr int kMaxAnalysPairs = 512;
+// Pairs per lane and waves of an analysis unit covering npair latitude pairs
+// (the smallest power-of-two coverage, up to 8 pairs per lane first).
+inline void analys_shape(int npair, int& lp, int& waves)
+{
+    lp = 1;
+    waves = 1;
+    while (64 * lp * waves < npair) {
+        if (lp < 8) lp *= 2;
+        else waves *= 2;
+    }
+}
+// Largest latitude-pair count one analysis unit covers (4 waves x 64 lanes x
+// 8 pairs).
+constexpr int kMaxAnalysPairs = 2048;
 
 // One work unit of a Legendre kernel = one wave (kUnitInts ints).  Steps j
 // count degrees from the order: n = m + j.
@@ -99,11 +111,14 @@ struct DevPlan {
     long nlm;
     int n_synth_units, n_analys_units;
     int synth_lp, analys_lp, fw, pad0;
+    // Longitude coefficients of one field: tile stride and size (complex).
+    long f_ts, f_size;
 };
 
 struct Tiling {
     int synth_lp = 1;
     int analys_lp = 8;
+    int analys_waves = 1;  // waves per analysis unit
     int fw = 1;
     int m_pairing = 0;  // synthesis: 1 = orders m and M-m share a workgroup
     int split = 0;     // 0 = automatic
@@ -150,11 +165,30 @@ int rebuild_units(Plan& p, std::string& err);     // units + restart states for 
 bool start_range(const Plan& p, int m, int i0, int i1, int lo, int hi, int& jmin, int& jmax);
 void build_image(Plan& p);                        // lays out the device buffer
 inline long lm_index(int L, int n, int m) { return (long)m * (2 * L + 1 - m) / 2 + n; }
+// Layout of the longitude coefficients F_m(theta_i) of one field: tiles of
+// kFTile consecutive latitudes, each tile order-major with the kFTile values
+// of one order adjacent:
+//   offset(m, i) = (i / kFTile) f_ts + m kFTile + i % kFTile,  f_ts = (mmax+1) kFTile.
+// The Legendre kernels' lanes (consecutive latitudes of one order) touch
+// whole 128-byte lines, and an FFT workgroup moves its rows in contiguous
+// runs (half a tile per order at K = 1024).
+constexpr int kFTile = 8;
+constexpr int kFTileLg = 3;
+struct FLayout {
+    long ts, size;  // tile stride and values per field (complex)
+};
+inline FLayout f_layout(int M, int nlat)
+{
+    const long ts = (long)(M + 1) * kFTile;
+    return {ts, ts * ((nlat + kFTile - 1) / kFTile)};
+}
+// XCDs of the chip: workgroup b of a launch runs on XCD b % kXcds.
+constexpr int kXcds = 8;
 size_t align256(size_t v);
 
 // Workspace layout of a plan call with nfields fields.
 struct WorkLayout {
-    size_t f_bytes;   // F: nfields x (M+1) x nlat complex
+    size_t f_bytes;   // F: nfields x f_layout().size complex
     size_t q_bytes;   // rescaled spectrum: nfields x nlm complex
     size_t total;
 };
@@ -173,6 +207,7 @@ struct LegLaunch {
     int nfields;
     int adjoint;           // 0 forward transform, 1 adjoint variant
     int lp, fw;            // template selection
+    int waves = 1;         // analysis: waves per unit (latitude pairs 64 lp waves)
     int wpg;               // synthesis: waves (consecutive units) per workgroup
 };
 // Qs = gamma * Q per field; q_off/s_off/fplan per field (device) or null.
@@ -186,7 +221,7 @@ struct FftLaunch {
     const int* rowblocks;     // device: per block {field, plan, row0, nrows} or null
     int nblocks;
     int grid_y;
-    int K;                    // for plan calls (all fields same K)
+    int K;                    // longest rows of the launch (sizes the LDS twiddle table)
     int rows_per_block;
     const long* g_off;        // per-field grid offset (doubles) or null
     const long* f_off;        // per-field F offset (doubles) or null
@@ -196,6 +231,7 @@ struct FftLaunch {
     double scale;             // r2c: output scale (2 pi/nphi or 1)
 };
 int launch_c2r(const FftLaunch& a, void* stream);
+int fft_rows_cap(int K);     // rows of K complex points held by one FFT workgroup
 int launch_r2c(const FftLaunch& a, void* stream);
 
 }  // namespace shtn

@@ -47,7 +47,7 @@ _SIGS = {
     "shtn_get_grid": (_c.c_int, [_vp, _dp, _dp]),
     "shtn_legendre_flops": (_c.c_double, [_vp]),
     "shtn_plan_table": (_c.c_long, [_vp, _c.c_int, _vp, _sz]),
-    "shtn_plan_set_tiling": (_c.c_int, [_vp] + [_c.c_int] * 6),
+    "shtn_plan_set_tiling": (_c.c_int, [_vp] + [_c.c_int] * 7),
     "shtn_batch": (_vp, [_c.c_int, _c.POINTER(_vp)]),
     "shtn_batch_destroy": (None, [_vp]),
     "shtn_batch_offsets": (_c.c_int, [_vp, _c.POINTER(_sz), _c.POINTER(_sz)]),
@@ -193,9 +193,10 @@ def shtn_plan_table(h, which):
     return out
 
 
-def shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split=0, fft_rows=0):
-    return check(load_library().shtn_plan_set_tiling(h, synth_lp, analys_lp, fw, m_pairing, split,
-                                                     fft_rows), "shtn_plan_set_tiling")
+def shtn_plan_set_tiling(h, synth_lp, analys_lp, analys_waves, fw, m_pairing, split=0, fft_rows=0):
+    return check(load_library().shtn_plan_set_tiling(h, synth_lp, analys_lp, analys_waves, fw,
+                                                     m_pairing, split, fft_rows),
+                 "shtn_plan_set_tiling")
 
 
 def shtn_batch(plan_handles):
@@ -325,14 +326,15 @@ class Plan:
         off = (-ptr) % 256
         shtn_plan_upload(self.handle, ptr + off, _stream_ptr(torch, self.device))
 
-    def set_tiling(self, synth_lp, analys_lp, fw=1, m_pairing=2, split=0, fft_rows=0):
-        shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, fw, m_pairing, split, fft_rows)
+    def set_tiling(self, synth_lp, analys_lp, analys_waves=1, fw=1, m_pairing=0, split=0, fft_rows=0):
+        shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, analys_waves, fw, m_pairing, split,
+                             fft_rows)
         self._upload()
 
     def tiling(self):
         t = shtn_plan_table(self.handle, 13)
-        return dict(synth_lp=int(t[0]), analys_lp=int(t[1]), fw=int(t[2]), m_pairing=int(t[3]),
-                    split=int(t[4]), fft_rows=int(t[5]))
+        return dict(synth_lp=int(t[0]), analys_lp=int(t[1]), analys_waves=int(t[6]), fw=int(t[2]),
+                    m_pairing=int(t[3]), split=int(t[4]), fft_rows=int(t[5]))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -59,6 +59,8 @@ def test_scalar_cases_full(case, dev):
     None,
     dict(synth_lp=1, analys_lp=8, m_pairing=0, split=128),
     dict(synth_lp=4, analys_lp=8, m_pairing=1, split=512, fft_rows=2),
+    dict(synth_lp=2, analys_lp=4, analys_waves=2, m_pairing=0, split=256),
+    dict(synth_lp=1, analys_lp=4, analys_waves=4, m_pairing=0),
 ])
 def test_lmax1023_sampled(tiling, dev):
     p, Q = inputs.scalar_case(2)
@@ -129,6 +131,9 @@ def test_edge_shapes_all_transforms(shape, dev):
     dict(synth_lp=4, analys_lp=4, fw=2, m_pairing=1),
     dict(synth_lp=1, analys_lp=4, fw=2, m_pairing=0, split=32),
     dict(synth_lp=4, analys_lp=8, fw=1, m_pairing=1, split=96),
+    dict(synth_lp=1, analys_lp=2, analys_waves=2, fw=1, m_pairing=0, split=64),
+    dict(synth_lp=2, analys_lp=4, analys_waves=2, fw=2, m_pairing=1),
+    dict(synth_lp=1, analys_lp=4, analys_waves=4, fw=1, m_pairing=0, split=32),
 ])
 def test_tilings_agree(tiling, dev):
     L, M, nlat, nphi = 255, 255, 256, 512
@@ -166,6 +171,32 @@ def test_adjoint_dot_products(dev):
     lhs = np.sum(Af.real * h.real + Af.imag * h.imag)
     rhs = np.sum(f * Ath)
     assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(f * Ath))
+
+
+def test_lmax2047_underflow_guard_and_wide_analysis(dev):
+    # lmax 2047: P_m^m underflows double precision near the poles for large m
+    # although P_n^m later matters (the plan-time guard), and an analysis unit
+    # spans 1024 latitude pairs (two waves of 8 pairs per lane).  Synthesis on
+    # selected orders against the long-double oracle; round trip in full.
+    L, nlat, nphi = 2047, 2048, 4096
+    plan = make_plan(L, L, nlat, nphi, dev)
+    assert plan.tiling()["analys_waves"] == 2
+    rng = np.random.default_rng(2047)
+    ms = [0, 700, 1200, 1600, 2000, 2047]
+    Q = np.zeros((1, plan.nlm), complex)
+    n_all, m_all = inputs.degree_order(L, L)
+    sel = np.isin(m_all, ms)
+    Q[0, sel] = (rng.standard_normal(sel.sum()) + 1j * rng.standard_normal(sel.sum())) \
+        * (n_all[sel] + 1.0) ** -1.0
+    Q[0, m_all == 0] = Q[0, m_all == 0].real
+    g = plan.synth(to_dev(Q, dev))
+    rows = np.array([0, 1, 5, 40, 200, 600, 1023, 1024, 1500, 2040, 2047])
+    gref = oracle.synth(Q, L, L, nlat, nphi, mlist=ms, rows=rows, precision="ld")
+    assert rel(g.cpu().numpy()[0][rows], gref[0]) <= 1e-10
+    R = plan.analys(g).cpu().numpy()
+    err = np.max(np.abs(R - Q)) / np.max(np.abs(Q))
+    print("lmax 2047 round trip: %.3e" % err)
+    assert err <= 1e-10
 
 
 def test_paper_accuracy_protocol(dev):
@@ -210,6 +241,7 @@ def test_bad_calls_raise(dev):
         plan.synth(torch.zeros(10, dtype=torch.complex128, device=dev))
     with pytest.raises(ValueError):
         plan.analys(torch.zeros(32, 64, dtype=torch.float32, device=dev))
-    big = make_plan(1100, 1100, 1101, 4096, dev)
+    # analysis units cover at most 4096 latitudes (2048 pairs)
+    big = make_plan(4200, 100, 4201, 256, dev)
     with pytest.raises(S.ShtnError):
-        big.analys(torch.zeros(1101, 4096, dtype=torch.float64, device=dev))
+        big.analys(torch.zeros(4201, 256, dtype=torch.float64, device=dev))

@@ -54,8 +54,11 @@ def test_calls_before_upload_and_null_pointers(lib):
         assert lib.shtn_work_bytes(h, 0) == 0
         assert lib.shtn_lm_index(h, 3, 4) == -1
         assert lib.shtn_lm_index(h, 8, 8) == S.shtn_nlm(h) - 1
-        assert lib.shtn_plan_set_tiling(h, 3, 1, 1, 1, 0, 0) == S.SHTN_EINVAL
-        assert lib.shtn_plan_set_tiling(h, 1, 1, 1, 1, 40, 0) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 3, 1, 1, 1, 1, 0, 0) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 1, 1, 1, 1, 1, 40, 0) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 1, 1, 3, 1, 0, 0, 0) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_tiling(h, 1, 1, 2, 1, 0, 0, 0) == S.SHTN_EINVAL  # lp 1 x 2 waves: not built
+        assert lib.shtn_plan_set_tiling(h, 1, 2, 2, 1, 0, 0, 0) == S.SHTN_OK
         assert S.shtn_strerror(S.SHTN_EUNSUPPORTED) == "unsupported configuration"
     finally:
         S.shtn_plan_destroy(h)
@@ -402,7 +405,7 @@ def test_synthesis_units_cover_all_work():
     for (L, M, nlat, pairing) in [(31, 31, 32, 1), (40, 33, 51, 1), (40, 33, 51, 0), (300, 300, 301, 1)]:
         h = S.shtn_plan(L, M, nlat, 1024)
         try:
-            S.shtn_plan_set_tiling(h, 1, 8 if nlat > 256 else 1, 1, pairing, 0, 0)
+            S.shtn_plan_set_tiling(h, 1, 8 if nlat > 256 else 1, 1, 1, pairing, 0, 0)
             t = _tables(h)
             su = t[T_SU].reshape(-1, UI)
             npair = (nlat + 1) // 2
