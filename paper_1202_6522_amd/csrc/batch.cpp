@@ -186,6 +186,7 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
                 const size_t nu = p.analys_units.size() / kUnitInts;
                 for (size_t i = 0; i < nu; i++) {
                     const int* pu = &p.analys_units[i * kUnitInts];
+                    if (pu[U_M] < 0) continue;  // padding of the plan's XCD queues
                     SU x{(long)(pu[U_J1] - pu[U_JS] + 4) * nf, {}};
                     std::copy(pu, pu + kUnitInts, x.u);
                     x.u[U_FIELD] = fg;

@@ -145,6 +145,23 @@ __device__ __forceinline__ void start_lanes(double (&ua)[LP], double (&ub)[LP], 
     }
 }
 
+// Analysis: the start steps stay in registers and the stored states in this
+// lane's slots in LDS (read back only at the checkpoints of the start
+// window, so they hold no registers through the degree loop).
+template <int LP>
+__device__ __forceinline__ void start_lanes_lds(double (&ua)[LP], double (&ub)[LP], const int (&sj)[LP],
+                                                const double2 (*sy)[64], int j)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        const double2 y = sy[p][lane];
+        const bool go = sj[p] == j;
+        ua[p] = go ? y.x : ua[p];
+        ub[p] = go ? y.y : ub[p];
+    }
+}
+
 template <int LP>
 __device__ __forceinline__ void rescale(double (&ua)[LP], double (&ub)[LP], int sh)
 {
@@ -416,53 +433,39 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
 template <int LP, int FW>
 struct AState {
     double x[LP], ua[LP], ub[LP];
-    // folded, weighted inputs w (F_N + F_S), w (F_N - F_S)
-    double ger[LP][FW], gei[LP][FW], gor[LP][FW], goi[LP][FW];
+    // folded, weighted inputs: even-degree (w (F_N + F_S)) and odd-degree
+    // (w (F_N - F_S)) parts, the component this lane keeps (k) and the one it
+    // hands to its neighbour lane (s): even lanes keep the real part, odd
+    // lanes the imaginary part
+    double ek[LP][FW], es[LP][FW], ok[LP][FW], os[LP][FW];
 };
 
-// Loads the folded inputs of every lane.  A lane that has not started holds a
-// zero state, so it adds exactly 0 whatever its inputs.
-template <int LP, int FW>
-__device__ __forceinline__ void analys_inputs(AState<LP, FW>& s, const double* const (&F)[FW], int nlat,
-                                              long fts, int m, int pb, int npair, int adjoint,
-                                              const double* wq)
+// v of the neighbouring lane (lanes 2i and 2i+1 swap; DPP quad_perm [1,0,3,2]).
+__device__ __forceinline__ double swap_lane_pair(double v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        const int pair = pb + p * 64 + lane;
-        const bool act = pair < npair;
-        const int pc = act ? pair : 0;
-        const bool middle = (nlat & 1) && pc == npair - 1;
-        const double wt = !act ? 0.0 : (adjoint ? (middle ? 0.5 : 1.0) : wq[pc]);
-#pragma unroll
-        for (int f = 0; f < FW; f++) {
-            const double2 vn = *(const double2*)(F[f] + 2 * f_index(fts, m, pc));
-            const double2 vs = *(const double2*)(F[f] + 2 * f_index(fts, m, nlat - 1 - pc));
-            s.ger[p][f] = wt * (vn.x + vs.x);
-            s.gei[p][f] = wt * (vn.y + vs.y);
-            s.gor[p][f] = wt * (vn.x - vs.x);
-            s.goi[p][f] = wt * (vn.y - vs.y);
-        }
-    }
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // One recurrence step (even t: ua and the even inputs, odd t: ub and the odd
-// inputs); returns this lane's partial sum over its pairs, per field.
+// inputs).  Returns per field the lane pair's partial sum over its pairs of
+// the kept component: real part on even lanes, imaginary part on odd lanes.
 template <int LP, int FW>
-__device__ __forceinline__ void analys_step(AState<LP, FW>& s, int t, double b,
-                                            double (&sr)[FW], double (&si)[FW])
+__device__ __forceinline__ void analys_step(AState<LP, FW>& s, int t, double b, double (&out)[FW])
 {
+    double sk[FW], ss[FW];
 #pragma unroll
-    for (int f = 0; f < FW; f++) sr[f] = si[f] = 0.0;
+    for (int f = 0; f < FW; f++) sk[f] = ss[f] = 0.0;
     if ((t & 1) == 0) {
 #pragma unroll
         for (int p = 0; p < LP; p++) {
             s.ua[p] = fma(s.x[p], s.ub[p], b * s.ua[p]);
 #pragma unroll
             for (int f = 0; f < FW; f++) {
-                sr[f] = fma(s.ger[p][f], s.ua[p], sr[f]);
-                si[f] = fma(s.gei[p][f], s.ua[p], si[f]);
+                sk[f] = fma(s.ek[p][f], s.ua[p], sk[f]);
+                ss[f] = fma(s.es[p][f], s.ua[p], ss[f]);
             }
         }
     } else {
@@ -471,31 +474,60 @@ __device__ __forceinline__ void analys_step(AState<LP, FW>& s, int t, double b,
             s.ub[p] = fma(s.x[p], s.ua[p], b * s.ub[p]);
 #pragma unroll
             for (int f = 0; f < FW; f++) {
-                sr[f] = fma(s.gor[p][f], s.ub[p], sr[f]);
-                si[f] = fma(s.goi[p][f], s.ub[p], si[f]);
+                sk[f] = fma(s.ok[p][f], s.ub[p], sk[f]);
+                ss[f] = fma(s.os[p][f], s.ub[p], ss[f]);
             }
         }
     }
+#pragma unroll
+    for (int f = 0; f < FW; f++) out[f] = sk[f] + swap_lane_pair(ss[f]);
 }
 
-// Each lane's partial sums go straight to LDS, one row per (degree, field,
-// re/im) with a column per thread of the workgroup; every 16/FW degrees one
-// pass sums the 32 rows (2W threads per row, padded rows).  No accumulators
-// stay in registers.  A workgroup of W waves covers 64 LP W latitude pairs:
-// wave w takes pairs [64 LP w, 64 LP (w + 1)); a wave none of whose
-// latitudes has started writes zero rows instead of computing.
+template <int N>
+struct DBlk {
+    double v[N];
+};
+
+// A block of N wave-uniform doubles through the scalar cache.
+template <int N>
+__device__ __forceinline__ void load_blk(DBlk<N>& d, cdp src)
+{
+    typedef const __attribute__((address_space(4))) DBlk<N>* cbp;
+    cbp p = (cbp)src;
+#pragma unroll
+    for (int i = 0; i < N; i++) d.v[i] = p->v[i];
+}
+
+// The degrees of a unit run in passes of SC = kChunk / FW degrees.  In a pass
+// each lane pair's partial sums (one row per degree and field, one column
+// per thread: real parts in even columns, imaginary parts in odd ones) go to
+// LDS, while the sums of the previous pass are read back, added over the
+// columns (2W threads per output, padded rows) and stored: with several
+// waves the passes alternate between two buffers with one barrier per pass.
+// A workgroup of W waves covers
+// 64 LP W latitude pairs: wave w takes pairs [64 LP w, 64 LP (w + 1)); a wave
+// none of whose latitudes has started writes zero rows instead of computing.
 template <int LP, int FW, int W>
 __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
 {
-    constexpr int C = kChunk;       // degrees per beta block load
-    constexpr int SC = kChunk / FW; // degrees per reduction
-    constexpr int NV = 2 * SC * FW; // rows reduced per pass
-    constexpr int NT = 64 * W;      // threads = columns
-    constexpr int PR = 2 * W;       // threads per row
-    static_assert(NV * PR == NT, "the threads cover the rows");
-    static_assert(kSegLen % C == 0, "chunks tile a segment");
-    static_assert(SC % kInject == 0, "lanes start at reduction-block boundaries or inside them");
-    __shared__ double red[NV][NT + 1];
+    constexpr int SC = kChunk / FW;  // degrees per pass
+    constexpr int NR = SC * FW;      // rows per pass
+    constexpr int NT = 64 * W;       // threads = columns
+    constexpr int PR = 2 * W;        // threads per output (row, component)
+    constexpr int NK = NT / 2 / PR;  // columns each of them adds
+    // row stride NT + 2 PR doubles: a thread's PR-wide column groups of
+    // consecutive rows start 4 PR banks apart, so the 32 lanes of a half-wave
+    // read distinct banks
+    constexpr int RS = NT + 2 * PR;
+    static_assert(2 * NR * PR == NT, "the threads cover the outputs");
+    static_assert(kSegLen % SC == 0, "passes tile a segment");
+    static_assert(SC % kInject == 0, "lanes start at pass boundaries or inside them");
+    // One wave executes its LDS operations in order, so with W = 1 the reads
+    // of the previous pass, issued before this pass's writes, need neither a
+    // second buffer nor a barrier.
+    constexpr int NB = W == 1 ? 1 : 2;
+    __shared__ double red[NB][NR][RS];
+    __shared__ double2 start_y[W][LP][64];  // stored lane start states
 
     cip U = (cip)a.units + (size_t)blockIdx.x * kUnitInts;
     const int m = U[U_M];
@@ -534,124 +566,162 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
     }
     if (js0 >= j1) return;
 
+    // Unit setup.  Every global load is issued before any of them is used
+    // (indices clamped to valid entries, inactive lanes masked afterwards),
+    // so the setup costs one memory round trip.
     AState<LP, FW> s;
-    Starts<LP> st;
-    load_starts(st, P, m, pb, nj);
+    int sj[LP];
     const bool from_rst = rst >= 0 && js0 == j0;
     int first = nj;  // first step at which a lane of this wave is live
+    {
+        const bool odd = lane & 1;
+        int pc[LP], jv[LP];
+        bool act[LP];
+        double xv[LP], wl[LP];
+        double2 y[LP], r[LP], fn[LP][FW], fsth[LP][FW];
 #pragma unroll
-    for (int p = 0; p < LP; p++) {
-        const int pair = pb + p * 64 + lane;
-        const bool act = pair < npair;
-        const int pc = act ? pair : 0;
-        s.x[p] = act ? P->xp[pc] : 0.0;
-        s.ua[p] = 0.0;
-        s.ub[p] = 0.0;
-        if (from_rst) {
-            const double2 r = *(const double2*)(P->rst_y + 2 * ((size_t)rst * npair + pc));
-            s.ua[p] = act ? r.x : 0.0;
-            s.ub[p] = act ? r.y : 0.0;
+        for (int p = 0; p < LP; p++) {
+            const int pair = pb + p * 64 + lane;
+            act[p] = pair < npair;
+            pc[p] = act[p] ? pair : 0;
+            const size_t q = (size_t)m * npair + pc[p];
+            xv[p] = P->xp[pc[p]];
+            wl[p] = P->wq[pc[p]];
+            y[p] = *(const double2*)(P->inj_y + 2 * q);
+            jv[p] = P->inj_j[q];
+#pragma unroll
+            for (int f = 0; f < FW; f++) {
+                const double* F = a.in + foff[f];
+                fn[p][f] = *(const double2*)(F + 2 * f_index(fts, m, pc[p]));
+                fsth[p][f] = *(const double2*)(F + 2 * f_index(fts, m, nlat - 1 - pc[p]));
+            }
         }
-        const bool live0 = from_rst && st.j[p] < j0;
-        first = min(first, live0 ? js0 : st.j[p]);
+        if (from_rst) {
+#pragma unroll
+            for (int p = 0; p < LP; p++)
+                r[p] = *(const double2*)(P->rst_y + 2 * ((size_t)rst * npair + pc[p]));
+        } else {
+#pragma unroll
+            for (int p = 0; p < LP; p++) r[p] = make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int p = 0; p < LP; p++) {
+            // lane starts: steps in registers, stored states in LDS
+            start_y[wv][p][lane] = y[p];
+            sj[p] = act[p] ? jv[p] : nj;
+            s.x[p] = act[p] ? xv[p] : 0.0;
+            s.ua[p] = act[p] ? r[p].x : 0.0;
+            s.ub[p] = act[p] ? r[p].y : 0.0;
+            const bool live0 = from_rst && sj[p] < j0;
+            first = min(first, live0 ? js0 : sj[p]);
+            // folded, weighted inputs; a lane that has not started holds a
+            // zero state, so it adds exactly 0 whatever its inputs
+            const bool middle = (nlat & 1) && pc[p] == npair - 1;
+            const double wt = !act[p] ? 0.0 : (a.adjoint ? (middle ? 0.5 : 1.0) : wl[p]);
+#pragma unroll
+            for (int f = 0; f < FW; f++) {
+                const double2 vn = fn[p][f], vs = fsth[p][f];
+                const double er = wt * (vn.x + vs.x), ei = wt * (vn.y + vs.y);
+                const double orr = wt * (vn.x - vs.x), oi = wt * (vn.y - vs.y);
+                s.ek[p][f] = odd ? ei : er;
+                s.es[p][f] = odd ? er : ei;
+                s.ok[p][f] = odd ? oi : orr;
+                s.os[p][f] = odd ? orr : oi;
+            }
+        }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o));
     first = __builtin_amdgcn_readfirstlane(first);
-    {
-        const double* F[FW];
-#pragma unroll
-        for (int f = 0; f < FW; f++) F[f] = a.in + foff[f];
-        analys_inputs(s, F, nlat, fts, m, pb, npair, a.adjoint, P->wq);
-    }
 
     // Warm L2 with the beta entries of this unit (one word per 64-byte line
     // per lane, consumed at the end; see the synthesis kernel).
     __builtin_amdgcn_sched_barrier(0);
     unsigned pf;
     {
-        const int nbytes = (j1 - js0 + C) * 8;
+        const int nbytes = (j1 - js0 + 2 * SC) * 8;
         const int off = lane * 64;
         pf = *(const unsigned*)((const char*)(P->beta + base + js0) + (off < nbytes ? off : 0));
     }
     const double cm = (m == 0 || !a.adjoint) ? 1.0 : 2.0;
-    const int v = tid / PR;   // reduction row of this thread
-    const int h = tid % PR;   // its part of the row
-    const int comp = v & 1;
-    const int t_out = (v >> 1) / FW;
-    const int f_out = (v >> 1) % FW;
+    const int o = tid / PR;        // output of this thread: (row, component)
+    const int h = tid % PR;        // its part of the columns
+    const int row = o >> 1, comp = o & 1;
+    const int t_out = row / FW;
+    const int f_out = row % FW;
     const int col = wv * 64 + lane;  // this thread's column
+    cdp gam_tab = (cdp)P->gamma + base;
 
-    // js0 is a segment start (the plan rounds it down)
-    for (int js = js0; js < j1; js += kSegLen) {
-        rescale(s.ua, s.ub, js > js0 ? segexp[js / kSegLen] : 0);
-        const int je = min(js + kSegLen, j1);
-        for (int c = js; c < je; c += C) {
-            // beta for the chunk in one block load (the table is padded).  A
-            // partial last chunk runs all C steps: the extra degrees belong to
-            // no output (their results are not written) and the unit ends here.
-            D16 b;
-            cd16p pbk = (cd16p)(bet + c);
+    // beta and the segment shift of the next pass are loaded one pass ahead
+    // (the beta table is padded past the last order).  A partial last pass
+    // runs all SC steps: the extra degrees belong to no output and are not
+    // stored.
+    DBlk<SC> bn;
+    load_blk(bn, bet + js0);
+    int shn = 0;        // js0 is a segment start (the plan rounds it down)
+    int buf = 0;
+    for (int c = js0; c < j1 + SC; c += SC) {
+        const bool compute = c < j1;
+        const DBlk<SC> b = bn;
+        const int sh = shn;
+        // The scalar loads above have arrived before the LDS reads of the
+        // previous pass's sums are issued (one counter covers both kinds), so
+        // the steps below wait on neither and the reads complete under them.
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        double part[NK];
 #pragma unroll
-            for (int i = 0; i < C; i++) b.v[i] = pbk->v[i];
-            const bool window = c <= jwin;
-            const bool idle = c + C <= first;  // wave-uniform: no lane live in the chunk
+        for (int k = 0; k < NK; k++) part[k] = red[(NB - 1) & (buf ^ 1)][row][2 * (k * PR + h) + comp];
+        // gamma of this thread's output in that pass, needed after the steps
+        const double gl = gam_tab[min(max(c - SC, js0) + t_out, j1 - 1)];
+        if (compute) {
+            const int cn = c + SC;
+            load_blk(bn, bet + cn);
+            shn = (cn < j1 && cn % kSegLen == 0) ? segexp[cn / kSegLen] : 0;
+            if (sh != 0) rescale(s.ua, s.ub, sh);
+            if (c + SC <= first) {
+                // wave-uniform: no lane live in the pass
 #pragma unroll
-            for (int c0 = 0; c0 < C; c0 += SC) {
-                // this thread's output scale, loaded ahead of the steps
-                // (clamped index: rows past the unit's end write nothing)
-                const int j_out = c + c0 + t_out;
-                const double gam = P->gamma[base + min(j_out, je - 1)] * cm;
-                if (idle) {
+                for (int r = 0; r < NR; r++) red[buf][r][col] = 0.0;
+            } else if (c <= jwin) {
 #pragma unroll
-                    for (int t = 0; t < NV; t++) red[t][col] = 0.0;
-                } else if (window) {
+                for (int t = 0; t < SC; t++) {
+                    if (t % kInject == 0) start_lanes_lds(s.ua, s.ub, sj, start_y[wv], c + t);
+                    double v[FW];
+                    analys_step(s, t, b.v[t], v);
 #pragma unroll
-                    for (int t = 0; t < SC; t++) {
-                        if ((c0 + t) % kInject == 0) start_lanes(s.ua, s.ub, st, c + c0 + t);
-                        double sr[FW], si[FW];
-                        analys_step(s, c0 + t, b.v[c0 + t], sr, si);
-#pragma unroll
-                        for (int f = 0; f < FW; f++) {
-                            red[2 * (t * FW + f)][col] = sr[f];
-                            red[2 * (t * FW + f) + 1][col] = si[f];
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int t = 0; t < SC; t++) {
-                        double sr[FW], si[FW];
-                        analys_step(s, c0 + t, b.v[c0 + t], sr, si);
-#pragma unroll
-                        for (int f = 0; f < FW; f++) {
-                            red[2 * (t * FW + f)][col] = sr[f];
-                            red[2 * (t * FW + f) + 1][col] = si[f];
-                        }
-                    }
+                    for (int f = 0; f < FW; f++) red[buf][t * FW + f][col] = v[f];
                 }
-                // row v summed over the NT columns by PR threads (columns
-                // r PR + h), four independent partial sums each
-                __syncthreads();
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            } else {
 #pragma unroll
-                for (int r = 0; r < 32; r += 4) {
-                    s0 += red[v][(r + 0) * PR + h];
-                    s1 += red[v][(r + 1) * PR + h];
-                    s2 += red[v][(r + 2) * PR + h];
-                    s3 += red[v][(r + 3) * PR + h];
-                }
-                double sum = (s0 + s1) + (s2 + s3);
+                for (int t = 0; t < SC; t++) {
+                    double v[FW];
+                    analys_step(s, t, b.v[t], v);
 #pragma unroll
-                for (int o = 1; o < PR; o <<= 1) sum += __shfl_xor(sum, o);
-                __syncthreads();
-                if (h == 0 && j_out < je && f_out < nf) {
-                    const long idx = base + j_out;
-                    double val = gam * sum;
-                    if (m == 0 && comp == 1) val = 0.0;
-                    a.out[qoff[f_out] + 2 * idx + comp] = val;
+                    for (int f = 0; f < FW; f++) red[buf][t * FW + f][col] = v[f];
                 }
             }
         }
+        if (c > js0) {
+            double s0 = part[0], s1 = part[1], s2 = part[2], s3 = part[3];
+#pragma unroll
+            for (int k = 4; k < NK; k += 4) {
+                s0 += part[k];
+                s1 += part[k + 1];
+                s2 += part[k + 2];
+                s3 += part[k + 3];
+            }
+            double sum = (s0 + s1) + (s2 + s3);
+#pragma unroll
+            for (int q = 1; q < PR; q <<= 1) sum += __shfl_xor(sum, q);
+            const int j_out = c - SC + t_out;
+            if (h == 0 && j_out < j1 && f_out < nf) {
+                double val = cm * gl * sum;
+                if (m == 0 && comp == 1) val = 0.0;
+                a.out[qoff[f_out] + 2 * (base + j_out) + comp] = val;
+            }
+        }
+        if (W > 1) __syncthreads();
+        buf = (NB - 1) & (buf ^ 1);
     }
     // keeps the prefetch load alive; nfields is never negative
     if (a.nfields < 0) a.out[lane] = (double)pf;

@@ -413,10 +413,40 @@ int rebuild_units(Plan& p, std::string& err)
         }
     }
     std::stable_sort(au.begin(), au.end(), [](const AU& a, const AU& b) { return a.cost > b.cost; });
+    // Workgroup b runs on XCD b % kXcds.  All units of one order go to one
+    // XCD, so the inputs and start states they share come from that XCD's
+    // L2; orders are dealt largest first to the XCD with the least work so
+    // far, each XCD runs its units longest first, and the shorter XCD queues
+    // are padded with units without work.
+    std::vector<long> mcost(M + 1, 0);
+    for (auto& a : au) mcost[a.m] += a.cost;
+    std::vector<int> ms(M + 1);
+    for (int m = 0; m <= M; m++) ms[m] = m;
+    std::stable_sort(ms.begin(), ms.end(), [&](int a, int b) { return mcost[a] > mcost[b]; });
+    std::vector<int> xcd_of(M + 1, 0);
+    long xload[kXcds] = {0};
+    for (int m : ms) {
+        int x = 0;
+        for (int k = 1; k < kXcds; k++)
+            if (xload[k] < xload[x]) x = k;
+        xload[x] += mcost[m];
+        xcd_of[m] = x;
+    }
+    std::vector<std::vector<int>> xq(kXcds);
+    for (size_t i = 0; i < au.size(); i++) xq[xcd_of[au[i].m]].push_back((int)i);
+    size_t qlen = 0;
+    for (auto& q : xq) qlen = std::max(qlen, q.size());
     p.analys_units.clear();
-    for (auto& a : au) {
-        int u[kUnitInts] = {0, t.fw, 0, a.m, a.js, a.jw, a.j0, a.j1, a.rst, 0, 0, 0};
-        p.analys_units.insert(p.analys_units.end(), u, u + kUnitInts);
+    for (size_t k = 0; k < qlen; k++) {
+        for (int x = 0; x < kXcds; x++) {
+            int u[kUnitInts] = {0, t.fw, 0, -1, 0, 0, 0, 0, -1, 0, 0, 0};
+            if (k < xq[x].size()) {
+                const AU& a = au[xq[x][k]];
+                const int v[kUnitInts] = {0, t.fw, 0, a.m, a.js, a.jw, a.j0, a.j1, a.rst, 0, 0, 0};
+                std::copy(v, v + kUnitInts, u);
+            }
+            p.analys_units.insert(p.analys_units.end(), u, u + kUnitInts);
+        }
     }
     p.rst_y.assign((size_t)nrst * np * 2, 0.0);
     // restart states, orders split over host threads

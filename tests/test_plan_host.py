@@ -360,6 +360,18 @@ def test_restart_states_match_recurrence():
         npair = 128
         sj = t[T_INJJ].reshape(L + 1, npair)
         # every order's degree range is covered exactly once
+        # workgroup b runs on XCD b % 8: each XCD runs its units longest
+        # first, all units of one order on one XCD, padding units without work
+        xcd = np.arange(len(au)) % 8
+        real = au[:, U_M] >= 0
+        for x in range(8):
+            q = au[(xcd == x) & real]
+            cost = q[:, U_J1] - q[:, U_JS]
+            assert np.all(np.diff(cost) <= 0), "units are ordered longest first"
+        for m in range(L + 1):
+            assert len(set(xcd[au[:, U_M] == m])) == 1
+        assert np.all(au[~real][:, U_M] == -1)
+        au = au[real]
         cover = {}
         for u in au:
             m, js, jw, j0, j1, r = (int(v) for v in u[[U_M, U_JS, U_JW, U_PB, U_J1, U_RST]])
@@ -380,8 +392,6 @@ def test_restart_states_match_recurrence():
             segs = sorted(cover[m])
             assert segs[0][0] == 0 and segs[-1][1] == L - m + 1
             assert all(a[1] == b[0] for a, b in zip(segs, segs[1:]))
-        cost = au[:, U_J1] - au[:, U_JS]
-        assert np.all(np.diff(cost) <= 0), "units are ordered longest first"
         # a restart state equals the recurrence run from the lane starts
         ry = t[T_RSTY].reshape(-1, npair, 2)
         assert t[T_RSTK].size == 0
