@@ -379,18 +379,22 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
         synth_block8(s, bet, qs, j, nj);
         j += 8;
     }
-    // Every lane has started: whole segments, straight-line.
+    // Every lane has started: whole segments, straight-line, the scalar
+    // operands of each 4-step block loaded one block ahead.
+    SBlock<FW> cur;
+    load_block(cur, bet, qs, j);
+    int shn = j < nj ? segexp[j / kSegLen] : 0;
     for (int js = j; js < nj; js += kSegLen) {
         const int je = min(js + kSegLen, nj);
-        rescale(s.ua, s.ub, segexp[js / kSegLen]);
+        rescale(s.ua, s.ub, shn);
+        shn = js + kSegLen < nj ? segexp[js / kSegLen + 1] : 0;
         if (je - js == kSegLen) {
 #pragma unroll
-            for (int bk = 0; bk < kSegLen; bk += 8) {
-                SBlock<FW> b0, b1;
-                load_block(b0, bet, qs, js + bk);
-                load_block(b1, bet, qs, js + bk + 4);
-                synth_block4(s, b0, 4);
-                synth_block4(s, b1, 4);
+            for (int bk = 0; bk < kSegLen; bk += 4) {
+                SBlock<FW> nxt;
+                load_block(nxt, bet, qs, js + bk + 4);
+                synth_block4(s, cur, 4);
+                cur = nxt;
             }
         } else {
             // last, partial segment of the order
@@ -444,8 +448,10 @@ struct AState {
 __device__ __forceinline__ double swap_lane_pair(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    // every lane is active here, so the "old" operand is never used; passing
+    // the source itself saves the moves that would initialise it
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0xB1, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
