@@ -148,30 +148,18 @@ __device__ __forceinline__ void start_lanes(double (&ua)[LP], double (&ub)[LP], 
 // Analysis: the start steps stay in registers and the stored states in this
 // lane's slots in LDS (read back only at the checkpoints of the start
 // window, so they hold no registers through the degree loop).
-// pwin[p] (wave-uniform) is the last step at which a lane of pair slot p
-// starts inside the unit, or -1: a slot past its window is left alone.  The
-// states y were read from LDS one pass ahead.
 template <int LP>
-__device__ __forceinline__ void start_lanes_pre(double (&ua)[LP], double (&ub)[LP], const int (&sj)[LP],
-                                                const int (&pwin)[LP], const double2 (&y)[LP], int j)
-{
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        if (j > pwin[p]) continue;
-        const bool go = sj[p] == j;
-        ua[p] = go ? y[p].x : ua[p];
-        ub[p] = go ? y[p].y : ub[p];
-    }
-}
-
-template <int LP>
-__device__ __forceinline__ void read_starts(double2 (&y)[LP], const int (&pwin)[LP], const double2 (*sy)[64],
-                                            int j)
+__device__ __forceinline__ void start_lanes_lds(double (&ua)[LP], double (&ub)[LP], const int (&sj)[LP],
+                                                const double2 (*sy)[64], int j)
 {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int p = 0; p < LP; p++)
-        if (j <= pwin[p]) y[p] = sy[p][lane];
+    for (int p = 0; p < LP; p++) {
+        const double2 y = sy[p][lane];
+        const bool go = sj[p] == j;
+        ua[p] = go ? y.x : ua[p];
+        ub[p] = go ? y.y : ub[p];
+    }
 }
 
 template <int LP>
@@ -379,16 +367,15 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
         }
     }
 
-    // Start window: blocks of 8 steps from the first start, lanes joining at
-    // the checkpoints (multiples of kInject), up to the segment boundary after
-    // the last start.  (The shift is 0 off segment boundaries: an
-    // unconditional ldexp, not a branch, which the compiler would turn into
-    // selects.)
-    static_assert(kInject % 8 == 0 && kSegLen % kInject == 0, "checkpoints fall on block starts");
+    // Start window: blocks of kInject steps from the first start, lanes
+    // joining at block boundaries, up to the segment boundary after the last
+    // start.  (The shift is 0 off segment boundaries: an unconditional
+    // ldexp, not a branch, which the compiler would turn into selects.)
+    static_assert(kInject == 8, "the start window advances in blocks of 8 steps");
     int j = jstart;
     while (j < nj && (j <= jwin || j % kSegLen != 0)) {
         rescale(s.ua, s.ub, (j > jstart && j % kSegLen == 0) ? segexp[j / kSegLen] : 0);
-        if (j % kInject == 0) start_lanes(s.ua, s.ub, st, j);
+        start_lanes(s.ua, s.ub, st, j);
         synth_block8(s, bet, qs, j, nj);
         j += 8;
     }
@@ -540,7 +527,7 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
     constexpr int RS = NT + 2 * PR;
     static_assert(2 * NR * PR == NT, "the threads cover the outputs");
     static_assert(kSegLen % SC == 0, "passes tile a segment");
-    static_assert(kInject % SC == 0, "lanes start at pass boundaries");
+    static_assert(SC % kInject == 0, "lanes start at pass boundaries or inside them");
     // One wave executes its LDS operations in order, so with W = 1 the reads
     // of the previous pass, issued before this pass's writes, need neither a
     // second buffer nor a barrier.
@@ -652,18 +639,6 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o));
     first = __builtin_amdgcn_readfirstlane(first);
-    // per pair slot: the last step at which one of its lanes starts inside
-    // the unit (lanes live from the restart state, or starting later, need
-    // no injection here).  The polar slots start over a long range of
-    // degrees, the others within a few steps of the order's first degree.
-    int pwin[LP];
-#pragma unroll
-    for (int p = 0; p < LP; p++) {
-        int v = (sj[p] >= js0 && sj[p] < j1) ? sj[p] : -1;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
-        pwin[p] = __builtin_amdgcn_readfirstlane(v);
-    }
 
     // Warm L2 with the beta entries of this unit (one word per 64-byte line
     // per lane, consumed at the end; see the synthesis kernel).
@@ -689,12 +664,6 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
     // stored.
     DBlk<SC> bn;
     load_blk(bn, bet + js0);
-    // start states of the slots still in their window, read one pass ahead
-    // (the reads complete under the previous pass's sums)
-    double2 ynext[LP];
-#pragma unroll
-    for (int p = 0; p < LP; p++) ynext[p] = make_double2(0.0, 0.0);
-    if (js0 <= jwin) read_starts(ynext, pwin, start_y[wv], js0);
     int shn = 0;        // js0 is a segment start (the plan rounds it down)
     int buf = 0;
     for (int c = js0; c < j1 + SC; c += SC) {
@@ -719,8 +688,16 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
                 // wave-uniform: no lane live in the pass
 #pragma unroll
                 for (int r = 0; r < NR; r++) red[buf][r][col] = 0.0;
+            } else if (c <= jwin) {
+#pragma unroll
+                for (int t = 0; t < SC; t++) {
+                    if (t % kInject == 0) start_lanes_lds(s.ua, s.ub, sj, start_y[wv], c + t);
+                    double v[FW];
+                    analys_step(s, t, b.v[t], v);
+#pragma unroll
+                    for (int f = 0; f < FW; f++) red[buf][t * FW + f][col] = v[f];
+                }
             } else {
-                if (c <= jwin && c % kInject == 0) start_lanes_pre(s.ua, s.ub, sj, pwin, ynext, c);
 #pragma unroll
                 for (int t = 0; t < SC; t++) {
                     double v[FW];
@@ -748,10 +725,6 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
                 if (m == 0 && comp == 1) val = 0.0;
                 a.out[qoff[f_out] + 2 * (base + j_out) + comp] = val;
             }
-        }
-        {
-            const int cn = c + SC;
-            if (cn <= jwin && cn < j1 && cn % kInject == 0) read_starts(ynext, pwin, start_y[wv], cn);
         }
         if (W > 1) __syncthreads();
         buf = (NB - 1) & (buf ^ 1);

@@ -33,7 +33,7 @@ constexpr int kGuardEvery = 4;
 // (u_{j-2}, u_{j-1}) entering that step as plain doubles.  A latitude that
 // never reaches the threshold for an order never starts.
 constexpr int kPolarLog2 = -200;
-constexpr int kInject = 16;
+constexpr int kInject = 8;
 // Analysis accumulates kChunk consecutive degrees per lane before a
 // cross-lane reduction.
 constexpr int kChunk = 16;

@@ -150,9 +150,8 @@ def test_start_values_scaled_exponents():
 
 def _lane_walk(t, L, M, npair, m, upto=None):
     """Yields (j, ua or ub, parity) along the kernels' per-lane recurrence for
-    order m: every lane holds 0 until its start step (a multiple of the
-    checkpoint spacing, tiling table entry 7), where it takes the state
-    stored by the plan; segment shifts at multiples of 32.
+    order m: every lane holds 0 until its start step (a multiple of 8), where
+    it takes the state stored by the plan; segment shifts at multiples of 32.
     Vectorised over latitude pairs."""
     xp, beta = t[T_XP], t[T_BETA]
     sege, sego = t[T_SEGE], t[T_SEGO]
@@ -160,7 +159,6 @@ def _lane_walk(t, L, M, npair, m, upto=None):
     sy = t[T_INJY].reshape(M + 1, npair, 2)[m]
     base = oracle.lm_index(L, m, m)
     nj = L - m + 1 if upto is None else upto
-    kinj = int(t[T_TIL][7])
     ua = np.zeros(npair)
     ub = np.zeros(npair)
     for j in range(0, nj, 2):
@@ -168,7 +166,7 @@ def _lane_walk(t, L, M, npair, m, upto=None):
             sc = 2.0 ** sege[sego[m] + j // 32]
             ua *= sc
             ub *= sc
-        if j % kinj == 0:
+        if j % 8 == 0:
             go = sj == j
             ua = np.where(go, sy[:, 0], ua)
             ub = np.where(go, sy[:, 1], ub)
@@ -312,9 +310,9 @@ def test_emulated_values_stay_in_range():
 
 def test_lane_starts_against_long_double_oracle():
     # Sec. 3.5 guard and Sec. 3.1 polar threshold at plan time: before its
-    # start step a lane's |P_n^m| stays below 2^-200, the block of K steps
-    # from its start (K = checkpoint spacing) reaches it, and the stored
-    # state continues the recurrence onto the true P_n^m (long-double oracle, whose exponent
+    # start step a lane's |P_n^m| stays below 2^-200, the block of 8 steps
+    # from its start reaches it, and the stored state continues the
+    # recurrence onto the true P_n^m (long-double oracle, whose exponent
     # range covers these values at lmax 1023).
     L, nlat = 1023, 1024
     h = S.shtn_plan(L, L, nlat, 2048)
@@ -330,14 +328,14 @@ def test_lane_starts_against_long_double_oracle():
             base = oracle.lm_index(L, m, m)
             i0 = int(first[m])
             assert np.all(sj[m, :i0] == nj)         # cut pairs never start
-            assert np.all(sj[m, i0:] < nj) and np.all(sj[m, i0:] % int(t[T_TIL][7]) == 0)
+            assert np.all(sj[m, i0:] < nj) and np.all(sj[m, i0:] % 8 == 0)
             for i in sorted({i0, min(i0 + 1, npair - 1), (i0 + npair) // 2, npair - 1}):
                 j = int(sj[m, i])
                 P = oracle.plm(L, m, np.array([x[i]]), precision="ld")[:, 0]
                 Pm = np.abs(P[base:base + nj])
                 assert np.all(Pm[:j] < 2.0**-200), (m, i)
                 # (the plan compares binary exponents: the threshold is met from 2^-201 on)
-                assert Pm[j:j + int(t[T_TIL][7])].max() >= 2.0**-201, (m, i)
+                assert Pm[j:j + 8].max() >= 2.0**-201, (m, i)
                 # two steps from the stored state
                 ua, ub = sy[m, i]
                 ua = x[i] * ub + t[T_BETA][base + j] * ua
