@@ -139,6 +139,60 @@ def batch_measure(dev, reps):
             "round_trip_rel_err": err}
 
 
+def polar_curve(lmaxes, thresholds, reps):
+    """Accuracy against work of the polar threshold (Sec. 3.1): for each lmax
+    (nlat = lmax + 1, nphi = 2 (lmax + 1), one field, spectrum
+    N(0,1)(n+1)^-1.5 drawn from a seed per lmax) and each threshold exponent,
+    the Legendre kernel times (library event timing, mean over reps
+    launches) and the max relative differences of the synthesis grid and
+    of the analysis of the default-threshold grid from their default-threshold
+    results.  `active` is the fraction of (n, m, latitude pair) triples on
+    which a lane is live (the work the threshold leaves)."""
+    import numpy as np
+    import torch
+    from paper_1202_6522_amd import inputs
+    from paper_1202_6522_amd import shtn as S
+    dev = torch.device("cuda:0")
+    rows = []
+    for L in lmaxes:
+        rng = np.random.default_rng(inputs.SEED_BASE + 100 + L)
+        Q = torch.from_numpy(inputs.draw_spectrum(rng, L, L, 1.5, 1)).to(dev)
+        plan = S.Plan(L, L, L + 1, 2 * (L + 1), device=dev)
+        g0 = plan.synth(Q)
+        a0 = plan.analys(g0)
+        torch.cuda.synchronize(dev)
+        total = float(plan.legendre_flops()) / 8.0  # (n, m, pair) triples
+        for thr in thresholds:
+            plan.set_polar(thr)
+            sj = S.shtn_plan_table(plan.handle, 15).reshape(L + 1, -1)
+            nj = (L - np.arange(L + 1) + 1)[:, None]
+            active = float(np.clip(nj - sj, 0, None).sum()) / total
+            g = plan.synth(Q)
+            a = plan.analys(g0)
+            for _ in range(2):
+                plan.synth(Q)
+                plan.analys(g0)
+            torch.cuda.synchronize(dev)
+            S.shtn_profile_reset()
+            S.shtn_profile_enable(True)
+            for _ in range(reps):
+                plan.synth(Q)
+                plan.analys(g0)
+            torch.cuda.synchronize(dev)
+            S.shtn_profile_enable(False)
+            t = {name: 1e3 * S.shtn_profile_read(k)[0] / max(1, S.shtn_profile_read(k)[1])
+                 for k, name in S.PROFILE_KINDS.items()}
+            row = {"lmax": L, "log2_threshold": thr, "active": round(active, 4),
+                   "synth_us": round(t["legendre_synth"], 1), "analys_us": round(t["legendre_analys"], 1),
+                   "synth_rel_diff": float((g - g0).abs().max() / g0.abs().max()),
+                   "analys_rel_diff": float((a - a0).abs().max() / a0.abs().max())}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+        del plan, g0, a0, Q
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,11 +201,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain copy kernel over MIB MiB (for counter scaling)")
+    ap.add_argument("--polar-curve", default="", metavar="LMAX,...",
+                    help="instead of the benchmark: polar-threshold accuracy/time table at these lmax")
+    ap.add_argument("--thresholds", default="-200,-120,-80,-60,-40,-30,-20",
+                    help="threshold exponents for --polar-curve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.polar_curve:
+        polar_curve([int(v) for v in args.polar_curve.split(",")],
+                    [int(v) for v in args.thresholds.split(",")], max(1, args.steps // 20))
+        return
 
     import numpy as np
     import torch

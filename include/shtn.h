@@ -125,8 +125,9 @@ double shtn_legendre_flops(shtn_plan_t plan);
  * (int32), 8 segment offsets per m (int32, mmax+2), 9 analysis restart
  * states (double, nrestart x npair x 2), 10 empty (kept for numbering),
  * 11 analysis units (int32 x 12 each), 12 synthesis units (int32 x 12 each),
- * 13 tiling (int32 x 8: synth_lp, analys_lp, fw, m_pairing, split, fft_rows,
- * analys_waves, start checkpoint spacing), 14 first latitude pair that
+ * 13 tiling (int32 x 9: synth_lp, analys_lp, fw, m_pairing, split, fft_rows,
+ * analys_waves, start checkpoint spacing, polar threshold exponent),
+ * 14 first latitude pair that
  * ever reaches the polar threshold, per m (int32), 15 start step of every
  * (order, pair) lane (int32, (mmax+1) x npair; lmax-m+1 = never), 16 the
  * recurrence state entering that step (double, (mmax+1) x npair x 2).
@@ -148,6 +149,20 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
  * re-upload afterwards.  Returns SHTN_EINVAL for unsupported values. */
 int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int analys_waves, int fw,
                          int m_pairing, int split, int fft_rows);
+
+/* Polar threshold (Sec. 3.1, polar optimisation): every (order m, latitude
+ * pair) lane enters the recurrence sums only from the first checkpoint
+ * (multiple of 8 degrees) of the 8-degree block in which |P_n^m(x)| first
+ * reaches 2^log2_threshold; earlier terms are dropped, and a latitude whose
+ * |P_n^m| never reaches it for an order takes no part in that order.  The
+ * default, -200, drops only terms below 1e-60 relative to the orthonormal
+ * scale of P, so results match the plain definition to rounding.  Raising it
+ * (say -40 to -20) skips more of the polar work at large lmax, at an error
+ * of the order of 2^log2_threshold times the spectrum norm.  log2_threshold
+ * must lie in [-1000, -1], else SHTN_EINVAL.  Host only: recomputes the lane
+ * starts, unit lists and restart tables; re-upload afterwards (the plan is
+ * not uploaded until then, calls return SHTN_ESTATE). */
+int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
 
 /* ---- batches of fields with different truncations (one launch per stage) ----
  *

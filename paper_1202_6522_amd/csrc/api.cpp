@@ -324,8 +324,8 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     const Plan& p = *plan->p;
     const void* src = nullptr;
     size_t n = 0;
-    int tiling[8] = {p.tiling.synth_lp, p.tiling.analys_lp, p.tiling.fw, p.tiling.m_pairing,
-                     p.split_used, rows_per_block(p), p.tiling.analys_waves, kInject};
+    int tiling[9] = {p.tiling.synth_lp, p.tiling.analys_lp, p.tiling.fw, p.tiling.m_pairing,
+                     p.split_used, rows_per_block(p), p.tiling.analys_waves, kInject, p.polar_log2};
     switch (which) {
     case 0: src = p.xp.data(); n = p.xp.size() * 8; break;
     case 1: src = p.sp.data(); n = p.sp.size() * 8; break;
@@ -383,6 +383,36 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
     std::string err;
     if (rebuild_units(p, err)) {
         p.tiling = old;
+        rebuild_units(p, err);
+        build_image(p);
+        return fail(SHTN_EINVAL, err);
+    }
+    build_image(p);
+    p.uploaded = false;
+    p.dev = nullptr;
+    return SHTN_OK;
+}
+
+int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (log2_threshold < -1000 || log2_threshold > -1)
+        return fail(SHTN_EINVAL, "polar threshold exponent must lie in [-1000, -1]");
+    Plan& p = *plan->p;
+    if (log2_threshold == p.polar_log2) return SHTN_OK;
+    const int old = p.polar_log2;
+    p.polar_log2 = log2_threshold;
+    try {
+        lane_starts(p);
+    } catch (const std::bad_alloc&) {
+        p.polar_log2 = old;
+        lane_starts(p);
+        return fail(SHTN_ENOMEM, "polar threshold: out of host memory");
+    }
+    std::string err;
+    if (rebuild_units(p, err)) {
+        p.polar_log2 = old;
+        lane_starts(p);
         rebuild_units(p, err);
         build_image(p);
         return fail(SHTN_EINVAL, err);

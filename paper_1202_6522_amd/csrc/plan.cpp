@@ -84,7 +84,7 @@ static int log2_floor(ld v)
 // scaled form u = w 2^{-256 k} with the kernels' own steps (same segment
 // shifts, same fused multiply-adds).  The lane starts at the checkpoint
 // (multiple of kInject) that opens the first block of kInject steps in which
-// |P_n^m| reaches 2^kPolarLog2; the state entering that step, converted to a
+// |P_n^m| reaches 2^polar_log2; the state entering that step, converted to a
 // plain double (exact: it is far inside the normal range), is stored.  A lane
 // that never reaches the threshold gets the start step nj = lmax - m + 1.
 static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double& yb)
@@ -120,7 +120,7 @@ static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double
             if (v > 0.0) {
                 int e;
                 std::frexp(v, &e);
-                if (e - (long)kGuardUnit * k >= kPolarLog2) sig = true;
+                if (e - (long)kGuardUnit * k >= p.polar_log2) sig = true;
             }
         }
         if (sig) {
@@ -132,7 +132,7 @@ static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double
     }
 }
 
-static void lane_starts(Plan& p)
+void lane_starts(Plan& p)
 {
     const int M = p.M, np = p.npair;
     p.inj_j.assign((size_t)(M + 1) * np, 0);

@@ -26,7 +26,8 @@ constexpr int kSegLen = 32;
 constexpr int kGuardUnit = 256;
 constexpr int kGuardEvery = 4;
 // Polar threshold (Sec. 3.1, polar optimisation): contributions with
-// |P_n^m| < 2^kPolarLog2 are dropped.  A lane starts at the first checkpoint
+// |P_n^m| < 2^kPolarLog2 are dropped (the default; a plan may raise the
+// threshold, trading accuracy for work, see Plan::polar_log2).  A lane starts at the first checkpoint
 // (a multiple of kInject steps) of the block of kInject steps in which its
 // |P_n^m| first reaches 2^kPolarLog2; before it the lane holds 0, so it adds
 // exactly 0 and the kernels carry no exponent.  The host stores the state
@@ -131,6 +132,7 @@ struct Plan {
     Tiling tiling;
     int split_used = 0;
     int synth_wpg = 1;  // waves per synthesis workgroup for the unit order
+    int polar_log2 = kPolarLog2;  // lanes start where |P_n^m| first reaches 2^polar_log2
     // host tables
     std::vector<double> x, w;                 // full grid
     std::vector<double> xp, sp, wq, wfull;    // per pair
@@ -160,6 +162,7 @@ int rows_per_block(const Plan& p);  // FFT rows per workgroup for a plan
 // Host plan construction (plan.cpp).
 Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err);
 int rebuild_units(Plan& p, std::string& err);     // units + restart states for the tiling
+void lane_starts(Plan& p);                        // start step and state of every (order, pair) lane
 // First / last start step of the lanes [i0, i1) of order m that start in
 // [lo, hi); false if none does.
 bool start_range(const Plan& p, int m, int i0, int i1, int lo, int hi, int& jmin, int& jmax);

@@ -48,6 +48,7 @@ _SIGS = {
     "shtn_legendre_flops": (_c.c_double, [_vp]),
     "shtn_plan_table": (_c.c_long, [_vp, _c.c_int, _vp, _sz]),
     "shtn_plan_set_tiling": (_c.c_int, [_vp] + [_c.c_int] * 7),
+    "shtn_plan_set_polar": (_c.c_int, [_vp, _c.c_int]),
     "shtn_batch": (_vp, [_c.c_int, _c.POINTER(_vp)]),
     "shtn_batch_destroy": (None, [_vp]),
     "shtn_batch_offsets": (_c.c_int, [_vp, _c.POINTER(_sz), _c.POINTER(_sz)]),
@@ -193,6 +194,10 @@ def shtn_plan_table(h, which):
     return out
 
 
+def shtn_plan_set_polar(h, log2_threshold):
+    return check(load_library().shtn_plan_set_polar(h, log2_threshold), "shtn_plan_set_polar")
+
+
 def shtn_plan_set_tiling(h, synth_lp, analys_lp, analys_waves, fw, m_pairing, split=0, fft_rows=0):
     return check(load_library().shtn_plan_set_tiling(h, synth_lp, analys_lp, analys_waves, fw,
                                                      m_pairing, split, fft_rows),
@@ -301,7 +306,7 @@ def _stream_ptr(torch, device):
 class Plan:
     """A transform plan whose tables live in a torch-owned device buffer."""
 
-    def __init__(self, lmax, mmax=None, nlat=None, nphi=None, device="cuda", tiling=None):
+    def __init__(self, lmax, mmax=None, nlat=None, nphi=None, device="cuda", tiling=None, polar_log2=None):
         import torch
         self.lmax = int(lmax)
         self.mmax = int(lmax if mmax is None else mmax)
@@ -313,6 +318,8 @@ class Plan:
         self.npair = (self.nlat + 1) // 2
         self._work = {}
         self._dev = None
+        if polar_log2 is not None:
+            shtn_plan_set_polar(self.handle, int(polar_log2))
         if tiling is not None:
             self.set_tiling(**tiling)
         else:
@@ -330,6 +337,14 @@ class Plan:
         shtn_plan_set_tiling(self.handle, synth_lp, analys_lp, analys_waves, fw, m_pairing, split,
                              fft_rows)
         self._upload()
+
+    def set_polar(self, log2_threshold):
+        """Polar threshold exponent (see shtn_plan_set_polar); re-uploads."""
+        shtn_plan_set_polar(self.handle, int(log2_threshold))
+        self._upload()
+
+    def polar_log2(self):
+        return int(shtn_plan_table(self.handle, 13)[8])
 
     def tiling(self):
         t = shtn_plan_table(self.handle, 13)

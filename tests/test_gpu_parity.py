@@ -245,3 +245,33 @@ def test_bad_calls_raise(dev):
     big = make_plan(4200, 100, 4201, 256, dev)
     with pytest.raises(S.ShtnError):
         big.analys(torch.zeros(4201, 256, dtype=torch.float64, device=dev))
+
+
+def test_polar_threshold_error_bound(dev):
+    # Sec. 3.1 polar optimisation with a raised threshold 2^-30: every
+    # dropped term has |P_n^m| < 2^-30, so the synthesis moves by at most
+    # 2 2^-30 sum|Q| (F_m enters the grid with weight <= 2) and the analysis
+    # by at most 2^-30 sum_i w_i |F_m| <= 2^-30 (sum w = 2) (2 pi max|f|).
+    # The default threshold must not move at all relative to itself.
+    from paper_1202_6522_amd import shtn as S
+    L = 511
+    rng = np.random.default_rng(inputs.SEED_BASE + 40)
+    Qh = inputs.draw_spectrum(rng, L, L, 1.5, 1)
+    Q = torch.from_numpy(Qh).to(dev)
+    exact = S.Plan(L, L, L + 1, 2 * (L + 1), device=dev)
+    cut = S.Plan(L, L, L + 1, 2 * (L + 1), device=dev, polar_log2=-30)
+    assert cut.polar_log2() == -30 and exact.polar_log2() == -200
+    g0 = exact.synth(Q)
+    g1 = cut.synth(Q)
+    dg = float((g1 - g0).abs().max())
+    bound_s = 2.0 * 2.0**-30 * float(np.abs(Qh).sum())
+    assert 0.0 < dg <= bound_s, (dg, bound_s)
+    a0 = exact.analys(g0)
+    a1 = cut.analys(g0)
+    da = float((a1 - a0).abs().max())
+    bound_a = 2.0**-30 * 2.0 * 2.0 * np.pi * float(g0.abs().max())
+    assert 0.0 < da <= bound_a, (da, bound_a)
+    # back to the default: identical to the plan that never changed
+    cut.set_polar(-200)
+    assert torch.equal(cut.synth(Q), g0)
+    assert torch.equal(cut.analys(g0), a0)

@@ -308,14 +308,18 @@ def test_emulated_values_stay_in_range():
         S.shtn_plan_destroy(h)
 
 
-def test_lane_starts_against_long_double_oracle():
+@pytest.mark.parametrize("thr", [-200, -40])
+def test_lane_starts_against_long_double_oracle(thr):
     # Sec. 3.5 guard and Sec. 3.1 polar threshold at plan time: before its
-    # start step a lane's |P_n^m| stays below 2^-200, the block of 8 steps
+    # start step a lane's |P_n^m| stays below 2^thr, the block of 8 steps
     # from its start reaches it, and the stored state continues the
     # recurrence onto the true P_n^m (long-double oracle, whose exponent
-    # range covers these values at lmax 1023).
+    # range covers these values at lmax 1023).  thr = -200 is the default;
+    # -40 a raised threshold set with shtn_plan_set_polar.
     L, nlat = 1023, 1024
     h = S.shtn_plan(L, L, nlat, 2048)
+    if thr != -200:
+        S.shtn_plan_set_polar(h, thr)
     try:
         t = _tables(h)
         npair = nlat // 2
@@ -329,13 +333,13 @@ def test_lane_starts_against_long_double_oracle():
             i0 = int(first[m])
             assert np.all(sj[m, :i0] == nj)         # cut pairs never start
             assert np.all(sj[m, i0:] < nj) and np.all(sj[m, i0:] % 8 == 0)
-            for i in sorted({i0, min(i0 + 1, npair - 1), (i0 + npair) // 2, npair - 1}):
+            for i in sorted({i0, min(i0 + 1, npair - 1), (i0 + npair) // 2, npair - 1} - {npair}):
                 j = int(sj[m, i])
                 P = oracle.plm(L, m, np.array([x[i]]), precision="ld")[:, 0]
                 Pm = np.abs(P[base:base + nj])
-                assert np.all(Pm[:j] < 2.0**-200), (m, i)
-                # (the plan compares binary exponents: the threshold is met from 2^-201 on)
-                assert Pm[j:j + 8].max() >= 2.0**-201, (m, i)
+                assert np.all(Pm[:j] < 2.0**thr), (m, i)
+                # (the plan compares binary exponents: the threshold is met from 2^(thr-1) on)
+                assert Pm[j:j + 8].max() >= 2.0**(thr - 1), (m, i)
                 # two steps from the stored state
                 ua, ub = sy[m, i]
                 ua = x[i] * ub + t[T_BETA][base + j] * ua
@@ -438,12 +442,15 @@ def test_synthesis_units_cover_all_work():
             S.shtn_plan_destroy(h)
 
 
-def test_polar_cut_drops_only_negligible_latitudes():
+@pytest.mark.parametrize("thr", [-200, -40])
+def test_polar_cut_drops_only_negligible_latitudes(thr):
     # Sec. 3.1 polar optimisation: the first kept pair per order is where
-    # max_n |P_n^m| first reaches 2^-200; checked with the long-double oracle,
+    # max_n |P_n^m| first reaches 2^thr; checked with the long-double oracle,
     # whose range (1e-4951) covers these values.
     L, nlat = 1023, 1024
     h = S.shtn_plan(L, L, nlat, 2048)
+    if thr != -200:
+        S.shtn_plan_set_polar(h, thr)
     try:
         first = S.shtn_plan_table(h, T_FIRST)
         x = S.shtn_plan_table(h, T_XP)
@@ -455,8 +462,8 @@ def test_polar_cut_drops_only_negligible_latitudes():
             P = oracle.plm(L, m, xs, precision="ld")
             rows = slice(oracle.lm_index(L, m, m), oracle.lm_index(L, L, m) + 1)
             Pm = np.abs(P[rows])
-            assert Pm[:, 0].max() < 2.0**-200, m       # dropped pair: negligible
-            assert Pm[:, 1].max() >= 2.0**-201, m      # first kept pair: at the threshold
+            assert Pm[:, 0].max() < 2.0**thr, m        # dropped pair: negligible
+            assert Pm[:, 1].max() >= 2.0**(thr - 1), m # first kept pair: at the threshold
     finally:
         S.shtn_plan_destroy(h)
 
@@ -498,3 +505,34 @@ def test_batch_layout_and_state_errors(lib):
     finally:
         for h in hs.values():
             S.shtn_plan_destroy(h)
+
+
+def test_polar_threshold_setting():
+    # shtn_plan_set_polar: range check, the plan reports the exponent, a
+    # raised threshold only delays lane starts (never advances one) and cuts
+    # at least as many polar latitudes, and the default restores the tables.
+    L = 255
+    h = S.shtn_plan(L, L, 256, 512)
+    try:
+        base = _tables(h)
+        assert int(base[T_TIL][8]) == -200
+        for bad in (-1001, 0, 5):
+            with pytest.raises(S.ShtnError):
+                S.shtn_plan_set_polar(h, bad)
+        S.shtn_plan_set_polar(h, -30)
+        t = _tables(h)
+        assert int(t[T_TIL][8]) == -30
+        assert np.all(t[T_INJJ] >= base[T_INJJ]) and np.any(t[T_INJJ] > base[T_INJJ])
+        assert np.all(t[T_FIRST] >= base[T_FIRST])
+        # units still cover every order's degrees once
+        au = t[T_AU].reshape(-1, UI)
+        au = au[au[:, U_M] >= 0]
+        for m in (0, 100, 255):
+            segs = sorted((int(u[U_PB]), int(u[U_J1])) for u in au if u[U_M] == m)
+            assert segs[0][0] == 0 and segs[-1][1] == L - m + 1
+        S.shtn_plan_set_polar(h, -200)
+        again = _tables(h)
+        for k in (T_INJJ, T_INJY, T_FIRST, T_AU, T_SU, T_RSTY):
+            assert np.array_equal(again[k], base[k]), k
+    finally:
+        S.shtn_plan_destroy(h)
