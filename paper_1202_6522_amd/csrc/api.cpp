@@ -98,6 +98,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     f.plans = dplan(p);
     f.rows_per_block = rows_per_block(p);
     f.nblocks = (p.nlat + f.rows_per_block - 1) / f.rows_per_block;
+    f.points = f.rows_per_block * p.K;
     f.grid_y = nfields;
     f.K = p.K;
     f.in = F;
@@ -126,6 +127,7 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     f.plans = dplan(p);
     f.rows_per_block = rows_per_block(p);
     f.nblocks = (p.nlat + f.rows_per_block - 1) / f.rows_per_block;
+    f.points = f.rows_per_block * p.K;
     f.grid_y = nfields;
     f.K = p.K;
     f.in = grid;

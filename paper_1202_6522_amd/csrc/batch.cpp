@@ -68,6 +68,7 @@ struct shtn_batch_s {
     std::vector<int> synth_units, analys_units, rowblocks;
     std::vector<AnalysClass> classes;
     int synth_wpg = 1;
+    int fft_points = 1;  // most complex points in one FFT row block
     int fft_kmax = 1;  // longest FFT rows of the batch (sizes the FFT's LDS)
     // device image
     std::vector<unsigned char> image;
@@ -204,7 +205,11 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
 
     // ---- FFT row blocks: {slot, plan, first row, rows} ----
     b.fft_kmax = 1;
-    for (auto* p : b.plans) b.fft_kmax = std::max(b.fft_kmax, p->K);
+    b.fft_points = 1;
+    for (auto* p : b.plans) {
+        b.fft_kmax = std::max(b.fft_kmax, p->K);
+        b.fft_points = std::max(b.fft_points, rows_per_block(*p) * p->K);
+    }
     b.rowblocks.clear();
     for (int s = 0; s < ns; s++) {
         const Plan& p = *b.plans[b.slot_plan[s]];
@@ -293,6 +298,7 @@ int run_synth(const shtn_batch_s& b, const double* Q, double* grid, void* work, 
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
     f.K = b.fft_kmax;
+    f.points = b.fft_points;
     f.nblocks = (int)(b.rowblocks.size() / 4);
     f.grid_y = 1;
     f.g_off = dev_at<const long>(b, b.off_g);
@@ -318,6 +324,7 @@ int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work,
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
     f.K = b.fft_kmax;
+    f.points = b.fft_points;
     f.nblocks = (int)(b.rowblocks.size() / 4);
     f.grid_y = 1;
     f.g_off = dev_at<const long>(b, b.off_g);

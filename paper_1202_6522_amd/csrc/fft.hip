@@ -7,21 +7,22 @@
 // passes (a 16-point DFT in registers as 4 x 4) and one radix-4 or radix-2
 // pass for the remaining factor: three passes through LDS at K = 1024.
 //
-// A workgroup of four waves holds 4096 complex points in LDS: 4096/K rows
-// (K <= 4096), a whole number of 4-latitude tiles of F when K <= 1024, so the
-// Fourier coefficients come and go as contiguous tiles.  Every thread owns 16
-// points of every pass (16/R butterflies of radix R); all index arithmetic is
-// shifts and masks (K is a power of two).  Row blocks are spread over the
-// XCDs so that neighbouring blocks share an L2.
+// A workgroup holds rows x K <= 4096 complex points in LDS with one thread
+// per 16 points (one to four waves), so several workgroups share a CU; the
+// twiddles come from a two-level table of at most 128 entries in LDS.  Every
+// thread owns 16 points of every pass (16/R butterflies of radix R); all
+// index arithmetic is shifts and masks (K is a power of two).  Row blocks are
+// spread over the XCDs so that neighbouring blocks share an L2.
 #include <hip/hip_runtime.h>
 
 #include "shtn_internal.h"
 
 namespace shtn {
 
-constexpr int kFftThreads = 256;              // four waves
-constexpr int kFftPoints = 4096;              // complex points per workgroup (LDS)
-constexpr int kFftPerThread = kFftPoints / kFftThreads;  // 16: one radix-16 butterfly per pass
+constexpr int kFftMaxThreads = 256;           // at most four waves
+constexpr int kFftPoints = 4096;              // complex points per workgroup at most (LDS)
+constexpr int kFftPerThread = 16;             // points per thread: one radix-16 butterfly per pass
+constexpr int kTwEntries = 128;               // two-level twiddle table, K <= 4096
 
 // Twiddle tables are read through global-address-space pointers (the plan
 // descriptor holds them as generic pointers, which would compile to flat
@@ -125,9 +126,18 @@ __device__ __forceinline__ void dft_r(double2 (&v)[R], int dir)
     }
 }
 
+// Twiddle e^{-2 pi i t/K} (0 <= t < K = 2^lgK) from the two-level table in
+// LDS: t = hi 2^lo + lo_part with lo = ceil(lgK/2); entries [0, 2^lo) hold
+// e^{-2 pi i b/K}, entries [2^lo, 2^lo + 2^(lgK-lo)) hold e^{-2 pi i a 2^lo/K}.
+__device__ __forceinline__ double2 tw_at(const double2* twl, int t, int lgK)
+{
+    const int lo = (lgK + 1) >> 1;
+    return cmul(twl[t & ((1 << lo) - 1)], twl[(1 << lo) + (t >> lo)]);
+}
+
 // One Stockham pass of radix R over the rows held in buf (npts = rows x K
 // points, K = 2^lgK); Ns = 2^lgNs = product of the radices of the previous
-// passes; twl = the twiddle table e^{-2 pi i t/K} in LDS.  Each thread reads
+// passes; twl = the two-level twiddle table in LDS.  Each thread reads
 // its 16/R butterflies, the workgroup synchronises, then they are written
 // back in place.  dir = -1 forward (e^{-2 pi i}), +1 inverse.
 template <int R, int LGR>
@@ -142,7 +152,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
     int dst[NB];
 #pragma unroll
     for (int i = 0; i < NB; i++) {
-        const int b = threadIdx.x + i * kFftThreads;
+        const int b = threadIdx.x + i * blockDim.x;
         dst[i] = -1;
         if (b < nb) {
             const int r = b >> lgKR, jj = b & (KR - 1);
@@ -155,7 +165,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
                 const int tstep = js << (lgK - lgNs - LGR);
 #pragma unroll
                 for (int q = 1; q < R; q++) {
-                    double2 w = twl[q * tstep];
+                    double2 w = tw_at(twl, q * tstep, lgK);
                     if (dir > 0) w = cconj(w);
                     v[i][q] = cmul(v[i][q], w);
                 }
@@ -191,11 +201,12 @@ __device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, in
     if (lgK - lgNs == 1) stockham_pass<2, 1>(buf, twl, lgK, npts, lgNs, dir);
 }
 
-// Copies the K twiddles e^{-2 pi i t/K} into LDS (consecutive threads,
-// consecutive entries).
-__device__ __forceinline__ void stage_twiddles(double2* twl, gdp tw, int K)
+// Builds the two-level twiddle table (see tw_at) from the K-entry table
+// e^{-2 pi i t/K} in global memory.
+__device__ __forceinline__ void stage_twiddles(double2* twl, gdp tw, int lgK)
 {
-    for (int t = threadIdx.x; t < K; t += kFftThreads) twl[t] = ld2(tw, t);
+    const int lo = (lgK + 1) >> 1, nlo = 1 << lo, n = nlo + (1 << (lgK - lo));
+    for (int t = threadIdx.x; t < n; t += blockDim.x) twl[t] = ld2(tw, t < nlo ? t : (t - nlo) << lo);
 }
 
 struct RowBlock {
@@ -242,7 +253,7 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
         for (int t = 0; t < nrows >> lgrun; t++) {
             const int i0 = row0 + (t << lgrun);  // first latitude of this run
             const long tb = (long)(i0 >> kFTileLg) * ts + (i0 & (kFTile - 1));
-            for (int e = threadIdx.x; e < per_tile; e += kFftThreads) {
+            for (int e = threadIdx.x; e < per_tile; e += blockDim.x) {
                 const int m = e >> lgrun, r = (t << lgrun) + (e & (run - 1));
                 const long off = tb + ((long)m << kFTileLg) + (e & (run - 1));
                 if (LOAD) {
@@ -256,7 +267,7 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
         }
     } else {
         const int n = nrows * (M + 1);
-        for (int e = threadIdx.x; e < n; e += kFftThreads) {
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
             const int r = e % nrows, m = e / nrows;
             const int i = row0 + r;
             const long off = (long)(i >> kFTileLg) * ts + ((long)m << kFTileLg) + (i & (kFTile - 1));
@@ -272,11 +283,11 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
 }
 
 // Fourier synthesis of rows: f_ik = Re F_0 + 2 Re sum_{m=1}^{M} F_m e^{2 pi i m k / N}.
-__global__ void __launch_bounds__(kFftThreads) k_c2r(FftArgs a)
+__global__ void __launch_bounds__(kFftMaxThreads) k_c2r(FftArgs a)
 {
-    extern __shared__ double2 lds[];  // points, then the twiddle table
+    extern __shared__ double2 lds[];  // points (16 per thread), then the twiddle table
     double2* buf = lds;
-    double2* twl = lds + lds_points(kFftPoints);
+    double2* twl = lds + lds_points(blockDim.x * kFftPerThread);
     const int pl = a.rowblocks ? a.rowblocks[4 * blockIdx.x + 1] : 0;
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
@@ -289,14 +300,14 @@ __global__ void __launch_bounds__(kFftThreads) k_c2r(FftArgs a)
     double* g = a.out + (a.g_off ? a.g_off[rb.field] : (long)rb.field * nlat * nphi);
     const int npts = rb.nrows << lgK;
 
-    stage_twiddles(twl, tw, K);
+    stage_twiddles(twl, tw, lgK);
     // w^m of this thread's points, loaded while the rows arrive
     double2 rw[kFftPerThread];
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++)
-        rw[e] = ld2(rtw, (threadIdx.x + e * kFftThreads) & (K - 1));
+        rw[e] = ld2(rtw, (threadIdx.x + e * blockDim.x) & (K - 1));
     // Y_m (Y_0 = Re F_0, Y_m = F_m for 1 <= m <= M, 0 above) row by row
-    for (int idx = threadIdx.x; idx < npts; idx += kFftThreads)
+    for (int idx = threadIdx.x; idx < npts; idx += blockDim.x)
         if ((idx & (K - 1)) > M) buf[at(idx)] = make_double2(0.0, 0.0);
     move_f<true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
     __syncthreads();
@@ -305,7 +316,7 @@ __global__ void __launch_bounds__(kFftThreads) k_c2r(FftArgs a)
     double2 z[kFftPerThread];
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * kFftThreads;
+        const int idx = threadIdx.x + e * blockDim.x;
         z[e] = make_double2(0.0, 0.0);
         if (idx < npts) {
             const int m = idx & (K - 1);
@@ -318,14 +329,14 @@ __global__ void __launch_bounds__(kFftThreads) k_c2r(FftArgs a)
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * kFftThreads;
+        const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) buf[at(idx)] = z[e];
     }
     __syncthreads();
     complex_fft(buf, twl, lgK, npts, +1);
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * kFftThreads;
+        const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) {
             const int r = idx >> lgK, k = idx & (K - 1);
             *(double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k) = buf[at(idx)];
@@ -334,11 +345,11 @@ __global__ void __launch_bounds__(kFftThreads) k_c2r(FftArgs a)
 }
 
 // Fourier analysis of rows: F_m(theta_i) = scale * sum_k f_ik e^{-2 pi i m k / N}, m <= M.
-__global__ void __launch_bounds__(kFftThreads) k_r2c(FftArgs a)
+__global__ void __launch_bounds__(kFftMaxThreads) k_r2c(FftArgs a)
 {
-    extern __shared__ double2 lds[];  // points, then the twiddle table
+    extern __shared__ double2 lds[];  // points (16 per thread), then the twiddle table
     double2* buf = lds;
-    double2* twl = lds + lds_points(kFftPoints);
+    double2* twl = lds + lds_points(blockDim.x * kFftPerThread);
     const int pl = a.rowblocks ? a.rowblocks[4 * blockIdx.x + 1] : 0;
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
@@ -350,10 +361,10 @@ __global__ void __launch_bounds__(kFftThreads) k_r2c(FftArgs a)
     const double* g = a.in + (a.g_off ? a.g_off[rb.field] : (long)rb.field * nlat * nphi);
     double* F = a.out + (a.f_off ? a.f_off[rb.field] : (long)rb.field * 2 * D.f_size);
     const int npts = rb.nrows << lgK;
-    stage_twiddles(twl, tw, K);
+    stage_twiddles(twl, tw, lgK);
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * kFftThreads;
+        const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) {
             const int r = idx >> lgK, k = idx & (K - 1);
             buf[at(idx)] = *(const double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k);
@@ -366,7 +377,7 @@ __global__ void __launch_bounds__(kFftThreads) k_r2c(FftArgs a)
     double2 rw[kFftPerThread];
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++)
-        rw[e] = ld2(rtw, (threadIdx.x + e * kFftThreads) & (K - 1));
+        rw[e] = ld2(rtw, (threadIdx.x + e * blockDim.x) & (K - 1));
     // scale <= 0: the analysis scale 2 pi / nphi of each field's plan
     const double sc = a.scale > 0.0 ? a.scale : 2.0 * 3.14159265358979323846 / nphi;
     // X_m from Z_m and Z_{K-m}, computed in registers, then written over the
@@ -374,7 +385,7 @@ __global__ void __launch_bounds__(kFftThreads) k_r2c(FftArgs a)
     double2 x[kFftPerThread];
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * kFftThreads;
+        const int idx = threadIdx.x + e * blockDim.x;
         x[e] = make_double2(0.0, 0.0);
         if (idx < npts) {
             const int m = idx & (K - 1);
@@ -392,7 +403,7 @@ __global__ void __launch_bounds__(kFftThreads) k_r2c(FftArgs a)
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * kFftThreads;
+        const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) buf[at(idx)] = x[e];
     }
     __syncthreads();
@@ -408,14 +419,25 @@ static FftArgs fft_args(const FftLaunch& l)
 
 int fft_rows_cap(int K) { return K <= kFftPoints ? kFftPoints / K : 1; }
 
-// Dynamic LDS of a launch whose longest rows have kmax points.
-static size_t fft_lds_bytes(int kmax) { return sizeof(double2) * ((size_t)lds_points(kFftPoints) + kmax); }
+// Threads of a launch whose largest block holds `points` complex points: one
+// per 16 points, whole waves, one to four.
+static int fft_threads(int points)
+{
+    const int t = (points + kFftPerThread - 1) / kFftPerThread;
+    return t < 64 ? 64 : (t > kFftMaxThreads ? kFftMaxThreads : (t + 63) / 64 * 64);
+}
+
+// Dynamic LDS for that thread count: 16 points per thread plus the twiddles.
+static size_t fft_lds_bytes(int threads)
+{
+    return sizeof(double2) * ((size_t)lds_points(threads * kFftPerThread) + kTwEntries);
+}
 
 // Allows the largest dynamic LDS of these kernels (above the 64 KB default).
 static int allow_lds()
 {
     static const int rc = [] {
-        const int bytes = (int)fft_lds_bytes(kFftPoints);
+        const int bytes = (int)fft_lds_bytes(kFftMaxThreads);
         hipError_t e = hipFuncSetAttribute((const void*)k_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -426,18 +448,20 @@ static int allow_lds()
 
 int launch_c2r(const FftLaunch& l, void* stream)
 {
-    if (l.K < 1 || l.K > kFftPoints) return (int)hipErrorInvalidValue;
+    if (l.K < 1 || l.K > kFftPoints || l.points < l.K || l.points > kFftPoints) return (int)hipErrorInvalidValue;
     if (int e = allow_lds()) return e;
-    hipLaunchKernelGGL(k_c2r, dim3(l.nblocks, l.grid_y), dim3(kFftThreads), fft_lds_bytes(l.K),
+    const int nt = fft_threads(l.points);
+    hipLaunchKernelGGL(k_c2r, dim3(l.nblocks, l.grid_y), dim3(nt), fft_lds_bytes(nt),
                        (hipStream_t)stream, fft_args(l));
     return (int)hipGetLastError();
 }
 
 int launch_r2c(const FftLaunch& l, void* stream)
 {
-    if (l.K < 1 || l.K > kFftPoints) return (int)hipErrorInvalidValue;
+    if (l.K < 1 || l.K > kFftPoints || l.points < l.K || l.points > kFftPoints) return (int)hipErrorInvalidValue;
     if (int e = allow_lds()) return e;
-    hipLaunchKernelGGL(k_r2c, dim3(l.nblocks, l.grid_y), dim3(kFftThreads), fft_lds_bytes(l.K),
+    const int nt = fft_threads(l.points);
+    hipLaunchKernelGGL(k_r2c, dim3(l.nblocks, l.grid_y), dim3(nt), fft_lds_bytes(nt),
                        (hipStream_t)stream, fft_args(l));
     return (int)hipGetLastError();
 }

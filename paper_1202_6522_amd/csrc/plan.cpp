@@ -370,7 +370,10 @@ int rebuild_units(Plan& p, std::string& err)
     } else {
         for (int m = 0; m <= M; m++)
             for (int b = 0; b < nblk; b++) emit(m, b);
-        p.synth_wpg = nblk <= max_wpg ? nblk : 1;
+        // the latitude blocks of one order, or an equal share of them
+        int wpg = std::min(nblk, max_wpg);
+        while (nblk % wpg) wpg--;
+        p.synth_wpg = wpg;
     }
 
     // ---- analysis units: (m, degree range) pieces, longest first ----
