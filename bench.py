@@ -139,6 +139,87 @@ def batch_measure(dev, reps):
             "round_trip_rel_err": err}
 
 
+def small_configs(dev, reps):
+    """The other single-field workloads (lmax 31 and 255): synthesis and
+    analysis kernel times (library event timing) and the round-trip error."""
+    import torch
+    from paper_1202_6522_amd import inputs
+    from paper_1202_6522_amd import shtn as S
+    out = {}
+    for case in (0, 1):
+        p, Qh = inputs.scalar_case(case)
+        L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+        plan = S.Plan(L, M, nlat, nphi, device=dev)
+        Q = torch.from_numpy(Qh).to(dev)
+        for _ in range(5):
+            g = plan.synth(Q)
+            R = plan.analys(g)
+        torch.cuda.synchronize(dev)
+        err = float((R - Q).abs().max() / Q.abs().max())
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        S.shtn_profile_reset()
+        S.shtn_profile_enable(True)
+        e0.record()
+        for _ in range(reps):
+            g = plan.synth(Q)
+            plan.analys(g)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        S.shtn_profile_enable(False)
+        kern = {name: 1e3 * S.shtn_profile_read(k)[0] / max(1, S.shtn_profile_read(k)[1])
+                for k, name in S.PROFILE_KINDS.items()}
+        fl = plan.legendre_flops()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        out["lmax%d" % L] = {
+            "round_trip_us": round(us, 2), "transforms_per_s": round(2e6 / us, 1),
+            "legendre_synth_us": round(kern["legendre_synth"], 2),
+            "legendre_analys_us": round(kern["legendre_analys"], 2),
+            "legendre_tflops": round(2 * fl / ((kern["legendre_synth"] + kern["legendre_analys"]) * 1e-6) / 1e12, 3),
+            "round_trip_rel_err": err}
+    return out
+
+
+def autograd_config(dev, reps):
+    """Differentiable workload: 16 fields, lmax 511 (nlat 512, nphi 1024);
+    loss sum_grid w (synth(Q) - T)^2, backward through the adjoint kernels.
+    Time of one forward + backward."""
+    import numpy as np
+    import torch
+    from paper_1202_6522_amd import inputs
+    from paper_1202_6522_amd import shtn as S
+    from paper_1202_6522_amd.autograd import synth
+    L = 511
+    rng = np.random.default_rng(inputs.SEED_BASE + 4)
+    plan = S.Plan(L, L, L + 1, 2 * (L + 1), device=dev)
+    T = synth(torch.from_numpy(inputs.draw_spectrum(rng, L, L, 1.5, 16)).to(dev), plan).detach()
+    Q0 = torch.from_numpy(inputs.draw_spectrum(rng, L, L, 1.5, 16)).to(dev)
+    _, w = plan.grid()
+    wg = torch.from_numpy(w).to(dev)[:, None]
+
+    def step():
+        Q = Q0.clone().requires_grad_(True)
+        loss = ((synth(Q, plan) - T) ** 2 * wg).sum()
+        loss.backward()
+        return Q.grad
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / reps
+    fl = 2 * 16 * plan.legendre_flops()  # synthesis + adjoint, 16 fields
+    return {"workload": "16 fields, lmax 511, loss sum_grid w (synth(Q) - T)^2, forward + backward",
+            "forward_backward_ms": round(ms, 3),
+            "legendre_tflops_lower_bound": round(fl / (ms * 1e-3) / 1e12, 3)}
+
+
 def polar_curve(lmaxes, thresholds, reps):
     """Accuracy against work of the polar threshold (Sec. 3.1): for each lmax
     (nlat = lmax + 1, nphi = 2 (lmax + 1), one field, spectrum
@@ -291,6 +372,12 @@ def main():
                             for k in ("legendre_synth", "legendre_analys")},
     }
     out["batch"] = batch_measure(dev, max(10, args.steps // 4))
+    out["small_configs"] = small_configs(dev, max(20, args.steps))
+    out["autograd"] = autograd_config(dev, max(5, args.steps // 20))
+    probe = S.shtn_fp64_probe_tflops(stream)
+    out["fp64_probe"] = {"tflops": round(probe, 2),
+                         "legendre_frac_of_probe": {k: round(flops / (kern[k]["avg_us"] * 1e-6) / 1e12 / probe, 4)
+                                                    for k in ("legendre_synth", "legendre_analys")}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, M, nlat, nphi, Qh[0])
     print(json.dumps(out))

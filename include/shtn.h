@@ -164,6 +164,14 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
  * not uploaded until then, calls return SHTN_ESTATE). */
 int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
 
+/* Measures the FP64 vector FMA rate (TFLOP/s, 2 flops per FMA) that the
+ * current device sustains with four waves per SIMD on independent chains
+ * with a scalar operand, the form of the Legendre kernels' inner loops: a
+ * reference for their achieved FLOP/s next to the published peak.  Not part
+ * of any transform.  Runs a few probe launches on `stream` (a hipStream_t)
+ * and synchronises it.  Returns a negative value on a HIP error. */
+double shtn_fp64_probe_tflops(void* stream);
+
 /* ---- batches of fields with different truncations (one launch per stage) ----
  *
  * Many independent fields, each with its own truncation and grid, transformed

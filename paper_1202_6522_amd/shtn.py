@@ -63,6 +63,7 @@ _SIGS = {
     "shtn_batch_replay": (_c.c_int, [_vp, _c.c_int, _vp]),
     "shtn_batch_tune": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c.c_int, _c.c_char_p,
                                    _c.POINTER(_c.c_float)]),
+    "shtn_fp64_probe_tflops": (_c.c_double, [_vp]),
     "shtn_profile_enable": (_c.c_int, [_c.c_int]),
     "shtn_profile_read": (_c.c_int, [_c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_long)]),
     "shtn_profile_reset": (None, []),
@@ -192,6 +193,13 @@ def shtn_plan_table(h, which):
     if n:
         lib.shtn_plan_table(h, which, out.ctypes.data, n)
     return out
+
+
+def shtn_fp64_probe_tflops(stream):
+    v = load_library().shtn_fp64_probe_tflops(stream)
+    if v < 0:
+        raise RuntimeError("shtn_fp64_probe_tflops: HIP error")
+    return v
 
 
 def shtn_plan_set_polar(h, log2_threshold):
