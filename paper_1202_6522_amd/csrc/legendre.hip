@@ -54,8 +54,6 @@ __device__ __forceinline__ long field_f_off(const LegArgs& a, int f, long fsize)
     return a.f_off ? ((clp)a.f_off)[f] : (long)f * 2 * fsize;
 }
 
-__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
-
 // Complex offset of F_m(theta_i) in a field's longitude coefficients (tiles
 // of kFTile latitudes, see f_layout).
 __device__ __forceinline__ long f_index(long ts, int m, int i)
@@ -98,12 +96,8 @@ struct D4 {
 struct D8 {
     double v[8];
 };
-struct D16 {
-    double v[16];
-};
 typedef const __attribute__((address_space(4))) D4* cd4p;
 typedef const __attribute__((address_space(4))) D8* cd8p;
-typedef const __attribute__((address_space(4))) D16* cd16p;
 
 // ---------------------------------------------------------------------------
 // Lane starts (shared by both directions).
