@@ -370,6 +370,13 @@ def main():
         "round_trip_rel_err": err,
         "legendre_tflops": {k: round(flops / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
                             for k in ("legendre_synth", "legendre_analys")},
+        # the paper's efficiency measure: (N+1)^3 / (2 T) elements per second,
+        # T the mean of the two transform times
+        "paper_efficiency_elements_per_s": round((L + 1) ** 3 / (2 * (0.5 * ms_step * 1e-3)), 1),
+        # algorithmic bytes of the longitude stage (F and the grid, read and
+        # written once) over the kernel time, against 8 TB/s
+        "fft_tb_per_s": {k: round((nlat * (M + 1) * 16 + nlat * nphi * 8) / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
+                         for k in ("c2r", "r2c")},
     }
     out["batch"] = batch_measure(dev, max(10, args.steps // 4))
     out["small_configs"] = small_configs(dev, max(20, args.steps))
