@@ -246,8 +246,11 @@ int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacke
  * milliseconds and the number of launches since the last reset.  Kinds:
  * 0 spectrum rescale, 1 Legendre synthesis, 2 Legendre analysis,
  * 3 Fourier synthesis (c2r), 4 Fourier analysis (r2c).  Not for use under
- * stream capture. */
+ * stream capture.  shtn_profile_select restricts the timing to the kinds
+ * whose bit is set in kind_mask (all kinds by default): every event pair
+ * costs a few microseconds of GPU time between kernels. */
 int shtn_profile_enable(int on);
+int shtn_profile_select(unsigned kind_mask);
 int shtn_profile_read(int kind, double* total_ms, long* launches);
 void shtn_profile_reset(void);
 

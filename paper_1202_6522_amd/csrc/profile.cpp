@@ -15,6 +15,7 @@ struct Pending {
 };
 std::mutex g_mu;
 bool g_on = false;
+unsigned g_mask = ~0u;  // kinds that are timed while enabled
 std::vector<Pending> g_pending;
 double g_ms[kProfKinds] = {0};
 thread_local bool t_capturing = false;
@@ -41,7 +42,7 @@ ProfScope::ProfScope(int kind, void* stream) : kind_(kind), stream_(stream)
 {
     if (t_capturing) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on) return;
+    if (!g_on || !((g_mask >> kind) & 1u)) return;
     hipEvent_t a;
     if (hipEventCreate(&a) != hipSuccess) return;
     if (hipEventRecord(a, (hipStream_t)stream) != hipSuccess) {
@@ -73,6 +74,13 @@ int shtn_profile_enable(int on)
 {
     std::lock_guard<std::mutex> lk(shtn::g_mu);
     shtn::g_on = on != 0;
+    return SHTN_OK;
+}
+
+int shtn_profile_select(unsigned kind_mask)
+{
+    std::lock_guard<std::mutex> lk(shtn::g_mu);
+    shtn::g_mask = kind_mask;
     return SHTN_OK;
 }
 

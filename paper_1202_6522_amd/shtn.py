@@ -65,6 +65,7 @@ _SIGS = {
                                    _c.POINTER(_c.c_float)]),
     "shtn_fp64_probe_tflops": (_c.c_double, [_vp]),
     "shtn_profile_enable": (_c.c_int, [_c.c_int]),
+    "shtn_profile_select": (_c.c_int, [_c.c_uint]),
     "shtn_profile_read": (_c.c_int, [_c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_long)]),
     "shtn_profile_reset": (None, []),
     "shtn_strerror": (_c.c_char_p, [_c.c_int]),
@@ -291,6 +292,14 @@ def shtn_profile_read(kind):
     n = _c.c_long()
     check(load_library().shtn_profile_read(kind, _c.byref(ms), _c.byref(n)), "shtn_profile_read")
     return ms.value, n.value
+
+
+def shtn_profile_select(kinds):
+    """Time only these kernel kinds (keys of PROFILE_KINDS) while enabled."""
+    mask = 0
+    for k in kinds:
+        mask |= 1 << int(k)
+    return check(load_library().shtn_profile_select(mask), "shtn_profile_select")
 
 
 def shtn_profile_reset():
