@@ -140,8 +140,9 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);
  * pairs per analysis lane and analys_waves (1, 2, 4) waves per analysis unit,
  * which together must cover every latitude pair (64 analys_lp analys_waves >=
  * ceil(nlat/2); built combinations: waves 1 with lp 1-8, 2 with lp 2-8, 4
- * with lp 4 or 8); fields per wave fw (1, 2; fw = 2 needs synth_lp <= 4,
- * analys_lp <= 4 and analys_waves <= 2); m_pairing (synthesis: 0 one
+ * with lp 4 or 8); fields per synthesis wave fw (1, 2, 4; fw = 4 needs
+ * synth_lp <= 2); the analysis takes min(fw, 2) fields per wave when
+ * analys_lp <= 4 and analys_waves <= 2, else 1; m_pairing (synthesis: 0 one
  * workgroup per order, 1 orders m and mmax-m share a workgroup so that all
  * workgroups carry equal work); split (analysis n-range piece length, a
  * multiple of 32; 0 = automatic); fft_rows (latitude rows per FFT workgroup,
@@ -212,7 +213,9 @@ int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpack
 int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpacked, void* work,
                       void* stream);
 /* Tiling of the whole batch: synth_lp (1, 2, 4) latitude pairs per synthesis
- * lane; fw (1, 2) fields of the same plan per wave; m_pairing (0, 1):
+ * lane; fw (1, 2, 4; 4 needs synth_lp <= 2) fields of the same plan per
+ * synthesis wave (the analysis of a latitude-pair class takes min(fw, 2) or
+ * 1, as for shtn_plan_set_tiling); m_pairing (0, 1):
  * synthesis units in longest-first order, or long and short units
  * alternating; analys_merge (0, 1): 0 launches the Legendre analysis once per
  * latitude-pair class (64, 128, 256, 512 pairs), 1 launches it once with the
@@ -229,7 +232,7 @@ int shtn_batch_capture(shtn_batch_t batch, int which, const double* in, double* 
 int shtn_batch_replay(shtn_batch_t batch, int which, void* stream);
 /* Autotuner: times a synthesis (Qpacked -> gridpacked) plus analysis
  * (gridpacked -> Qout) round trip of graph replays for every tiling
- * (synth_lp 1|2, fw 1|2, m_pairing 0|1, analys_merge 0|1; reps replays each,
+ * (synth_lp 1|2, fw 1|2|4, m_pairing 0|1, analys_merge 0|1; reps replays each,
  * default 10 when reps < 1), keeps the fastest, re-uploads and leaves both
  * graphs captured for these buffers.  Blocks until done.  With cache_path
  * (may be NULL), a tiling stored there for the same list of field shapes is

@@ -144,14 +144,14 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     l.plans = dplan(p);
     l.units = dev_table_int(p, TB_ANALYS_UNITS);
     l.nunits = (int)(p.analys_units.size() / kUnitInts);
-    l.grid_y = (nfields + p.tiling.fw - 1) / p.tiling.fw;
+    l.lp = p.tiling.analys_lp;
+    l.waves = p.tiling.analys_waves;
+    l.fw = analys_fw(p.tiling.fw, l.lp, l.waves);
+    l.grid_y = (nfields + l.fw - 1) / l.fw;
     l.in = F;
     l.out = Q;
     l.nfields = nfields;
     l.adjoint = adjoint;
-    l.lp = p.tiling.analys_lp;
-    l.waves = p.tiling.analys_waves;
-    l.fw = p.tiling.fw;
     {
         ProfScope ps(PK_LEG_ANALYS, stream);
         e = launch_legendre_analys(l, stream);
@@ -362,13 +362,12 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
     if (synth_lp > 4) return fail(SHTN_EINVAL, "synth_lp must be 1, 2 or 4");
     if (!(analys_waves == 1 || analys_waves == 2 || analys_waves == 4))
         return fail(SHTN_EINVAL, "analys_waves must be 1, 2 or 4");
-    // analysis kernels built: waves 1 (lp 1-8), 2 (lp 2-8), 4 (lp 4, 8); fw 2 with lp <= 4
+    // analysis kernels built: waves 1 (lp 1-8), 2 (lp 2-8), 4 (lp 4, 8); the
+    // analysis takes analys_fw(fw, lp, waves) fields per wave
     if ((analys_waves == 2 && analys_lp < 2) || (analys_waves == 4 && analys_lp < 4))
         return fail(SHTN_EINVAL, "analys_lp too small for analys_waves");
-    if (!(fw == 1 || fw == 2)) return fail(SHTN_EINVAL, "fw must be 1 or 2");
-    if (fw == 2 && synth_lp > 4) return fail(SHTN_EINVAL, "fw=2 needs synth_lp <= 4");
-    if (fw == 2 && (analys_lp > 4 || analys_waves > 2))
-        return fail(SHTN_EINVAL, "fw=2 needs analys_lp <= 4 and analys_waves <= 2");
+    if (!(fw == 1 || fw == 2 || fw == 4)) return fail(SHTN_EINVAL, "fw must be 1, 2 or 4");
+    if (fw == 4 && synth_lp > 2) return fail(SHTN_EINVAL, "fw=4 needs synth_lp <= 2");
     if (64 * analys_lp * analys_waves < p.npair && p.npair <= kMaxAnalysPairs)
         return fail(SHTN_EINVAL, "analysis unit too small: 64 analys_lp analys_waves must cover all latitude pairs");
     if (m_pairing < 0 || m_pairing > 1) return fail(SHTN_EINVAL, "m_pairing must be 0 or 1");

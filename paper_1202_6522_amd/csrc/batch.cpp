@@ -176,8 +176,7 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
     b.classes.clear();
     for (int cl : classes) {
         const int lp = cl / 16, waves = cl % 16;
-        // two-field kernels exist for lp <= 4 and waves <= 2
-        const int fw = (lp >= 8 || waves > 2) ? 1 : t.fw;
+        const int fw = analys_fw(t.fw, lp, waves);
         std::vector<SU> au;
         for (size_t pi = 0; pi < b.plans.size(); pi++) {
             const Plan& p = *b.plans[pi];
@@ -451,7 +450,8 @@ int validate(const BatchTiling& t)
 {
     if (t.synth_lp != 1 && t.synth_lp != 2 && t.synth_lp != 4)
         return set_error(SHTN_EINVAL, "synth_lp must be 1, 2 or 4");
-    if (t.fw != 1 && t.fw != 2) return set_error(SHTN_EINVAL, "fw must be 1 or 2");
+    if (t.fw != 1 && t.fw != 2 && t.fw != 4) return set_error(SHTN_EINVAL, "fw must be 1, 2 or 4");
+    if (t.fw == 4 && t.synth_lp > 2) return set_error(SHTN_EINVAL, "fw=4 needs synth_lp <= 2");
     if (t.m_pairing != 0 && t.m_pairing != 1) return set_error(SHTN_EINVAL, "m_pairing must be 0 or 1");
     if (t.analys_merge != 0 && t.analys_merge != 1)
         return set_error(SHTN_EINVAL, "analys_merge must be 0 or 1");
@@ -651,7 +651,7 @@ int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacke
             return hip_error((int)hipGetLastError(), "tuner events");
         std::vector<BatchTiling> cands;
         for (int lp : {1, 2})
-            for (int fw : {1, 2})
+            for (int fw : {1, 2, 4})
                 for (int mp : {0, 1})
                     for (int merge : {0, 1}) cands.push_back(BatchTiling{lp, fw, mp, merge});
         for (const BatchTiling& t : cands) {

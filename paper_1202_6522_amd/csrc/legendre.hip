@@ -90,14 +90,10 @@ k_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int
 constexpr int kPrefetchSlots = 2;
 
 // Blocks of scalar operands.
-struct D4 {
-    double v[4];
+template <int N>
+struct DN {
+    double v[N];
 };
-struct D8 {
-    double v[8];
-};
-typedef const __attribute__((address_space(4))) D4* cd4p;
-typedef const __attribute__((address_space(4))) D8* cd8p;
 
 // ---------------------------------------------------------------------------
 // Lane starts (shared by both directions).
@@ -175,29 +171,41 @@ struct SynthState {
     double er[LP][FW], ei[LP][FW], orr[LP][FW], oi[LP][FW];
 };
 
-// beta and the rescaled spectrum (re, im per field) for four degrees
+// Degrees per block of scalar operands: four, two with four fields, so that
+// a block (beta and the spectra of all fields) fits the scalar registers.
+// Blocks start at even offsets and hold an even number of steps, so a step's
+// parity within its block is the parity of its degree offset.
+template <int FW>
+constexpr int block_steps() { return FW >= 4 ? 2 : 4; }
+
+// beta and the rescaled spectrum (re, im per field) for NS = block_steps degrees
 template <int FW>
 struct SBlock {
-    D4 b;
-    D8 q[FW];
+    static constexpr int NS = block_steps<FW>();
+    static_assert(NS % 2 == 0, "blocks keep the step parity");
+    DN<NS> b;
+    DN<2 * NS> q[FW];
 };
 
 template <int FW>
 __device__ __forceinline__ void load_block(SBlock<FW>& B, cdp bet, const cdp (&qs)[FW], int j)
 {
-    cd4p pb = (cd4p)(bet + j);
+    constexpr int NS = SBlock<FW>::NS;
+    typedef const __attribute__((address_space(4))) DN<NS>* cbp;
+    typedef const __attribute__((address_space(4))) DN<2 * NS>* cqp;
+    cbp pb = (cbp)(bet + j);
 #pragma unroll
-    for (int i = 0; i < 4; i++) B.b.v[i] = pb->v[i];
+    for (int i = 0; i < NS; i++) B.b.v[i] = pb->v[i];
 #pragma unroll
     for (int f = 0; f < FW; f++) {
-        cd8p pq = (cd8p)(qs[f] + 2 * j);
+        cqp pq = (cqp)(qs[f] + 2 * j);
 #pragma unroll
-        for (int i = 0; i < 8; i++) B.q[f].v[i] = pq->v[i];
+        for (int i = 0; i < 2 * NS; i++) B.q[f].v[i] = pq->v[i];
     }
 }
 
-// Step t of a block (degree offset j + t).  Even t advance ua and feed the
-// even (E) sums, odd t advance ub and feed the odd (O) sums.
+// Step t of a block (degree offset j + t, j even).  Even t advance ua and
+// feed the even (E) sums, odd t advance ub and feed the odd (O) sums.
 template <int LP, int FW>
 __device__ __forceinline__ void synth_step(SynthState<LP, FW>& s, const SBlock<FW>& B, int t)
 {
@@ -227,28 +235,42 @@ __device__ __forceinline__ void synth_step(SynthState<LP, FW>& s, const SBlock<F
     }
 }
 
-// Four steps; `lim` = number of valid steps (4 for a full block).
+// The steps of one block; `lim` = number of valid steps.
 template <int LP, int FW>
-__device__ __forceinline__ void synth_block4(SynthState<LP, FW>& s, const SBlock<FW>& B, int lim)
+__device__ __forceinline__ void synth_block(SynthState<LP, FW>& s, const SBlock<FW>& B, int lim)
 {
 #pragma unroll
-    for (int t = 0; t < 4; t++)
+    for (int t = 0; t < SBlock<FW>::NS; t++)
         if (t < lim) synth_step(s, B, t);
 }
 
-// Eight steps from j (bounded by nj).
+// Eight steps from j (bounded by nj; the operand tables are padded, so the
+// loads stay in bounds past nj).  One field: both 4-step blocks are loaded
+// before either is used; with several fields two blocks would not fit the
+// scalar registers, so each block is loaded where it is used.
 template <int LP, int FW>
 __device__ __forceinline__ void synth_block8(SynthState<LP, FW>& s, cdp bet, const cdp (&qs)[FW], int j, int nj)
 {
-    SBlock<FW> b0, b1;
-    load_block(b0, bet, qs, j);
-    load_block(b1, bet, qs, j + 4);
-    if (j + 8 <= nj) {
-        synth_block4(s, b0, 4);
-        synth_block4(s, b1, 4);
-    } else {
-        synth_block4(s, b0, nj - j);
-        if (j + 4 < nj) synth_block4(s, b1, nj - j - 4);
+    constexpr int NS = SBlock<FW>::NS;
+    if (FW == 1) {
+        SBlock<FW> b0, b1;
+        load_block(b0, bet, qs, j);
+        load_block(b1, bet, qs, j + NS);
+        if (j + 2 * NS <= nj) {
+            synth_block(s, b0, NS);
+            synth_block(s, b1, NS);
+        } else {
+            synth_block(s, b0, nj - j);
+            if (j + NS < nj) synth_block(s, b1, nj - j - NS);
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k += NS) {
+        if (j + k >= nj) break;
+        SBlock<FW> b0;
+        load_block(b0, bet, qs, j + k);
+        synth_block(s, b0, nj - j - k);
     }
 }
 
@@ -373,22 +395,30 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
         synth_block8(s, bet, qs, j, nj);
         j += 8;
     }
-    // Every lane has started: whole segments, straight-line, the scalar
-    // operands of each 4-step block loaded one block ahead.
+    // Every lane has started: whole segments, straight-line.  One field: the
+    // scalar operands of each 4-step block are loaded one block ahead; with
+    // several fields each block is loaded where it is used.
     SBlock<FW> cur;
-    load_block(cur, bet, qs, j);
+    if (FW == 1) load_block(cur, bet, qs, j);
     int shn = j < nj ? segexp[j / kSegLen] : 0;
     for (int js = j; js < nj; js += kSegLen) {
         const int je = min(js + kSegLen, nj);
         rescale(s.ua, s.ub, shn);
         shn = js + kSegLen < nj ? segexp[js / kSegLen + 1] : 0;
         if (je - js == kSegLen) {
+            constexpr int NS = SBlock<FW>::NS;
 #pragma unroll
-            for (int bk = 0; bk < kSegLen; bk += 4) {
-                SBlock<FW> nxt;
-                load_block(nxt, bet, qs, js + bk + 4);
-                synth_block4(s, cur, 4);
-                cur = nxt;
+            for (int bk = 0; bk < kSegLen; bk += NS) {
+                if (FW == 1) {
+                    SBlock<FW> nxt;
+                    load_block(nxt, bet, qs, js + bk + NS);
+                    synth_block(s, cur, NS);
+                    cur = nxt;
+                } else {
+                    SBlock<FW> b0;
+                    load_block(b0, bet, qs, js + bk);
+                    synth_block(s, b0, NS);
+                }
             }
         } else {
             // last, partial segment of the order
@@ -766,6 +796,7 @@ int launch_legendre_synth(const LegLaunch& l, void* stream)
     if (l.lp == LPV && l.fw == FWV) return launch_synth_t<LPV, FWV>(l, stream);
     SHTN_S(1, 1) SHTN_S(2, 1) SHTN_S(4, 1)
     SHTN_S(1, 2) SHTN_S(2, 2) SHTN_S(4, 2)
+    SHTN_S(1, 4) SHTN_S(2, 4)
 #undef SHTN_S
     return (int)hipErrorInvalidValue;
 }

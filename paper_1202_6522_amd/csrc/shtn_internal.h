@@ -197,6 +197,15 @@ struct WorkLayout {
 };
 WorkLayout work_layout(const Plan& p, int nfields);
 
+// Fields per wave of the analysis kernel for a (pairs per lane, waves) class:
+// the largest count <= fw among the built kernels (two fields with lp <= 4
+// and waves <= 2, else one).  Four-field analysis passes were slower than
+// two-field ones in every class that can hold them.
+inline int analys_fw(int fw, int lp, int waves)
+{
+    return fw >= 2 && lp <= 4 && waves <= 2 ? 2 : 1;
+}
+
 // Kernel launchers (legendre.hip, fft.hip).  Return a hipError_t as int.
 struct LegLaunch {
     const DevPlan* plans;  // device array of plans

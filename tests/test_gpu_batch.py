@@ -62,6 +62,8 @@ TILINGS = [
     dict(synth_lp=2, fw=2, m_pairing=1, analys_merge=0),
     dict(synth_lp=1, fw=2, m_pairing=0, analys_merge=1),
     dict(synth_lp=4, fw=1, m_pairing=1, analys_merge=1),
+    dict(synth_lp=2, fw=4, m_pairing=0, analys_merge=0),
+    dict(synth_lp=1, fw=4, m_pairing=1, analys_merge=1),
 ]
 
 
@@ -128,7 +130,7 @@ def test_tuner_picks_a_tiling_and_caches_it(mixed, tmp_path):
     best = b.tune(Qin, g, a, reps=3, cache_path=cache)
     assert best > 0
     t = b.tiling()
-    assert t["synth_lp"] in (1, 2) and t["fw"] in (1, 2)
+    assert t["synth_lp"] in (1, 2) and t["fw"] in (1, 2, 4)
     # the graphs are left captured for these buffers
     g.zero_()
     b.replay(0)

@@ -137,6 +137,10 @@ def test_edge_shapes_all_transforms(shape, dev):
     # FFT workgroups of one row (one wave) and of three rows (a ragged last block)
     dict(synth_lp=1, analys_lp=4, fw=1, m_pairing=0, fft_rows=1),
     dict(synth_lp=1, analys_lp=4, fw=2, m_pairing=0, fft_rows=3),
+    dict(synth_lp=1, analys_lp=2, analys_waves=2, fw=4, m_pairing=0),
+    dict(synth_lp=2, analys_lp=2, fw=4, m_pairing=1, split=64),
+    dict(synth_lp=2, analys_lp=2, fw=4, m_pairing=0, fft_rows=1),
+    dict(synth_lp=1, analys_lp=8, fw=4, m_pairing=1),
 ])
 def test_tilings_agree(tiling, dev):
     L, M, nlat, nphi = 255, 255, 256, 512

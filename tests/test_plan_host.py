@@ -59,6 +59,10 @@ def test_calls_before_upload_and_null_pointers(lib):
         assert lib.shtn_plan_set_tiling(h, 1, 1, 3, 1, 0, 0, 0) == S.SHTN_EINVAL
         assert lib.shtn_plan_set_tiling(h, 1, 1, 2, 1, 0, 0, 0) == S.SHTN_EINVAL  # lp 1 x 2 waves: not built
         assert lib.shtn_plan_set_tiling(h, 1, 2, 2, 1, 0, 0, 0) == S.SHTN_OK
+        assert lib.shtn_plan_set_tiling(h, 1, 1, 1, 3, 0, 0, 0) == S.SHTN_EINVAL  # fw 3
+        assert lib.shtn_plan_set_tiling(h, 4, 1, 1, 4, 0, 0, 0) == S.SHTN_EINVAL  # fw 4 needs synth_lp <= 2
+        # fw 4: the analysis takes fewer fields per wave (two, or one for analys_lp 8)
+        assert lib.shtn_plan_set_tiling(h, 2, 8, 1, 4, 0, 0, 0) == S.SHTN_OK
         assert S.shtn_strerror(S.SHTN_EUNSUPPORTED) == "unsupported configuration"
     finally:
         S.shtn_plan_destroy(h)
@@ -493,8 +497,10 @@ def test_batch_layout_and_state_errors(lib):
             assert lib.shtn_batch_capture(b, 0, fake, ctypes.c_void_p(8192), fake) == S.SHTN_ESTATE
             assert lib.shtn_batch_replay(b, 0, None) == S.SHTN_ESTATE
             assert lib.shtn_batch_upload(b, ctypes.c_void_p(4097), None) == S.SHTN_EINVAL
-            for bad in [(3, 1, 0, 0), (1, 3, 0, 0), (1, 1, 2, 0), (1, 1, 0, 2)]:
+            for bad in [(3, 1, 0, 0), (1, 3, 0, 0), (1, 1, 2, 0), (1, 1, 0, 2), (4, 4, 0, 0)]:
                 assert lib.shtn_batch_set_tiling(b, *bad) == S.SHTN_EINVAL
+            S.shtn_batch_set_tiling(b, 2, 4, 0, 0)
+            assert S.shtn_batch_get_tiling(b) == [2, 4, 0, 0]
             S.shtn_batch_set_tiling(b, 2, 2, 1, 1)
             assert S.shtn_batch_get_tiling(b) == [2, 2, 1, 1]
         finally:
