@@ -165,6 +165,54 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
  * not uploaded until then, calls return SHTN_ESTATE). */
 int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
 
+/* ---- stored-P Legendre stage (Sec. 3.1, precomputed P_n^m) ----
+ *
+ * The second algorithm of the paper: P_n^m(x_i) stored for every order,
+ * degree and northern latitude pair, read instead of recomputed.  With
+ * several fields of one shape the Legendre stage is then a dense contraction
+ * per order (pairs x degrees by degrees x (field, re/im)), run here on the
+ * FP64 matrix cores; it trades the recurrence for reading the table
+ * (8 ceil(nlat/2) nlm bytes plus padding: 0.29 GB at lmax 511, 2.2 GB at
+ * lmax 1023), so it pays off with many fields per call.  Results agree with
+ * the on-the-fly kernels to rounding: the table holds the same recurrence
+ * values, and 0 where the polar threshold drops a term. */
+#define SHTN_ALGO_ONTHEFLY 0
+#define SHTN_ALGO_STORED 1
+/* Bytes of device memory the plan's table needs; negative on error. */
+long shtn_ptable_bytes(shtn_plan_t plan);
+/* Builds the table into dev_buf (device memory owned by the caller, 256-byte
+ * aligned, at least shtn_ptable_bytes; it must stay allocated while the plan
+ * uses it) from the uploaded plan, on `stream`, and waits for it.  The plan
+ * records the buffer.  SHTN_ESTATE if the plan is not uploaded, SHTN_EINVAL
+ * for a null, misaligned or short buffer.  A later shtn_plan_set_polar makes
+ * the table stale: build it again. */
+int shtn_ptable_build(shtn_plan_t plan, void* dev_buf, size_t bytes, void* stream);
+/* Forgets the table (the caller may then free it) and selects the on-the-fly
+ * algorithm. */
+int shtn_ptable_release(shtn_plan_t plan);
+/* Work decomposition of the stored-P kernels (one wave each): synthesis
+ * synth_rt (1, 2, 4) tiles of 16 latitude pairs x synth_ct (1, 2) tiles of 8
+ * fields; analysis analys_jt (1, 2, 4) tiles of 16 degrees of each parity x
+ * analys_ct (1, 2) tiles of 8 fields.  Default 4, 2, 2, 2.  SHTN_EINVAL for
+ * other values.  Takes effect at the next call. */
+int shtn_ptable_set_tiling(shtn_plan_t plan, int synth_rt, int synth_ct, int analys_jt, int analys_ct);
+/* tiling4 = {synth_rt, synth_ct, analys_jt, analys_ct}. */
+int shtn_ptable_get_tiling(shtn_plan_t plan, int* tiling4);
+/* Selects the Legendre algorithm of the four transforms: SHTN_ALGO_ONTHEFLY
+ * (default) or SHTN_ALGO_STORED (needs a current table, else SHTN_ESTATE).
+ * The FFT stages are the same for both. */
+int shtn_plan_set_algorithm(shtn_plan_t plan, int algo);
+/* The selected algorithm, or a negative error code. */
+int shtn_plan_get_algorithm(shtn_plan_t plan);
+/* Runtime tuning (Sec. 3.2): times `reps` synthesis (Q -> grid) plus analysis
+ * (grid -> Qout) round trips of nfields fields with each algorithm (the
+ * stored one only if the table is current), selects the faster and returns
+ * the two mean round-trip times in microseconds (us_stored = -1 when not
+ * timed; either pointer may be NULL).  Q, grid and Qout are device buffers
+ * of nfields fields; Qout must not alias Q.  Blocks until done. */
+int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, double* Qout, int nfields,
+                             void* work, void* stream, int reps, float* us_onthefly, float* us_stored);
+
 /* Measures the FP64 vector FMA rate (TFLOP/s, 2 flops per FMA) that the
  * current device sustains with four waves per SIMD on independent chains
  * with a scalar operand, the form of the Legendre kernels' inner loops: a

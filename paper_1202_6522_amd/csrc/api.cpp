@@ -61,6 +61,15 @@ int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, c
     return SHTN_OK;
 }
 
+// Stored-P kernel arguments; ESTATE when the plan has no current table.
+int sp_args(const Plan& p, const double* in, double* out, int nfields, int adjoint, PtabArgs& a)
+{
+    if (!p.ptab.built) return fail(SHTN_ESTATE, "stored-P table not built for the current plan (shtn_ptable_build)");
+    a = PtabArgs{dplan(p), (const long*)p.ptab.dev, (const double*)((char*)p.ptab.dev + p.ptab.head_bytes),
+                 in, out, nfields, adjoint, p.ptab.npt, 0};
+    return SHTN_OK;
+}
+
 // Legendre synthesis-type pass (synthesis or adjoint of the analysis) then c2r.
 int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream,
             int adjoint)
@@ -72,6 +81,15 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     double* F = (double*)work;
     double* Qs = (double*)((char*)work + wl.f_bytes);
     int e;
+    if (p.algo == 1) {
+        PtabArgs a;
+        if ((rc = sp_args(p, Q, F, nfields, adjoint, a))) return rc;
+        {
+            ProfScope ps(PK_LEG_SYNTH, stream);
+            e = launch_sp_synth(a, p.M, p.ptab.synth_rt, p.ptab.synth_ct, stream);
+        }
+        if (e) return hip_fail(e, "stored-P synthesis launch");
+    } else {
     {
         ProfScope ps(PK_PRESCALE, stream);
         e = launch_prescale(dplan(p), nullptr, nullptr, nullptr, Q, Qs, p.nlm, nfields, stream);
@@ -94,6 +112,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
         e = launch_legendre_synth(l, stream);
     }
     if (e) return hip_fail(e, "legendre synthesis launch");
+    }
     FftLaunch f{};
     f.plans = dplan(p);
     f.rows_per_block = rows_per_block(p);
@@ -120,8 +139,10 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     int rc = check_call(plan, grid, Q, nfields, work);
     if (rc) return rc;
     const Plan& p = *plan->p;
-    if (p.npair > kMaxAnalysPairs)
-        return fail(SHTN_EUNSUPPORTED, "analysis supports at most 4096 latitudes");
+    if (p.algo == 0 && p.npair > kMaxAnalysPairs)
+        return fail(SHTN_EUNSUPPORTED, "on-the-fly analysis supports at most 4096 latitudes");
+    if (p.algo == 1 && !p.ptab.built)
+        return fail(SHTN_ESTATE, "stored-P table not built for the current plan (shtn_ptable_build)");
     double* F = (double*)work;
     FftLaunch f{};
     f.plans = dplan(p);
@@ -140,6 +161,17 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
         e = launch_r2c(f, stream);
     }
     if (e) return hip_fail(e, "r2c launch");
+    if (p.algo == 1) {
+        PtabArgs a;
+        if ((rc = sp_args(p, F, Q, nfields, adjoint, a))) return rc;
+        const int nbr_max = ((p.L + 2) / 2 + 15) / 16;  // block rows of order 0, even parity
+        {
+            ProfScope ps(PK_LEG_ANALYS, stream);
+            e = launch_sp_analys(a, p.M, nbr_max, p.ptab.analys_jt, p.ptab.analys_ct, stream);
+        }
+        if (e) return hip_fail(e, "stored-P analysis launch");
+        return SHTN_OK;
+    }
     LegLaunch l{};
     l.plans = dplan(p);
     l.units = dev_table_int(p, TB_ANALYS_UNITS);
@@ -421,8 +453,138 @@ int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold)
     build_image(p);
     p.uploaded = false;
     p.dev = nullptr;
+    p.ptab.built = false;  // the table follows the lane starts
     return SHTN_OK;
 }
+
+long shtn_ptable_bytes(shtn_plan_t plan)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    const PTable& t = plan->p->ptab;
+    return (long)(t.head_bytes + (size_t)t.nblocks * 256 * sizeof(double));
+}
+
+int shtn_ptable_build(shtn_plan_t plan, void* dev_buf, size_t bytes, void* stream)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    Plan& p = *plan->p;
+    if (!p.uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
+    if (!dev_buf) return fail(SHTN_EINVAL, "null device buffer");
+    if ((uintptr_t)dev_buf % 256) return fail(SHTN_EINVAL, "device buffer must be 256-byte aligned");
+    const size_t need = p.ptab.head_bytes + (size_t)p.ptab.nblocks * 256 * sizeof(double);
+    if (bytes < need) return fail(SHTN_EINVAL, "stored-P buffer smaller than shtn_ptable_bytes");
+    p.ptab.built = false;
+    hipError_t e = hipMemcpyAsync(dev_buf, p.ptab.boff.data(), p.ptab.boff.size() * sizeof(long),
+                                  hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail((int)e, "stored-P offsets copy");
+    const int k = launch_ptable_build(dplan(p), (const long*)dev_buf,
+                                      (double*)((char*)dev_buf + p.ptab.head_bytes), p.ptab.npt, p.M, stream);
+    if (k) return hip_fail(k, "stored-P build launch");
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail((int)e, "stored-P build sync");
+    p.ptab.dev = dev_buf;
+    p.ptab.built = true;
+    return SHTN_OK;
+}
+
+int shtn_ptable_release(shtn_plan_t plan)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    plan->p->ptab.dev = nullptr;
+    plan->p->ptab.built = false;
+    plan->p->algo = SHTN_ALGO_ONTHEFLY;
+    return SHTN_OK;
+}
+
+int shtn_ptable_set_tiling(shtn_plan_t plan, int synth_rt, int synth_ct, int analys_jt, int analys_ct)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    auto ok_t = [](int v) { return v == 1 || v == 2 || v == 4; };
+    auto ok_c = [](int v) { return v == 1 || v == 2; };
+    if (!ok_t(synth_rt) || !ok_t(analys_jt)) return fail(SHTN_EINVAL, "synth_rt and analys_jt must be 1, 2 or 4");
+    if (!ok_c(synth_ct) || !ok_c(analys_ct)) return fail(SHTN_EINVAL, "synth_ct and analys_ct must be 1 or 2");
+    PTable& t = plan->p->ptab;
+    t.synth_rt = synth_rt;
+    t.synth_ct = synth_ct;
+    t.analys_jt = analys_jt;
+    t.analys_ct = analys_ct;
+    return SHTN_OK;
+}
+
+int shtn_ptable_get_tiling(shtn_plan_t plan, int* tiling4)
+{
+    if (!plan || !plan->p || !tiling4) return fail(SHTN_EINVAL, "null plan or output");
+    const PTable& t = plan->p->ptab;
+    tiling4[0] = t.synth_rt;
+    tiling4[1] = t.synth_ct;
+    tiling4[2] = t.analys_jt;
+    tiling4[3] = t.analys_ct;
+    return SHTN_OK;
+}
+
+int shtn_plan_set_algorithm(shtn_plan_t plan, int algo)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (algo != SHTN_ALGO_ONTHEFLY && algo != SHTN_ALGO_STORED)
+        return fail(SHTN_EINVAL, "algorithm must be SHTN_ALGO_ONTHEFLY or SHTN_ALGO_STORED");
+    if (algo == SHTN_ALGO_STORED && !plan->p->ptab.built)
+        return fail(SHTN_ESTATE, "stored-P table not built for the current plan (shtn_ptable_build)");
+    plan->p->algo = algo;
+    return SHTN_OK;
+}
+
+int shtn_plan_get_algorithm(shtn_plan_t plan)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    return plan->p->algo;
+}
+
+int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, double* Qout, int nfields,
+                             void* work, void* stream, int reps, float* us_onthefly, float* us_stored)
+{
+    int rc = check_call(plan, Q, grid, nfields, work);
+    if (rc) return rc;
+    if (!Qout || Qout == Q || (const void*)Qout == (const void*)grid)
+        return fail(SHTN_EINVAL, "Qout must be a separate buffer");
+    if (reps < 1) reps = 5;
+    Plan& p = *plan->p;
+    const int keep = p.algo;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail((int)hipGetLastError(), "tuner events");
+    }
+    float t[2] = {-1.f, -1.f};
+    for (int algo = 0; algo < 2 && !rc; algo++) {
+        if (algo == SHTN_ALGO_STORED && !p.ptab.built) break;
+        p.algo = algo;
+        // one untimed round trip, then the timed ones
+        for (int r = -1; r < reps && !rc; r++) {
+            if (r == 0 && hipEventRecord(e0, (hipStream_t)stream) != hipSuccess)
+                rc = hip_fail((int)hipGetLastError(), "tuner event record");
+            if (!rc) rc = to_grid(plan, Q, grid, nfields, work, stream, 0);
+            if (!rc) rc = to_spec(plan, grid, Qout, nfields, work, stream, 0);
+        }
+        if (!rc && hipEventRecord(e1, (hipStream_t)stream) != hipSuccess)
+            rc = hip_fail((int)hipGetLastError(), "tuner event record");
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = hip_fail((int)hipGetLastError(), "tuner sync");
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = hip_fail((int)hipGetLastError(), "tuner elapsed time");
+        if (!rc) t[algo] = 1e3f * ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        p.algo = keep;
+        return rc;
+    }
+    p.algo = (t[1] >= 0.f && t[1] < t[0]) ? SHTN_ALGO_STORED : SHTN_ALGO_ONTHEFLY;
+    if (us_onthefly) *us_onthefly = t[0];
+    if (us_stored) *us_stored = t[1];
+    return SHTN_OK;
+}
+
 
 const char* shtn_strerror(int code)
 {

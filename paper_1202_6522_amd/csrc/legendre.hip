@@ -54,13 +54,6 @@ __device__ __forceinline__ long field_f_off(const LegArgs& a, int f, long fsize)
     return a.f_off ? ((clp)a.f_off)[f] : (long)f * 2 * fsize;
 }
 
-// Complex offset of F_m(theta_i) in a field's longitude coefficients (tiles
-// of kFTile latitudes, see f_layout).
-__device__ __forceinline__ long f_index(long ts, int m, int i)
-{
-    return (long)(i >> kFTileLg) * ts + m * kFTile + (i & (kFTile - 1));
-}
-
 // ---------------------------------------------------------------------------
 // Spectrum rescaling: Qs = gamma * Q (complex), per field.
 // ---------------------------------------------------------------------------

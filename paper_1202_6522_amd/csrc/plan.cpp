@@ -277,6 +277,7 @@ Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
     analys_shape(np, p->tiling.analys_lp, p->tiling.analys_waves);
     if (rebuild_units(*p, err)) { delete p; return nullptr; }
     build_image(*p);
+    ptable_layout(*p);
     return p;
 }
 
@@ -476,6 +477,27 @@ static size_t put(std::vector<unsigned char>& img, size_t off, const std::vector
     if (img.size() < off + bytes) img.resize(off + bytes);
     if (bytes) std::memcpy(img.data() + off, v.data(), bytes);
     return align256(off + bytes);
+}
+
+// Stored-P table geometry: per order m (nj = lmax - m + 1 degrees) the even
+// offsets j = n - m give ceil(nj/2) rows and the odd ones floor(nj/2); each
+// parity takes ceil(rows/16) block rows of npt blocks.
+void ptable_layout(Plan& p)
+{
+    PTable& t = p.ptab;
+    t.npt = (p.npair + 15) / 16;
+    t.boff.assign((size_t)(p.M + 1) * 2, 0);
+    long cur = 0;
+    for (int m = 0; m <= p.M; m++) {
+        const int nj = p.L - m + 1;
+        const int rows[2] = {(nj + 1) / 2, nj / 2};
+        for (int q = 0; q < 2; q++) {
+            t.boff[2 * m + q] = cur;
+            cur += (long)((rows[q] + 15) / 16) * t.npt;
+        }
+    }
+    t.nblocks = cur;
+    t.head_bytes = align256(t.boff.size() * sizeof(long));
 }
 
 void build_image(Plan& p)

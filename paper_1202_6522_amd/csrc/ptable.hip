@@ -1,0 +1,343 @@
+// Stored-P Legendre stage (Sec. 3.1, precomputed P_n^m; the runtime choice
+// between the two algorithms is the tuning of Sec. 3.2).
+//
+// The table holds P_n^m(x_i) for every order m, degree n and northern
+// latitude pair i, as doubles, split by the parity of j = n - m (the mirror
+// fold of Sec. 3.1 pairs even j with F_N + F_S and odd j with F_N - F_S).
+// Per (m, parity q) the degrees j = 2 jq + q form rows jq, the pairs form
+// columns; both are padded to multiples of 16 with zeros and cut into 16 x 16
+// blocks (2 KB), laid out block row by block row.  Inside a block, entry
+// (jl, pl) sits at
+//     (jl / 4) 64 + (pl / 4) 16 + (jl % 4) 4 + pl % 4,
+// so that the 4 degrees x 16 pairs the synthesis feeds one matrix
+// instruction, and the 16 degrees x 4 pairs the analysis feeds one, are each
+// four whole 128-byte lines.
+//
+// With several fields of the same shape the Legendre stage is then a dense
+// contraction per order: synthesis F[pair][col] = sum_j P[j][pair] Q[j][col],
+// analysis Q[j][col] = sum_pair P[j][pair] G[pair][col], where a column is
+// (field, re/im).  Both run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4_f64: D[16x16] += A[16x4] B[4x16]).  The table is built
+// on the device from the plan's own recurrence tables (lane starts, segment
+// shifts), so an entry is 0 exactly where the on-the-fly kernels drop the
+// term (the polar cut), and equals gamma_n u_n elsewhere.
+#include <hip/hip_runtime.h>
+
+#include "shtn_internal.h"
+
+namespace shtn {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// m-major index of (n = m, m): the first coefficient of order m.
+__device__ __forceinline__ long order_base(int L, int m) { return (long)m * (2 * L + 1 - m) / 2 + m; }
+
+__device__ __forceinline__ int ptab_in_block(int jl, int pl)
+{
+    return (jl >> 2) * 64 + (pl >> 2) * 16 + (jl & 3) * 4 + (pl & 3);
+}
+
+// ---------------------------------------------------------------------------
+// Builder: one thread per (order, pair column, padded to whole blocks).  The
+// recurrence is the synthesis kernel's (same steps, same segment shifts, same
+// lane starts), so a lane is 0 before its start step.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_ptable_build(const DevPlan* plan, const long* boff, double* tab, int npt)
+{
+    const DevPlan& P = *plan;
+    const int m = blockIdx.y;
+    const int pair = blockIdx.x * 64 + threadIdx.x;
+    if (pair >= npt * 16) return;
+    const int L = P.L, npair = P.npair;
+    const int nj = L - m + 1;
+    const long base = order_base(L, m);
+    const bool act = pair < npair;
+    const size_t q = (size_t)m * npair + (act ? pair : 0);
+    const int jst = act ? P.inj_j[q] : nj;
+    const double2 y = act ? *(const double2*)(P.inj_y + 2 * q) : make_double2(0.0, 0.0);
+    const double x = act ? P.xp[pair] : 0.0;
+    const int* segexp = P.segexp + P.segoff[m];
+    const int pt = pair >> 4, pl = pair & 15;
+    double* t0 = tab + boff[2 * m] * 256;
+    double* t1 = tab + boff[2 * m + 1] * 256;
+    auto at = [&](double* t, int jq) -> double& {
+        return t[((long)(jq >> 4) * npt + pt) * 256 + ptab_in_block(jq & 15, pl)];
+    };
+    double ua = 0.0, ub = 0.0;
+    for (int j = 0; j < nj; j += 2) {
+        if (j > 0 && j % kSegLen == 0) {
+            const int d = segexp[j / kSegLen];
+            ua = ldexp(ua, d);
+            ub = ldexp(ub, d);
+        }
+        if (j == jst) {  // start steps are multiples of kInject, hence even
+            ua = y.x;
+            ub = y.y;
+        }
+        ua = fma(x, ub, P.beta[base + j] * ua);
+        at(t0, j >> 1) = j >= jst ? P.gamma[base + j] * ua : 0.0;
+        if (j + 1 < nj) {
+            ub = fma(x, ua, P.beta[base + j + 1] * ub);
+            at(t1, j >> 1) = j + 1 >= jst ? P.gamma[base + j + 1] * ub : 0.0;
+        }
+    }
+    // zero rows up to the end of the last block row of each parity
+    const int c0 = (nj + 1) >> 1, c1 = nj >> 1;
+    for (int jq = c0; jq < ((c0 + 15) & ~15); jq++) at(t0, jq) = 0.0;
+    for (int jq = c1; jq < ((c1 + 15) & ~15); jq++) at(t1, jq) = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Synthesis (or the adjoint of the analysis): one wave per (order, group of
+// RT pair tiles, group of CT column tiles).  Lane l feeds A[pair l%16][degree
+// l/16] and B[degree l/16][column l%16] and holds D[pair l/16 + 4 r][column
+// l%16], r < 4.  Even and odd degrees accumulate apart; the fold north =
+// E + O, south = E - O is then lane-local.
+// ---------------------------------------------------------------------------
+template <int RT, int CT>
+__global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
+{
+    const DevPlan& P = *a.plan;
+    const int pg = blockIdx.x, m = blockIdx.y;
+    const int L = P.L, nlat = P.nlat, npair = P.npair;
+    const int npt = a.npt;
+    const int nj = L - m + 1;
+    const long base = order_base(L, m);
+    const int lane = threadIdx.x;
+    const int col = lane & 15, kk = lane >> 4;
+    const int comp = col & 1;
+
+    const double* qp[CT];
+    bool fv[CT];
+    int fld[CT];
+#pragma unroll
+    for (int c = 0; c < CT; c++) {
+        const int f = (blockIdx.z * CT + c) * 8 + (col >> 1);
+        fv[c] = f < a.nfields;
+        fld[c] = f;
+        qp[c] = a.in + (long)(fv[c] ? f : 0) * 2 * P.nlm + 2 * base + comp;
+    }
+    // pair tiles past the last one read tile pg RT (always present) and
+    // feed zeros
+    bool tv[RT];
+    int tr[RT];
+#pragma unroll
+    for (int r = 0; r < RT; r++) {
+        tv[r] = pg * RT + r < npt;
+        tr[r] = tv[r] ? r : 0;
+    }
+    const int a_off = ptab_in_block(kk, lane & 15);  // + 64 s for step s of a block
+
+    d4 acc[2][RT][CT];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int r = 0; r < RT; r++)
+#pragma unroll
+            for (int c = 0; c < CT; c++) acc[q][r][c] = d4{0.0, 0.0, 0.0, 0.0};
+
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const int cnt = q ? nj >> 1 : (nj + 1) >> 1;
+        const int nbr = (cnt + 15) >> 4;  // block rows of this parity
+        const double* tq = a.tab + a.boff[2 * m + q] * 256 + (long)pg * RT * 256 + a_off;
+        for (int br = 0; br < nbr; br++) {
+            const double* tb = tq + (long)br * npt * 256;
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                const int j = 2 * (br * 16 + s * 4 + kk) + q;
+                double bv[CT], av[RT];
+#pragma unroll
+                for (int c = 0; c < CT; c++) {
+                    const double v = qp[c][2 * min(j, nj - 1)];
+                    bv[c] = (j < nj && fv[c]) ? v : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < RT; r++) {
+                    const double v = tb[tr[r] * 256 + s * 64];
+                    av[r] = tv[r] ? v : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < RT; r++)
+#pragma unroll
+                    for (int c = 0; c < CT; c++)
+                        acc[q][r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], acc[q][r][c], 0, 0, 0);
+            }
+        }
+    }
+
+    // For the adjoint of the analysis the output carries (2 pi/nphi) w_i / c_m.
+    const double cm = a.adjoint ? (2.0 * M_PI / P.nphi) * (m == 0 ? 1.0 : 0.5) : 1.0;
+#pragma unroll
+    for (int r = 0; r < RT; r++) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int pair = (pg * RT + r) * 16 + kk + 4 * i;
+            if (pair >= npair) continue;
+            const double sc = a.adjoint ? cm * P.wfull[pair] : 1.0;
+            const int is = nlat - 1 - pair;
+#pragma unroll
+            for (int c = 0; c < CT; c++) {
+                if (!fv[c]) continue;
+                double* F = a.out + (long)fld[c] * 2 * P.f_size + comp;
+                const double e = acc[0][r][c][i], o = acc[1][r][c][i];
+                F[2 * f_index(P.f_ts, m, pair)] = sc * (e + o);
+                if (is != pair) F[2 * f_index(P.f_ts, m, is)] = sc * (e - o);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Analysis (or the adjoint of the synthesis): one wave per (order, group of
+// JT block rows of each parity, group of CT column tiles); the contraction
+// runs over all pairs, 4 per step.  Lane l feeds A[degree l%16][pair l/16]
+// and B[pair l/16][column l%16] = the folded, weighted longitude
+// coefficients, and holds D[degree l/16 + 4 r][column l%16].
+// ---------------------------------------------------------------------------
+template <int JT, int CT>
+__global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
+{
+    const DevPlan& P = *a.plan;
+    const int g = blockIdx.x, m = blockIdx.y;
+    const int L = P.L, nlat = P.nlat, npair = P.npair;
+    const int npt = a.npt;
+    const int nj = L - m + 1;
+    const int nbr0 = (((nj + 1) >> 1) + 15) >> 4, nbr1 = ((nj >> 1) + 15) >> 4;
+    if (g * JT >= nbr0) return;  // nbr0 >= nbr1
+    const long base = order_base(L, m);
+    const int lane = threadIdx.x;
+    const int col = lane & 15, kk = lane >> 4;
+    const int comp = col & 1;
+
+    const double* fp[CT];
+    bool fv[CT];
+    int fld[CT];
+#pragma unroll
+    for (int c = 0; c < CT; c++) {
+        const int f = (blockIdx.z * CT + c) * 8 + (col >> 1);
+        fv[c] = f < a.nfields;
+        fld[c] = f;
+        fp[c] = a.in + (long)(fv[c] ? f : 0) * 2 * P.f_size + comp;
+    }
+    bool rv[2][JT];
+    const double* tq[2][JT];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int t = 0; t < JT; t++) {
+            const int br = g * JT + t;
+            rv[q][t] = br < (q ? nbr1 : nbr0);
+            // a block row past the last of its parity (the odd parity of
+            // order lmax has none) reads the first even one and feeds zeros
+            const long blk = rv[q][t] ? a.boff[2 * m + q] + (long)br * npt : a.boff[2 * m];
+            tq[q][t] = a.tab + blk * 256 + ptab_in_block(lane & 15, kk);  // + 256 pt + 16 (step % 4)
+        }
+
+    d4 acc[2][JT][CT];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int t = 0; t < JT; t++)
+#pragma unroll
+            for (int c = 0; c < CT; c++) acc[q][t][c] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int pt = 0; pt < npt; pt++) {
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int pair = pt * 16 + s * 4 + kk;
+            const bool pv = pair < npair;
+            const int pc = pv ? pair : 0;
+            const bool middle = (nlat & 1) && pc == npair - 1;
+            const double wt = !pv ? 0.0 : (a.adjoint ? (middle ? 0.5 : 1.0) : P.wq[pc]);
+            double ge[CT], go[CT];
+#pragma unroll
+            for (int c = 0; c < CT; c++) {
+                const double vn = fp[c][2 * f_index(P.f_ts, m, pc)];
+                const double vs = fp[c][2 * f_index(P.f_ts, m, nlat - 1 - pc)];
+                ge[c] = wt * (vn + vs);
+                go[c] = wt * (vn - vs);
+            }
+            double av[2][JT];
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int t = 0; t < JT; t++) {
+                    const double v = tq[q][t][pt * 256 + s * 16];
+                    av[q][t] = rv[q][t] ? v : 0.0;
+                }
+#pragma unroll
+            for (int t = 0; t < JT; t++)
+#pragma unroll
+                for (int c = 0; c < CT; c++) {
+                    acc[0][t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][t], ge[c], acc[0][t][c], 0, 0, 0);
+                    acc[1][t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][t], go[c], acc[1][t][c], 0, 0, 0);
+                }
+        }
+    }
+
+    const double cm = (m == 0 || !a.adjoint) ? 1.0 : 2.0;
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int t = 0; t < JT; t++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int j = 2 * ((g * JT + t) * 16 + kk + 4 * i) + q;
+                if (j >= nj) continue;
+#pragma unroll
+                for (int c = 0; c < CT; c++) {
+                    if (!fv[c]) continue;
+                    const double v = (m == 0 && comp == 1) ? 0.0 : cm * acc[q][t][c][i];
+                    a.out[(long)fld[c] * 2 * P.nlm + 2 * (base + j) + comp] = v;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int launch_ptable_build(const DevPlan* plan, const long* boff, double* tab, int npt, int M, void* stream)
+{
+    hipLaunchKernelGGL(k_ptable_build, dim3((npt * 16 + 63) / 64, M + 1), dim3(64), 0, (hipStream_t)stream,
+                       plan, boff, tab, npt);
+    return (int)hipGetLastError();
+}
+
+template <int RT, int CT>
+static int launch_sp_synth_t(const PtabArgs& a, int M, void* stream)
+{
+    const int npg = (a.npt + RT - 1) / RT;
+    const int nfg = (a.nfields + 8 * CT - 1) / (8 * CT);
+    hipLaunchKernelGGL((k_sp_synth<RT, CT>), dim3(npg, M + 1, nfg), dim3(64), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+template <int JT, int CT>
+static int launch_sp_analys_t(const PtabArgs& a, int M, int nbr_max, void* stream)
+{
+    const int ng = (nbr_max + JT - 1) / JT;
+    const int nfg = (a.nfields + 8 * CT - 1) / (8 * CT);
+    hipLaunchKernelGGL((k_sp_analys<JT, CT>), dim3(ng, M + 1, nfg), dim3(64), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+int launch_sp_synth(const PtabArgs& a, int M, int rt, int ct, void* stream)
+{
+#define SHTN_SP(RV, CV) \
+    if (rt == RV && ct == CV) return launch_sp_synth_t<RV, CV>(a, M, stream);
+    SHTN_SP(1, 1) SHTN_SP(2, 1) SHTN_SP(4, 1) SHTN_SP(1, 2) SHTN_SP(2, 2) SHTN_SP(4, 2)
+#undef SHTN_SP
+    return (int)hipErrorInvalidValue;
+}
+
+int launch_sp_analys(const PtabArgs& a, int M, int nbr_max, int jt, int ct, void* stream)
+{
+#define SHTN_SP(JV, CV) \
+    if (jt == JV && ct == CV) return launch_sp_analys_t<JV, CV>(a, M, nbr_max, stream);
+    SHTN_SP(1, 1) SHTN_SP(2, 1) SHTN_SP(4, 1) SHTN_SP(1, 2) SHTN_SP(2, 2) SHTN_SP(4, 2)
+#undef SHTN_SP
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace shtn

@@ -126,6 +126,21 @@ struct Tiling {
     int fft_rows = 0;  // latitude rows per FFT workgroup, 0 = automatic
 };
 
+// Stored-P table of a plan (Sec. 3, precomputed P_n^m; ptable.hip): P_n^m
+// at the northern latitude pairs per (order, parity of n - m) in 16 x 16
+// blocks of (degree row, pair), rows and pairs zero-padded to 16.  The device
+// buffer holds the block offsets (boff) first, then the blocks.
+struct PTable {
+    int npt = 0;              // pair tiles of 16
+    std::vector<long> boff;   // [(M+1) * 2] first block of (order, parity)
+    long nblocks = 0;
+    size_t head_bytes = 0;    // boff, padded to 256 bytes
+    void* dev = nullptr;      // caller's buffer once built
+    bool built = false;       // matches the plan's current lane starts
+    int synth_rt = 4, synth_ct = 2;    // synthesis: pair tiles, column tiles per wave
+    int analys_jt = 2, analys_ct = 2;  // analysis: block rows per parity, column tiles per wave
+};
+
 struct Plan {
     int L = 0, M = 0, nlat = 0, nphi = 0, npair = 0, K = 0;
     long nlm = 0;
@@ -151,7 +166,10 @@ struct Plan {
     std::vector<size_t> table_off;     // byte offsets of each table inside the image
     void* dev = nullptr;               // caller's device buffer after upload
     bool uploaded = false;
+    PTable ptab;
+    int algo = 0;  // Legendre stage: 0 on-the-fly recurrence, 1 stored P
 };
+void ptable_layout(Plan& p);  // geometry of the stored-P table
 
 // Error reporting shared by the C-ABI sources (api.cpp): sets the detail
 // string of shtn_last_error_detail and returns the code.
@@ -180,6 +198,13 @@ constexpr int kFTileLg = 3;
 struct FLayout {
     long ts, size;  // tile stride and values per field (complex)
 };
+#ifdef __HIPCC__
+// Complex offset of F_m(theta_i) in a field's longitude coefficients.
+__device__ __forceinline__ long f_index(long ts, int m, int i)
+{
+    return (long)(i >> kFTileLg) * ts + m * kFTile + (i & (kFTile - 1));
+}
+#endif
 inline FLayout f_layout(int M, int nlat)
 {
     const long ts = (long)(M + 1) * kFTile;
@@ -225,6 +250,21 @@ struct LegLaunch {
 // Qs = gamma * Q per field; q_off/s_off/fplan per field (device) or null.
 int launch_prescale(const DevPlan* plans, const long* q_off, const long* s_off, const int* fplan,
                     const double* Q, double* Qs, long max_nlm, int nfields, void* stream);
+// Stored-P kernels (ptable.hip).
+struct PtabArgs {
+    const DevPlan* plan;
+    const long* boff;    // device copy of PTable::boff
+    const double* tab;   // the blocks
+    const double* in;    // synthesis: spectra (nfields x nlm complex); analysis: F
+    double* out;         // synthesis: F; analysis: spectra
+    int nfields;
+    int adjoint;
+    int npt;
+    int pad;
+};
+int launch_ptable_build(const DevPlan* plan, const long* boff, double* tab, int npt, int M, void* stream);
+int launch_sp_synth(const PtabArgs& a, int M, int rt, int ct, void* stream);
+int launch_sp_analys(const PtabArgs& a, int M, int nbr_max, int jt, int ct, void* stream);
 int launch_legendre_synth(const LegLaunch& a, void* stream);
 int launch_legendre_analys(const LegLaunch& a, void* stream);
 

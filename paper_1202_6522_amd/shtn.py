@@ -25,6 +25,8 @@ SHTN_EUNSUPPORTED = -2
 SHTN_ESTATE = -3
 SHTN_EHIP = -4
 SHTN_ENOMEM = -5
+SHTN_ALGO_ONTHEFLY = 0
+SHTN_ALGO_STORED = 1
 
 _lib = None
 
@@ -63,6 +65,15 @@ _SIGS = {
     "shtn_batch_replay": (_c.c_int, [_vp, _c.c_int, _vp]),
     "shtn_batch_tune": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c.c_int, _c.c_char_p,
                                    _c.POINTER(_c.c_float)]),
+    "shtn_ptable_bytes": (_c.c_long, [_vp]),
+    "shtn_ptable_build": (_c.c_int, [_vp, _vp, _sz, _vp]),
+    "shtn_ptable_release": (_c.c_int, [_vp]),
+    "shtn_ptable_set_tiling": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "shtn_ptable_get_tiling": (_c.c_int, [_vp, _c.POINTER(_c.c_int)]),
+    "shtn_plan_set_algorithm": (_c.c_int, [_vp, _c.c_int]),
+    "shtn_plan_get_algorithm": (_c.c_int, [_vp]),
+    "shtn_plan_tune_algorithm": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int, _vp, _vp, _c.c_int,
+                                            _c.POINTER(_c.c_float), _c.POINTER(_c.c_float)]),
     "shtn_fp64_probe_tflops": (_c.c_double, [_vp]),
     "shtn_profile_enable": (_c.c_int, [_c.c_int]),
     "shtn_profile_select": (_c.c_int, [_c.c_uint]),
@@ -203,6 +214,53 @@ def shtn_fp64_probe_tflops(stream):
     return v
 
 
+def shtn_ptable_bytes(h):
+    v = load_library().shtn_ptable_bytes(h)
+    if v < 0:
+        raise ShtnError(v, "shtn_ptable_bytes")
+    return v
+
+
+def shtn_ptable_build(h, dev_ptr, nbytes, stream):
+    return check(load_library().shtn_ptable_build(h, dev_ptr, nbytes, stream), "shtn_ptable_build")
+
+
+def shtn_ptable_release(h):
+    return check(load_library().shtn_ptable_release(h), "shtn_ptable_release")
+
+
+def shtn_ptable_set_tiling(h, synth_rt, synth_ct, analys_jt, analys_ct):
+    return check(load_library().shtn_ptable_set_tiling(h, synth_rt, synth_ct, analys_jt, analys_ct),
+                 "shtn_ptable_set_tiling")
+
+
+def shtn_ptable_get_tiling(h):
+    t = (_c.c_int * 4)()
+    check(load_library().shtn_ptable_get_tiling(h, t), "shtn_ptable_get_tiling")
+    return list(t)
+
+
+def shtn_plan_set_algorithm(h, algo):
+    return check(load_library().shtn_plan_set_algorithm(h, algo), "shtn_plan_set_algorithm")
+
+
+def shtn_plan_get_algorithm(h):
+    v = load_library().shtn_plan_get_algorithm(h)
+    if v < 0:
+        raise ShtnError(v, "shtn_plan_get_algorithm")
+    return v
+
+
+def shtn_plan_tune_algorithm(h, Q, grid, Qout, nfields, work, stream, reps=5):
+    """Returns (on-the-fly, stored) mean round-trip microseconds (stored -1 if not timed)."""
+    t0 = _c.c_float(-1.0)
+    t1 = _c.c_float(-1.0)
+    check(load_library().shtn_plan_tune_algorithm(h, Q, grid, Qout, nfields, work, stream, reps,
+                                                  _c.byref(t0), _c.byref(t1)),
+          "shtn_plan_tune_algorithm")
+    return float(t0.value), float(t1.value)
+
+
 def shtn_plan_set_polar(h, log2_threshold):
     return check(load_library().shtn_plan_set_polar(h, log2_threshold), "shtn_plan_set_polar")
 
@@ -335,6 +393,7 @@ class Plan:
         self.npair = (self.nlat + 1) // 2
         self._work = {}
         self._dev = None
+        self._ptab = None
         if polar_log2 is not None:
             shtn_plan_set_polar(self.handle, int(polar_log2))
         if tiling is not None:
@@ -356,9 +415,70 @@ class Plan:
         self._upload()
 
     def set_polar(self, log2_threshold):
-        """Polar threshold exponent (see shtn_plan_set_polar); re-uploads."""
+        """Polar threshold exponent (see shtn_plan_set_polar); re-uploads and
+        rebuilds the stored-P table if the plan has one."""
+        algo = shtn_plan_get_algorithm(self.handle)
         shtn_plan_set_polar(self.handle, int(log2_threshold))
         self._upload()
+        if self._ptab is not None:
+            self.build_ptable()
+            shtn_plan_set_algorithm(self.handle, algo)
+
+    # --- stored-P Legendre stage (Sec. 3.1) and the runtime choice (Sec. 3.2) ---
+    def build_ptable(self):
+        """Allocates and builds the stored-P table (shtn_ptable_bytes of device memory)."""
+        import torch
+        nb = shtn_ptable_bytes(self.handle)
+        if self._ptab is None or self._ptab.numel() < nb + 256:
+            self._ptab = None
+            self._ptab = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._ptab.data_ptr()
+        shtn_ptable_build(self.handle, ptr + ((-ptr) % 256), nb, _stream_ptr(torch, self.device))
+
+    def release_ptable(self):
+        """Drops the table (and selects the on-the-fly algorithm)."""
+        shtn_ptable_release(self.handle)
+        self._ptab = None
+
+    def ptable_bytes(self):
+        return shtn_ptable_bytes(self.handle)
+
+    def set_algorithm(self, algo):
+        """'onthefly' or 'stored' (builds the table if the plan has none)."""
+        a = {"onthefly": SHTN_ALGO_ONTHEFLY, "stored": SHTN_ALGO_STORED}.get(algo, algo)
+        if a == SHTN_ALGO_STORED and self._ptab is None:
+            self.build_ptable()
+        shtn_plan_set_algorithm(self.handle, int(a))
+
+    def algorithm(self):
+        return "stored" if shtn_plan_get_algorithm(self.handle) == SHTN_ALGO_STORED else "onthefly"
+
+    def set_ptable_tiling(self, synth_rt=4, synth_ct=2, analys_jt=2, analys_ct=2):
+        shtn_ptable_set_tiling(self.handle, synth_rt, synth_ct, analys_jt, analys_ct)
+
+    def ptable_tiling(self):
+        t = shtn_ptable_get_tiling(self.handle)
+        return dict(synth_rt=t[0], synth_ct=t[1], analys_jt=t[2], analys_ct=t[3])
+
+    def tune_algorithm(self, nfields, reps=5, keep_table=False):
+        """Runtime choice between the two Legendre algorithms for calls of
+        nfields fields (Sec. 3.2): builds the table, times both on random
+        data, keeps the faster (the table is dropped when the on-the-fly
+        algorithm wins, unless keep_table)."""
+        import torch
+        if self._ptab is None:
+            self.build_ptable()
+        g = torch.Generator(device=self.device).manual_seed(12026522)
+        Q = torch.randn((nfields, self.nlm), dtype=torch.complex128, device=self.device, generator=g)
+        grid = torch.empty((nfields, self.nlat, self.nphi), dtype=torch.float64, device=self.device)
+        Qout = torch.empty_like(Q)
+        t_otf, t_sp = shtn_plan_tune_algorithm(self.handle, Q.data_ptr(), grid.data_ptr(), Qout.data_ptr(),
+                                               nfields, self.workspace(nfields),
+                                               _stream_ptr(torch, self.device), reps)
+        algo = self.algorithm()
+        if algo == "onthefly" and not keep_table:
+            self.release_ptable()
+        return dict(algorithm=algo, onthefly_us=t_otf, stored_us=t_sp)
 
     def polar_log2(self):
         return int(shtn_plan_table(self.handle, 13)[8])

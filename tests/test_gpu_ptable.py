@@ -1,0 +1,213 @@
+"""GPU parity of the stored-P Legendre stage (Sec. 3.1, precomputed P_n^m)
+and of the runtime choice between the two algorithms (Sec. 3.2).
+
+Bars: the table entries against the oracle's P_n^m(x_i) to 1e-12 of the
+largest |P| (both sides run an FP64 three-term recurrence; its rounding floor
+against long double is about 3e-13 of max |P| at lmax 255, 1.4e-13 measured
+here at lmax 100), exact 0 where the polar threshold drops a term, which
+needs |P| < 2^-200; the four transforms against the oracle to 1e-11 relative to
+the largest output (1e-9 at lmax 1023, sampled orders); stored against
+on-the-fly results to 1e-12 (the two sum the same terms in other orders).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_6522_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1202_6522_amd import shtn
+    shtn.load_library()
+    return torch.device("cuda:0")
+
+
+def make_plan(L, M, nlat, nphi, dev):
+    from paper_1202_6522_amd.shtn import Plan
+    return Plan(L, M, nlat, nphi, device=dev)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def decode_table(plan):
+    """The table as P[m][n][pair] (dense numpy, zero outside n >= m), read
+    back from the device through the documented block layout."""
+    L, M, npair = plan.lmax, plan.mmax, plan.npair
+    npt = (npair + 15) // 16
+    nb = plan.ptable_bytes()
+    raw = plan._ptab
+    off = (-raw.data_ptr()) % 256
+    buf = raw[off:off + nb].cpu().numpy()
+    head = ((M + 1) * 2 * 8 + 255) // 256 * 256
+    boff = buf[:(M + 1) * 16].view(np.int64)
+    blocks = buf[head:].view(np.float64).reshape(-1, 256)
+    jl = np.arange(16)[:, None]
+    pl = np.arange(16)[None, :]
+    inblk = (jl // 4) * 64 + (pl // 4) * 16 + (jl % 4) * 4 + pl % 4
+    out = np.zeros((M + 1, L + 1, npt * 16))
+    pad = []
+    for m in range(M + 1):
+        nj = L - m + 1
+        for q in range(2):
+            rows = (nj + 1 - q) // 2
+            nbr = (rows + 15) // 16
+            dense = np.zeros((nbr * 16, npt * 16))
+            for br in range(nbr):
+                for pt in range(npt):
+                    dense[br * 16:(br + 1) * 16, pt * 16:(pt + 1) * 16] = \
+                        blocks[boff[2 * m + q] + br * npt + pt][inblk]
+            js = 2 * np.arange(rows) + q
+            out[m, m + js, :] = dense[:rows]
+            pad.append(dense[rows:])
+    pad_vals = np.concatenate([p.ravel() for p in pad]) if pad else np.zeros(0)
+    return out[:, :, :npair], out[:, :, npair:], pad_vals
+
+
+@pytest.mark.parametrize("shape", [(31, 31, 32, 64), (63, 40, 65, 128), (100, 100, 101, 256), (0, 0, 1, 2)])
+def test_table_matches_oracle_plm(shape, dev):
+    L, M, nlat, nphi = shape
+    plan = make_plan(L, M, nlat, nphi, dev)
+    plan.build_ptable()
+    tab, pad_pairs, pad_rows = decode_table(plan)
+    x, _ = oracle.gauss(nlat)
+    P = oracle.plm(L, M, x[:plan.npair])  # [nlm, npair]
+    n_all, m_all = inputs.degree_order(L, M)
+    ref = np.zeros_like(tab)
+    ref[m_all, n_all, :] = P
+    scale = np.abs(ref).max()
+    zero = tab == 0.0
+    # entries kept by the polar threshold agree with P; dropped ones are tiny
+    assert np.max(np.abs(tab - ref)[~zero]) <= 1e-12 * scale
+    assert np.all(np.abs(ref[zero]) < 2.0 ** -200 * max(1.0, scale))
+    assert np.all(pad_pairs == 0.0) and np.all(pad_rows == 0.0)
+
+
+@pytest.mark.parametrize("shape", [(31, 31, 32, 64), (63, 40, 65, 128), (100, 100, 101, 256),
+                                   (0, 0, 1, 2), (5, 3, 7, 16)])
+@pytest.mark.parametrize("nf", [1, 3, 17])
+def test_stored_transforms_match_oracle(shape, nf, dev):
+    L, M, nlat, nphi = shape
+    rng = np.random.default_rng(L * 100 + nf)
+    Q = inputs.draw_spectrum(rng, L, M, 1.0, nf)
+    Q[:, :L + 1] += 0.5j  # Im Q_n^0 must be ignored
+    grid = rng.standard_normal((nf, nlat, nphi))
+    plan = make_plan(L, M, nlat, nphi, dev)
+    plan.set_algorithm("stored")
+    assert plan.algorithm() == "stored"
+    g = plan.synth(to_dev(Q, dev)).cpu().numpy()
+    assert rel(g, oracle.synth(Q, L, M, nlat, nphi)) <= 1e-11
+    A = plan.analys(to_dev(grid, dev)).cpu().numpy()
+    assert rel(A, oracle.analys(grid, L, M, nlat, nphi)) <= 1e-11
+    assert np.all(A[:, :L + 1].imag == 0)
+    St = plan.synth_adj(to_dev(grid, dev)).cpu().numpy()
+    assert rel(St, oracle.synth_adj(grid, L, M, nlat, nphi)) <= 1e-11
+    At = plan.analys_adj(to_dev(Q, dev)).cpu().numpy()
+    assert rel(At, oracle.analys_adj(Q, L, M, nlat, nphi)) <= 1e-11
+
+
+@pytest.mark.parametrize("tiling", [
+    dict(synth_rt=1, synth_ct=1, analys_jt=1, analys_ct=1),
+    dict(synth_rt=2, synth_ct=2, analys_jt=4, analys_ct=1),
+    dict(synth_rt=4, synth_ct=1, analys_jt=2, analys_ct=2),
+    dict(synth_rt=4, synth_ct=2, analys_jt=4, analys_ct=2),
+])
+def test_stored_tilings_agree_with_onthefly(tiling, dev):
+    L, M, nlat, nphi = 127, 127, 129, 256  # odd nlat: a middle latitude, a ragged pair tile
+    rng = np.random.default_rng(41)
+    nf = 19
+    Q = to_dev(inputs.draw_spectrum(rng, L, M, 1.5, nf), dev)
+    grid = to_dev(rng.standard_normal((nf, nlat, nphi)), dev)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    ref = [plan.synth(Q), plan.analys(grid), plan.synth_adj(grid), plan.analys_adj(Q)]
+    plan.set_ptable_tiling(**tiling)
+    assert plan.ptable_tiling() == tiling
+    plan.set_algorithm("stored")
+    got = [plan.synth(Q), plan.analys(grid), plan.synth_adj(grid), plan.analys_adj(Q)]
+    for a, b in zip(got, ref):
+        assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+
+
+def test_stored_lmax1023_sampled(dev):
+    p, Q1 = inputs.scalar_case(2)
+    L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+    rng = np.random.default_rng(7)
+    Q = np.concatenate([Q1, inputs.draw_spectrum(rng, L, M, 1.5, 2)])
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Qd = to_dev(Q, dev)
+    g_otf = plan.synth(Qd)
+    plan.set_algorithm("stored")
+    g = plan.synth(Qd)
+    assert rel(g.cpu().numpy(), g_otf.cpu().numpy()) <= 1e-12
+    rows = np.array([0, 1, 17, 255, 511, 512, 1000, 1023])
+    gref = oracle.synth(Q[:1], L, M, nlat, nphi, rows=rows)
+    assert rel(g[0].cpu().numpy()[rows], gref[0]) <= 1e-9
+    R = plan.analys(g).cpu().numpy()
+    assert rel(R, Q) <= 1e-9
+    grid = inputs.random_grid(5, 1, nlat, nphi)[0]
+    A = plan.analys(to_dev(grid, dev)).cpu().numpy()
+    ms = [0, 1, 300, 777, 1023]
+    Aref = oracle.analys(grid, L, M, nlat, nphi, mlist=ms)
+    _, m_all = inputs.degree_order(L, M)
+    sel = np.isin(m_all, ms)
+    assert rel(A[sel], Aref[sel]) <= 1e-9
+
+
+def test_stored_follows_polar_threshold(dev):
+    L, M, nlat, nphi = 255, 255, 256, 512
+    rng = np.random.default_rng(5)
+    Q = to_dev(inputs.draw_spectrum(rng, L, M, 1.0, 4), dev)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    plan.set_algorithm("stored")
+    plan.set_polar(-40)  # rebuilds the table for the new lane starts
+    assert plan.algorithm() == "stored"
+    g_sp = plan.synth(Q).cpu().numpy()
+    a_sp = plan.analys(plan.synth(Q)).cpu().numpy()
+    plan.set_algorithm("onthefly")
+    g_otf = plan.synth(Q).cpu().numpy()
+    a_otf = plan.analys(plan.synth(Q)).cpu().numpy()
+    assert rel(g_sp, g_otf) <= 1e-12
+    assert rel(a_sp, a_otf) <= 1e-12
+
+
+def test_tune_algorithm(dev):
+    L, M, nlat, nphi = 127, 127, 128, 256
+    plan = make_plan(L, M, nlat, nphi, dev)
+    res = plan.tune_algorithm(16, reps=3)
+    assert res["algorithm"] in ("onthefly", "stored")
+    assert res["onthefly_us"] > 0 and res["stored_us"] > 0
+    assert plan.algorithm() == res["algorithm"]
+    rng = np.random.default_rng(9)
+    Q = inputs.draw_spectrum(rng, L, M, 1.0, 16)
+    R = plan.analys(plan.synth(to_dev(Q, dev))).cpu().numpy()
+    assert rel(R, Q) <= 1e-11
+
+
+def test_autograd_through_stored(dev):
+    from paper_1202_6522_amd.autograd import synth
+    L, M, nlat, nphi = 63, 63, 64, 128
+    rng = np.random.default_rng(21)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Q0 = to_dev(inputs.draw_spectrum(rng, L, M, 1.0, 9), dev)
+    T = to_dev(rng.standard_normal((9, nlat, nphi)), dev)
+
+    def grad():
+        Q = Q0.clone().requires_grad_(True)
+        ((synth(Q, plan) - T) ** 2).sum().backward()
+        return Q.grad.cpu().numpy()
+
+    g_otf = grad()
+    plan.set_algorithm("stored")
+    g_sp = grad()
+    assert rel(g_sp, g_otf) <= 1e-12

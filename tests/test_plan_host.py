@@ -542,3 +542,37 @@ def test_polar_threshold_setting():
             assert np.array_equal(again[k], base[k]), k
     finally:
         S.shtn_plan_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(0, 0, 1, 2), (31, 31, 32, 64), (63, 40, 65, 128), (1023, 1023, 1024, 2048)])
+def test_ptable_geometry_and_states(lib, shape):
+    """Stored-P table size: per order m (nj = lmax - m + 1) ceil(nj/2) even and
+    floor(nj/2) odd degree rows, each parity in block rows of 16 x ceil(npair/16)
+    blocks of 16 x 16 doubles, after the block offsets padded to 256 bytes."""
+    L, M, nlat, nphi = shape
+    h = S.shtn_plan(L, M, nlat, nphi)
+    try:
+        npt = ((nlat + 1) // 2 + 15) // 16
+        nblocks = sum(((L - m + 2) // 2 + 15) // 16 * npt + ((L - m + 1) // 2 + 15) // 16 * npt
+                      for m in range(M + 1))
+        head = ((M + 1) * 2 * 8 + 255) // 256 * 256
+        assert S.shtn_ptable_bytes(h) == head + nblocks * 2048
+        if shape[0] == 1023:
+            assert abs(S.shtn_ptable_bytes(h) / 2.2e9 - 1) < 0.05
+        # no table yet: the stored algorithm is refused, building needs an upload
+        assert lib.shtn_plan_set_algorithm(h, S.SHTN_ALGO_STORED) == S.SHTN_ESTATE
+        assert lib.shtn_plan_set_algorithm(h, 2) == S.SHTN_EINVAL
+        assert S.shtn_plan_get_algorithm(h) == S.SHTN_ALGO_ONTHEFLY
+        assert lib.shtn_ptable_build(h, ctypes.c_void_p(4096), 1 << 40, None) == S.SHTN_ESTATE
+        assert S.shtn_ptable_get_tiling(h) == [4, 2, 2, 2]
+        for bad in [(3, 1, 1, 1), (1, 4, 1, 1), (1, 1, 8, 1), (1, 1, 1, 0)]:
+            assert lib.shtn_ptable_set_tiling(h, *bad) == S.SHTN_EINVAL
+        S.shtn_ptable_set_tiling(h, 2, 1, 4, 2)
+        assert S.shtn_ptable_get_tiling(h) == [2, 1, 4, 2]
+        S.shtn_ptable_release(h)
+        assert S.shtn_plan_get_algorithm(h) == S.SHTN_ALGO_ONTHEFLY
+        one = ctypes.c_void_p(16)
+        assert lib.shtn_plan_tune_algorithm(h, one, ctypes.c_void_p(32), ctypes.c_void_p(48), 1, one, None,
+                                            1, None, None) == S.SHTN_ESTATE
+    finally:
+        S.shtn_plan_destroy(h)
