@@ -136,27 +136,48 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
 #pragma unroll
             for (int c = 0; c < CT; c++) acc[q][r][c] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // Step br covers block row br of both parities (the odd parity has as
+    // many rows as the even one, or one fewer: its missing row reloads the
+    // even row and feeds zeros).  All operands of a step are loaded before
+    // its first matrix instruction, every load unconditional from a valid
+    // address (one memory round trip per step; the waves resident on a SIMD
+    // overlap them): degrees past the order's last are masked by a factor 0
+    // (the clamped coefficient belongs to the same order, so this can only
+    // turn an output that already involves a non-finite input into NaN),
+    // other invalid operands by selects.
+    const int nbr0 = (((nj + 1) >> 1) + 15) >> 4, nbr1 = ((nj >> 1) + 15) >> 4;
+    const double* t0 = a.tab + a.boff[2 * m] * 256 + (long)pg * RT * 256 + a_off;
+    const double* t1 = a.tab + a.boff[2 * m + 1] * 256 + (long)pg * RT * 256 + a_off;
+    struct Ops {
+        double a[2][4][RT];
+        double b[2][4][CT];
+    };
+    auto load = [&](Ops& o, int br) {
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
-        const int cnt = q ? nj >> 1 : (nj + 1) >> 1;
-        const int nbr = (cnt + 15) >> 4;  // block rows of this parity
-        const double* tq = a.tab + a.boff[2 * m + q] * 256 + (long)pg * RT * 256 + a_off;
-        for (int br = 0; br < nbr; br++) {
-            const double* tb = tq + (long)br * npt * 256;
+        for (int q = 0; q < 2; q++) {
+            const double* tb = (q && br < nbr1 ? t1 : t0) + (long)br * npt * 256;
 #pragma unroll
             for (int s = 0; s < 4; s++) {
-                const int j = 2 * (br * 16 + s * 4 + kk) + q;
-                double bv[CT], av[RT];
 #pragma unroll
-                for (int c = 0; c < CT; c++) {
-                    const double v = qp[c][2 * min(j, nj - 1)];
-                    bv[c] = (j < nj && fv[c]) ? v : 0.0;
-                }
+                for (int r = 0; r < RT; r++) o.a[q][s][r] = tb[tr[r] * 256 + s * 64];
+                const int j = min(2 * (br * 16 + s * 4 + kk) + q, nj - 1);
 #pragma unroll
-                for (int r = 0; r < RT; r++) {
-                    const double v = tb[tr[r] * 256 + s * 64];
-                    av[r] = tv[r] ? v : 0.0;
-                }
+                for (int c = 0; c < CT; c++) o.b[q][s][c] = qp[c][2 * j];
+            }
+        }
+    };
+    auto run = [&](const Ops& o, int br) {
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const bool rowv = q == 0 || br < nbr1;
+#pragma unroll
+            for (int s = 0; s < 4; s++) {
+                const double mj = 2 * (br * 16 + s * 4 + kk) + q < nj ? 1.0 : 0.0;
+                double av[RT], bv[CT];
+#pragma unroll
+                for (int c = 0; c < CT; c++) bv[c] = o.b[q][s][c] * (fv[c] ? mj : 0.0);
+#pragma unroll
+                for (int r = 0; r < RT; r++) av[r] = (tv[r] && rowv) ? o.a[q][s][r] : 0.0;
 #pragma unroll
                 for (int r = 0; r < RT; r++)
 #pragma unroll
@@ -164,6 +185,11 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
                         acc[q][r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], acc[q][r][c], 0, 0, 0);
             }
         }
+    };
+    for (int br = 0; br < nbr0; br++) {
+        Ops o;
+        load(o, br);
+        run(o, br);
     }
 
     // For the adjoint of the analysis the output carries (2 pi/nphi) w_i / c_m.
@@ -242,30 +268,41 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
 #pragma unroll
             for (int c = 0; c < CT; c++) acc[q][t][c] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // Per pair tile (4 steps of 4 pairs) every operand is loaded before the
+    // first matrix instruction, unconditionally from valid addresses (pairs
+    // past the last read the last pair with weight 0): one memory round trip
+    // per tile, overlapped across the waves resident on a SIMD.
     for (int pt = 0; pt < npt; pt++) {
+        double pa[4][2][JT], vn[4][CT], vs[4][CT], wv[4];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            const int pair = pt * 16 + s * 4 + kk;
-            const bool pv = pair < npair;
-            const int pc = pv ? pair : 0;
-            const bool middle = (nlat & 1) && pc == npair - 1;
-            const double wt = !pv ? 0.0 : (a.adjoint ? (middle ? 0.5 : 1.0) : P.wq[pc]);
-            double ge[CT], go[CT];
+            const int pc = min(pt * 16 + s * 4 + kk, npair - 1);
+            wv[s] = P.wq[pc];
 #pragma unroll
             for (int c = 0; c < CT; c++) {
-                const double vn = fp[c][2 * f_index(P.f_ts, m, pc)];
-                const double vs = fp[c][2 * f_index(P.f_ts, m, nlat - 1 - pc)];
-                ge[c] = wt * (vn + vs);
-                go[c] = wt * (vn - vs);
+                vn[s][c] = fp[c][2 * f_index(P.f_ts, m, pc)];
+                vs[s][c] = fp[c][2 * f_index(P.f_ts, m, nlat - 1 - pc)];
             }
-            double av[2][JT];
 #pragma unroll
             for (int q = 0; q < 2; q++)
 #pragma unroll
-                for (int t = 0; t < JT; t++) {
-                    const double v = tq[q][t][pt * 256 + s * 16];
-                    av[q][t] = rv[q][t] ? v : 0.0;
-                }
+                for (int t = 0; t < JT; t++) pa[s][q][t] = tq[q][t][pt * 256 + s * 16];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int pair = pt * 16 + s * 4 + kk;
+            const bool middle = (nlat & 1) && pair == npair - 1;
+            const double wt = pair >= npair ? 0.0 : (a.adjoint ? (middle ? 0.5 : 1.0) : wv[s]);
+            double ge[CT], go[CT], av[2][JT];
+#pragma unroll
+            for (int c = 0; c < CT; c++) {
+                ge[c] = wt * (vn[s][c] + vs[s][c]);
+                go[c] = wt * (vn[s][c] - vs[s][c]);
+            }
+#pragma unroll
+            for (int q = 0; q < 2; q++)
+#pragma unroll
+                for (int t = 0; t < JT; t++) av[q][t] = rv[q][t] ? pa[s][q][t] : 0.0;
 #pragma unroll
             for (int t = 0; t < JT; t++)
 #pragma unroll
