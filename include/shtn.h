@@ -176,8 +176,12 @@ int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
  * lmax 1023), so it pays off with many fields per call.  Results agree with
  * the on-the-fly kernels to rounding: the table holds the same recurrence
  * values, and 0 where the polar threshold drops a term. */
-#define SHTN_ALGO_ONTHEFLY 0
-#define SHTN_ALGO_STORED 1
+#define SHTN_ALGO_ONTHEFLY 0       /* both passes recompute P (default)          */
+#define SHTN_ALGO_STORED 1         /* both passes read the table                 */
+#define SHTN_ALGO_STORED_SYNTH 2   /* synthesis-type passes (synthesis, adjoint  */
+                                   /* of the analysis) read it, the others not   */
+#define SHTN_ALGO_STORED_ANALYS 3  /* analysis-type passes (analysis, adjoint of */
+                                   /* the synthesis) read it, the others not     */
 /* Bytes of device memory the plan's table needs; negative on error. */
 long shtn_ptable_bytes(shtn_plan_t plan);
 /* Builds the table into dev_buf (device memory owned by the caller, 256-byte
@@ -193,25 +197,27 @@ int shtn_ptable_release(shtn_plan_t plan);
 /* Work decomposition of the stored-P kernels (one wave each): synthesis
  * synth_rt (1, 2, 4) tiles of 16 latitude pairs x synth_ct (1, 2) tiles of 8
  * fields; analysis analys_jt (1, 2, 4) tiles of 16 degrees of each parity x
- * analys_ct (1, 2) tiles of 8 fields.  Default 4, 2, 2, 2.  SHTN_EINVAL for
+ * analys_ct (1, 2) tiles of 8 fields.  Default 4, 2, 4, 2.  SHTN_EINVAL for
  * other values.  Takes effect at the next call. */
 int shtn_ptable_set_tiling(shtn_plan_t plan, int synth_rt, int synth_ct, int analys_jt, int analys_ct);
 /* tiling4 = {synth_rt, synth_ct, analys_jt, analys_ct}. */
 int shtn_ptable_get_tiling(shtn_plan_t plan, int* tiling4);
-/* Selects the Legendre algorithm of the four transforms: SHTN_ALGO_ONTHEFLY
- * (default) or SHTN_ALGO_STORED (needs a current table, else SHTN_ESTATE).
- * The FFT stages are the same for both. */
+/* Selects the Legendre algorithm of the four transforms, one of SHTN_ALGO_*
+ * (anything but SHTN_ALGO_ONTHEFLY needs a current table, else SHTN_ESTATE).
+ * The FFT stages are the same for all. */
 int shtn_plan_set_algorithm(shtn_plan_t plan, int algo);
 /* The selected algorithm, or a negative error code. */
 int shtn_plan_get_algorithm(shtn_plan_t plan);
-/* Runtime tuning (Sec. 3.2): times `reps` synthesis (Q -> grid) plus analysis
- * (grid -> Qout) round trips of nfields fields with each algorithm (the
- * stored one only if the table is current), selects the faster and returns
- * the two mean round-trip times in microseconds (us_stored = -1 when not
- * timed; either pointer may be NULL).  Q, grid and Qout are device buffers
- * of nfields fields; Qout must not alias Q.  Blocks until done. */
+/* Runtime tuning (Sec. 3.2): times `reps` synthesis calls (Q -> grid) and
+ * `reps` analysis calls (grid -> Qout) of nfields fields with each algorithm
+ * (the stored one only if the table is current), and selects for each pass
+ * type the faster (the adjoints follow the pass they share kernels with).
+ * us4 (may be NULL) receives the mean times in microseconds: synthesis
+ * on-the-fly, synthesis stored, analysis on-the-fly, analysis stored (-1
+ * when not timed).  Q, grid and Qout are device buffers of nfields fields;
+ * Qout must not alias Q.  Blocks until done. */
 int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, double* Qout, int nfields,
-                             void* work, void* stream, int reps, float* us_onthefly, float* us_stored);
+                             void* work, void* stream, int reps, float* us4);
 
 /* Measures the FP64 vector FMA rate (TFLOP/s, 2 flops per FMA) that the
  * current device sustains with four waves per SIMD on independent chains

@@ -61,6 +61,10 @@ int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, c
     return SHTN_OK;
 }
 
+// Which passes of an algorithm choice read the stored table.
+bool stored_synth(int algo) { return algo == SHTN_ALGO_STORED || algo == SHTN_ALGO_STORED_SYNTH; }
+bool stored_analys(int algo) { return algo == SHTN_ALGO_STORED || algo == SHTN_ALGO_STORED_ANALYS; }
+
 // Stored-P kernel arguments; ESTATE when the plan has no current table.
 int sp_args(const Plan& p, const double* in, double* out, int nfields, int adjoint, PtabArgs& a)
 {
@@ -81,7 +85,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     double* F = (double*)work;
     double* Qs = (double*)((char*)work + wl.f_bytes);
     int e;
-    if (p.algo == 1) {
+    if (stored_synth(p.algo)) {
         PtabArgs a;
         if ((rc = sp_args(p, Q, F, nfields, adjoint, a))) return rc;
         {
@@ -139,9 +143,9 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     int rc = check_call(plan, grid, Q, nfields, work);
     if (rc) return rc;
     const Plan& p = *plan->p;
-    if (p.algo == 0 && p.npair > kMaxAnalysPairs)
+    if (!stored_analys(p.algo) && p.npair > kMaxAnalysPairs)
         return fail(SHTN_EUNSUPPORTED, "on-the-fly analysis supports at most 4096 latitudes");
-    if (p.algo == 1 && !p.ptab.built)
+    if (stored_analys(p.algo) && !p.ptab.built)
         return fail(SHTN_ESTATE, "stored-P table not built for the current plan (shtn_ptable_build)");
     double* F = (double*)work;
     FftLaunch f{};
@@ -161,7 +165,7 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
         e = launch_r2c(f, stream);
     }
     if (e) return hip_fail(e, "r2c launch");
-    if (p.algo == 1) {
+    if (stored_analys(p.algo)) {
         PtabArgs a;
         if ((rc = sp_args(p, F, Q, nfields, adjoint, a))) return rc;
         const int nbr_max = ((p.L + 2) / 2 + 15) / 16;  // block rows of order 0, even parity
@@ -525,9 +529,9 @@ int shtn_ptable_get_tiling(shtn_plan_t plan, int* tiling4)
 int shtn_plan_set_algorithm(shtn_plan_t plan, int algo)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
-    if (algo != SHTN_ALGO_ONTHEFLY && algo != SHTN_ALGO_STORED)
-        return fail(SHTN_EINVAL, "algorithm must be SHTN_ALGO_ONTHEFLY or SHTN_ALGO_STORED");
-    if (algo == SHTN_ALGO_STORED && !plan->p->ptab.built)
+    if (algo < SHTN_ALGO_ONTHEFLY || algo > SHTN_ALGO_STORED_ANALYS)
+        return fail(SHTN_EINVAL, "algorithm must be one of SHTN_ALGO_*");
+    if (algo != SHTN_ALGO_ONTHEFLY && !plan->p->ptab.built)
         return fail(SHTN_ESTATE, "stored-P table not built for the current plan (shtn_ptable_build)");
     plan->p->algo = algo;
     return SHTN_OK;
@@ -540,7 +544,7 @@ int shtn_plan_get_algorithm(shtn_plan_t plan)
 }
 
 int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, double* Qout, int nfields,
-                             void* work, void* stream, int reps, float* us_onthefly, float* us_stored)
+                             void* work, void* stream, int reps, float* us4)
 {
     int rc = check_call(plan, Q, grid, nfields, work);
     if (rc) return rc;
@@ -549,39 +553,51 @@ int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, do
     if (reps < 1) reps = 5;
     Plan& p = *plan->p;
     const int keep = p.algo;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) (void)hipEventDestroy(e0);
-        return hip_fail((int)hipGetLastError(), "tuner events");
-    }
-    float t[2] = {-1.f, -1.f};
-    for (int algo = 0; algo < 2 && !rc; algo++) {
-        if (algo == SHTN_ALGO_STORED && !p.ptab.built) break;
-        p.algo = algo;
-        // one untimed round trip, then the timed ones
-        for (int r = -1; r < reps && !rc; r++) {
-            if (r == 0 && hipEventRecord(e0, (hipStream_t)stream) != hipSuccess)
-                rc = hip_fail((int)hipGetLastError(), "tuner event record");
-            if (!rc) rc = to_grid(plan, Q, grid, nfields, work, stream, 0);
-            if (!rc) rc = to_spec(plan, grid, Qout, nfields, work, stream, 0);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return hip_fail((int)hipGetLastError(), "tuner events");
         }
-        if (!rc && hipEventRecord(e1, (hipStream_t)stream) != hipSuccess)
-            rc = hip_fail((int)hipGetLastError(), "tuner event record");
-        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = hip_fail((int)hipGetLastError(), "tuner sync");
-        float ms = 0.f;
-        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+    // t[pass][algo]: mean synthesis (pass 0) and analysis (pass 1) times
+    float t[2][2] = {{-1.f, -1.f}, {-1.f, -1.f}};
+    hipStream_t st = (hipStream_t)stream;
+    for (int algo = 0; algo < 2 && !rc; algo++) {
+        if (algo == 1 && !p.ptab.built) break;
+        p.algo = algo;
+        // one untimed round trip, then reps synthesis calls and reps analysis calls
+        rc = to_grid(plan, Q, grid, nfields, work, stream, 0);
+        if (!rc) rc = to_spec(plan, grid, Qout, nfields, work, stream, 0);
+        if (!rc && hipEventRecord(ev[0], st) != hipSuccess) rc = hip_fail((int)hipGetLastError(), "tuner event");
+        for (int r = 0; r < reps && !rc; r++) rc = to_grid(plan, Q, grid, nfields, work, stream, 0);
+        if (!rc && hipEventRecord(ev[1], st) != hipSuccess) rc = hip_fail((int)hipGetLastError(), "tuner event");
+        for (int r = 0; r < reps && !rc; r++) rc = to_spec(plan, grid, Qout, nfields, work, stream, 0);
+        if (!rc && hipEventRecord(ev[2], st) != hipSuccess) rc = hip_fail((int)hipGetLastError(), "tuner event");
+        if (!rc && hipEventSynchronize(ev[2]) != hipSuccess) rc = hip_fail((int)hipGetLastError(), "tuner sync");
+        float ms0 = 0.f, ms1 = 0.f;
+        if (!rc && (hipEventElapsedTime(&ms0, ev[0], ev[1]) != hipSuccess ||
+                    hipEventElapsedTime(&ms1, ev[1], ev[2]) != hipSuccess))
             rc = hip_fail((int)hipGetLastError(), "tuner elapsed time");
-        if (!rc) t[algo] = 1e3f * ms / reps;
+        if (!rc) {
+            t[0][algo] = 1e3f * ms0 / reps;
+            t[1][algo] = 1e3f * ms1 / reps;
+        }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc) {
         p.algo = keep;
         return rc;
     }
-    p.algo = (t[1] >= 0.f && t[1] < t[0]) ? SHTN_ALGO_STORED : SHTN_ALGO_ONTHEFLY;
-    if (us_onthefly) *us_onthefly = t[0];
-    if (us_stored) *us_stored = t[1];
+    const bool ss = t[0][1] >= 0.f && t[0][1] < t[0][0];
+    const bool sa = t[1][1] >= 0.f && t[1][1] < t[1][0];
+    p.algo = ss ? (sa ? SHTN_ALGO_STORED : SHTN_ALGO_STORED_SYNTH) : (sa ? SHTN_ALGO_STORED_ANALYS : SHTN_ALGO_ONTHEFLY);
+    if (us4) {
+        us4[0] = t[0][0];
+        us4[1] = t[0][1];
+        us4[2] = t[1][0];
+        us4[3] = t[1][1];
+    }
     return SHTN_OK;
 }
 

@@ -138,7 +138,7 @@ struct PTable {
     void* dev = nullptr;      // caller's buffer once built
     bool built = false;       // matches the plan's current lane starts
     int synth_rt = 4, synth_ct = 2;    // synthesis: pair tiles, column tiles per wave
-    int analys_jt = 2, analys_ct = 2;  // analysis: block rows per parity, column tiles per wave
+    int analys_jt = 4, analys_ct = 2;  // analysis: block rows per parity, column tiles per wave
 };
 
 struct Plan {

@@ -27,6 +27,10 @@ SHTN_EHIP = -4
 SHTN_ENOMEM = -5
 SHTN_ALGO_ONTHEFLY = 0
 SHTN_ALGO_STORED = 1
+SHTN_ALGO_STORED_SYNTH = 2
+SHTN_ALGO_STORED_ANALYS = 3
+ALGORITHMS = {"onthefly": SHTN_ALGO_ONTHEFLY, "stored": SHTN_ALGO_STORED,
+              "stored_synth": SHTN_ALGO_STORED_SYNTH, "stored_analys": SHTN_ALGO_STORED_ANALYS}
 
 _lib = None
 
@@ -73,7 +77,7 @@ _SIGS = {
     "shtn_plan_set_algorithm": (_c.c_int, [_vp, _c.c_int]),
     "shtn_plan_get_algorithm": (_c.c_int, [_vp]),
     "shtn_plan_tune_algorithm": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int, _vp, _vp, _c.c_int,
-                                            _c.POINTER(_c.c_float), _c.POINTER(_c.c_float)]),
+                                            _c.POINTER(_c.c_float)]),
     "shtn_fp64_probe_tflops": (_c.c_double, [_vp]),
     "shtn_profile_enable": (_c.c_int, [_c.c_int]),
     "shtn_profile_select": (_c.c_int, [_c.c_uint]),
@@ -252,13 +256,12 @@ def shtn_plan_get_algorithm(h):
 
 
 def shtn_plan_tune_algorithm(h, Q, grid, Qout, nfields, work, stream, reps=5):
-    """Returns (on-the-fly, stored) mean round-trip microseconds (stored -1 if not timed)."""
-    t0 = _c.c_float(-1.0)
-    t1 = _c.c_float(-1.0)
-    check(load_library().shtn_plan_tune_algorithm(h, Q, grid, Qout, nfields, work, stream, reps,
-                                                  _c.byref(t0), _c.byref(t1)),
+    """Mean microseconds [synthesis on-the-fly, synthesis stored, analysis
+    on-the-fly, analysis stored] (-1 where not timed)."""
+    t = (_c.c_float * 4)()
+    check(load_library().shtn_plan_tune_algorithm(h, Q, grid, Qout, nfields, work, stream, reps, t),
           "shtn_plan_tune_algorithm")
-    return float(t0.value), float(t1.value)
+    return [float(v) for v in t]
 
 
 def shtn_plan_set_polar(h, log2_threshold):
@@ -444,16 +447,18 @@ class Plan:
         return shtn_ptable_bytes(self.handle)
 
     def set_algorithm(self, algo):
-        """'onthefly' or 'stored' (builds the table if the plan has none)."""
-        a = {"onthefly": SHTN_ALGO_ONTHEFLY, "stored": SHTN_ALGO_STORED}.get(algo, algo)
-        if a == SHTN_ALGO_STORED and self._ptab is None:
+        """'onthefly', 'stored', 'stored_synth' or 'stored_analys' (the
+        passes that read the table; builds it if the plan has none)."""
+        a = ALGORITHMS.get(algo, algo)
+        if a != SHTN_ALGO_ONTHEFLY and self._ptab is None:
             self.build_ptable()
         shtn_plan_set_algorithm(self.handle, int(a))
 
     def algorithm(self):
-        return "stored" if shtn_plan_get_algorithm(self.handle) == SHTN_ALGO_STORED else "onthefly"
+        v = shtn_plan_get_algorithm(self.handle)
+        return next(k for k, a in ALGORITHMS.items() if a == v)
 
-    def set_ptable_tiling(self, synth_rt=4, synth_ct=2, analys_jt=2, analys_ct=2):
+    def set_ptable_tiling(self, synth_rt=4, synth_ct=2, analys_jt=4, analys_ct=2):
         shtn_ptable_set_tiling(self.handle, synth_rt, synth_ct, analys_jt, analys_ct)
 
     def ptable_tiling(self):
@@ -472,13 +477,13 @@ class Plan:
         Q = torch.randn((nfields, self.nlm), dtype=torch.complex128, device=self.device, generator=g)
         grid = torch.empty((nfields, self.nlat, self.nphi), dtype=torch.float64, device=self.device)
         Qout = torch.empty_like(Q)
-        t_otf, t_sp = shtn_plan_tune_algorithm(self.handle, Q.data_ptr(), grid.data_ptr(), Qout.data_ptr(),
-                                               nfields, self.workspace(nfields),
-                                               _stream_ptr(torch, self.device), reps)
+        t = shtn_plan_tune_algorithm(self.handle, Q.data_ptr(), grid.data_ptr(), Qout.data_ptr(),
+                                     nfields, self.workspace(nfields), _stream_ptr(torch, self.device), reps)
         algo = self.algorithm()
         if algo == "onthefly" and not keep_table:
             self.release_ptable()
-        return dict(algorithm=algo, onthefly_us=t_otf, stored_us=t_sp)
+        return dict(algorithm=algo, synth_onthefly_us=t[0], synth_stored_us=t[1],
+                    analys_onthefly_us=t[2], analys_stored_us=t[3])
 
     def polar_log2(self):
         return int(shtn_plan_table(self.handle, 13)[8])

@@ -185,13 +185,34 @@ def test_tune_algorithm(dev):
     L, M, nlat, nphi = 127, 127, 128, 256
     plan = make_plan(L, M, nlat, nphi, dev)
     res = plan.tune_algorithm(16, reps=3)
-    assert res["algorithm"] in ("onthefly", "stored")
-    assert res["onthefly_us"] > 0 and res["stored_us"] > 0
+    assert res["algorithm"] in ("onthefly", "stored", "stored_synth", "stored_analys")
+    for k in ("synth_onthefly_us", "synth_stored_us", "analys_onthefly_us", "analys_stored_us"):
+        assert res[k] > 0
     assert plan.algorithm() == res["algorithm"]
+    # each pass type takes the faster of its two timings
+    assert ("stored" in res["algorithm"] and res["algorithm"] != "stored_analys") == \
+        (res["synth_stored_us"] < res["synth_onthefly_us"])
+    assert res["algorithm"] in (("stored", "stored_analys") if res["analys_stored_us"] < res["analys_onthefly_us"]
+                                else ("onthefly", "stored_synth"))
     rng = np.random.default_rng(9)
     Q = inputs.draw_spectrum(rng, L, M, 1.0, 16)
     R = plan.analys(plan.synth(to_dev(Q, dev))).cpu().numpy()
     assert rel(R, Q) <= 1e-11
+
+
+@pytest.mark.parametrize("algo", ["stored_synth", "stored_analys"])
+def test_mixed_algorithms(algo, dev):
+    L, M, nlat, nphi = 63, 50, 65, 128
+    rng = np.random.default_rng(33)
+    Q = inputs.draw_spectrum(rng, L, M, 1.0, 5)
+    grid = rng.standard_normal((5, nlat, nphi))
+    plan = make_plan(L, M, nlat, nphi, dev)
+    plan.set_algorithm(algo)
+    assert plan.algorithm() == algo
+    assert rel(plan.synth(to_dev(Q, dev)).cpu().numpy(), oracle.synth(Q, L, M, nlat, nphi)) <= 1e-11
+    assert rel(plan.analys(to_dev(grid, dev)).cpu().numpy(), oracle.analys(grid, L, M, nlat, nphi)) <= 1e-11
+    assert rel(plan.synth_adj(to_dev(grid, dev)).cpu().numpy(), oracle.synth_adj(grid, L, M, nlat, nphi)) <= 1e-11
+    assert rel(plan.analys_adj(to_dev(Q, dev)).cpu().numpy(), oracle.analys_adj(Q, L, M, nlat, nphi)) <= 1e-11
 
 
 def test_autograd_through_stored(dev):

@@ -561,10 +561,11 @@ def test_ptable_geometry_and_states(lib, shape):
             assert abs(S.shtn_ptable_bytes(h) / 2.2e9 - 1) < 0.05
         # no table yet: the stored algorithm is refused, building needs an upload
         assert lib.shtn_plan_set_algorithm(h, S.SHTN_ALGO_STORED) == S.SHTN_ESTATE
-        assert lib.shtn_plan_set_algorithm(h, 2) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_algorithm(h, 4) == S.SHTN_EINVAL
+        assert lib.shtn_plan_set_algorithm(h, S.SHTN_ALGO_STORED_SYNTH) == S.SHTN_ESTATE
         assert S.shtn_plan_get_algorithm(h) == S.SHTN_ALGO_ONTHEFLY
         assert lib.shtn_ptable_build(h, ctypes.c_void_p(4096), 1 << 40, None) == S.SHTN_ESTATE
-        assert S.shtn_ptable_get_tiling(h) == [4, 2, 2, 2]
+        assert S.shtn_ptable_get_tiling(h) == [4, 2, 4, 2]
         for bad in [(3, 1, 1, 1), (1, 4, 1, 1), (1, 1, 8, 1), (1, 1, 1, 0)]:
             assert lib.shtn_ptable_set_tiling(h, *bad) == S.SHTN_EINVAL
         S.shtn_ptable_set_tiling(h, 2, 1, 4, 2)
@@ -573,6 +574,6 @@ def test_ptable_geometry_and_states(lib, shape):
         assert S.shtn_plan_get_algorithm(h) == S.SHTN_ALGO_ONTHEFLY
         one = ctypes.c_void_p(16)
         assert lib.shtn_plan_tune_algorithm(h, one, ctypes.c_void_p(32), ctypes.c_void_p(48), 1, one, None,
-                                            1, None, None) == S.SHTN_ESTATE
+                                            1, None) == S.SHTN_ESTATE
     finally:
         S.shtn_plan_destroy(h)
