@@ -8,14 +8,16 @@ transform of Schaeffer (arXiv 1202.6522), used to check the GPU library.  Only
 The arithmetic lives in ``shtn_oracle.c`` (double and long-double
 instantiations); this module only marshals numpy arrays through ctypes.
 ``dense.py`` holds an independent tiny dense brute force built on scipy, used
-to pin the C oracle itself.
+to pin the C oracle itself.  ``vector.py`` holds the vector (spheroidal /
+toroidal) transforms in plain numpy on top of this module's nodes and P_n^m.
 
 Conventions: spectra are complex128 arrays in m-major triangular order
 idx(n,m) = m(2L+1-m)/2 + n; grids are float64 [nlat, nphi] with row i the
 colatitude theta_i increasing and column k the longitude 2 pi k / nphi.
 
 Parity status: every function here is pinned by tests/test_oracle_pins.py
-(closed forms, identities, scipy brute force, quadrature exactness).
+(closed forms, identities, scipy brute force, quadrature exactness), and
+those of vector.py by tests/test_oracle_vector_pins.py.
 """
 from __future__ import annotations
 
