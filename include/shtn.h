@@ -165,6 +165,30 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
  * not uploaded until then, calls return SHTN_ESTATE). */
 int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
 
+/* ---- vector (spheroidal / toroidal) transforms ----
+ *
+ * The paper names vector transforms but gives no formulas; the definition
+ * used here is the usual one.  A tangent field on the unit sphere with
+ * spheroidal potential S and toroidal potential T (spectra as for scalars,
+ * same plan, Im of the m = 0 coefficients ignored) is
+ *   V_theta = dS/dtheta - (1/sin theta) dT/dphi,
+ *   V_phi   = (1/sin theta) dS/dphi + dT/dtheta,
+ * on the plan's grid ([field][nlat][nphi] float64 per component).  The
+ * analysis is the projection on the basis fields of each (n, m), divided by
+ * their squared norm n(n+1): it inverts the synthesis for band-limited
+ * fields (nlat >= lmax + 1); degree 0 comes out 0 and Im of m = 0 as 0.
+ * Internally four scalar Legendre passes of modified spectra (or of
+ * weighted longitude coefficients) with the plan's algorithm, tiling and
+ * polar threshold, through sin(theta) dP_n^m/dtheta = n x P_n^m -
+ * c_n P_{n-1}^m.  work: shtn_vec_work_bytes(plan, nfields) bytes of device
+ * memory, 256-byte aligned.  Errors as for shtn_synth; outputs must not
+ * alias inputs or each other. */
+size_t shtn_vec_work_bytes(shtn_plan_t plan, int nfields);
+int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* Vtheta, double* Vphi, int nfields,
+                   void* work, void* stream);
+int shtn_vec_analys(shtn_plan_t plan, const double* Vtheta, const double* Vphi, double* S, double* T, int nfields,
+                    void* work, void* stream);
+
 /* ---- stored-P Legendre stage (Sec. 3.1, precomputed P_n^m) ----
  *
  * The second algorithm of the paper: P_n^m(x_i) stored for every order,

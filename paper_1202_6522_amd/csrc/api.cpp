@@ -74,26 +74,23 @@ int sp_args(const Plan& p, const double* in, double* out, int nfields, int adjoi
     return SHTN_OK;
 }
 
-// Legendre synthesis-type pass (synthesis or adjoint of the analysis) then c2r.
-int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream,
-            int adjoint)
+// Legendre synthesis-type stage (synthesis or adjoint of the analysis):
+// spectra Q -> longitude coefficients F.  Qs is the scratch of the rescaled
+// spectra (on-the-fly algorithm), nfields x nlm complex plus padding.
+int leg_to_f(const Plan& p, const double* Q, double* F, double* Qs, int nfields, int adjoint, void* stream)
 {
-    int rc = check_call(plan, Q, grid, nfields, work);
-    if (rc) return rc;
-    const Plan& p = *plan->p;
-    WorkLayout wl = work_layout(p, nfields);
-    double* F = (double*)work;
-    double* Qs = (double*)((char*)work + wl.f_bytes);
     int e;
     if (stored_synth(p.algo)) {
         PtabArgs a;
-        if ((rc = sp_args(p, Q, F, nfields, adjoint, a))) return rc;
+        int rc = sp_args(p, Q, F, nfields, adjoint, a);
+        if (rc) return rc;
         {
             ProfScope ps(PK_LEG_SYNTH, stream);
             e = launch_sp_synth(a, p.M, p.ptab.synth_rt, p.ptab.synth_ct, stream);
         }
         if (e) return hip_fail(e, "stored-P synthesis launch");
-    } else {
+        return SHTN_OK;
+    }
     {
         ProfScope ps(PK_PRESCALE, stream);
         e = launch_prescale(dplan(p), nullptr, nullptr, nullptr, Q, Qs, p.nlm, nfields, stream);
@@ -116,7 +113,11 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
         e = launch_legendre_synth(l, stream);
     }
     if (e) return hip_fail(e, "legendre synthesis launch");
-    }
+    return SHTN_OK;
+}
+
+FftLaunch fft_launch(const Plan& p, const double* in, double* out, int nfields, double scale)
+{
     FftLaunch f{};
     f.plans = dplan(p);
     f.rows_per_block = rows_per_block(p);
@@ -124,50 +125,53 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
     f.points = f.rows_per_block * p.K;
     f.grid_y = nfields;
     f.K = p.K;
-    f.in = F;
-    f.out = grid;
+    f.in = in;
+    f.out = out;
     f.nfields = nfields;
-    f.scale = 1.0;
-    {
-        ProfScope ps(PK_C2R, stream);
-        e = launch_c2r(f, stream);
-    }
-    if (e) return hip_fail(e, "c2r launch");
-    return SHTN_OK;
+    f.scale = scale;
+    return f;
 }
 
-// r2c then Legendre analysis-type pass (analysis or adjoint of the synthesis).
-int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work, void* stream,
-            int adjoint)
+// Longitude synthesis: F -> grid (c2r).
+int f_to_grid(const Plan& p, const double* F, double* grid, int nfields, void* stream)
 {
-    int rc = check_call(plan, grid, Q, nfields, work);
-    if (rc) return rc;
-    const Plan& p = *plan->p;
+    int e;
+    {
+        ProfScope ps(PK_C2R, stream);
+        e = launch_c2r(fft_launch(p, F, grid, nfields, 1.0), stream);
+    }
+    return e ? hip_fail(e, "c2r launch") : SHTN_OK;
+}
+
+// Longitude analysis: grid -> F (r2c), F scaled by `scale`.
+int grid_to_f(const Plan& p, const double* grid, double* F, int nfields, double scale, void* stream)
+{
+    int e;
+    {
+        ProfScope ps(PK_R2C, stream);
+        e = launch_r2c(fft_launch(p, grid, F, nfields, scale), stream);
+    }
+    return e ? hip_fail(e, "r2c launch") : SHTN_OK;
+}
+
+// Checks that the analysis-type stage can run with the plan's algorithm.
+int check_analys_stage(const Plan& p)
+{
     if (!stored_analys(p.algo) && p.npair > kMaxAnalysPairs)
         return fail(SHTN_EUNSUPPORTED, "on-the-fly analysis supports at most 4096 latitudes");
     if (stored_analys(p.algo) && !p.ptab.built)
         return fail(SHTN_ESTATE, "stored-P table not built for the current plan (shtn_ptable_build)");
-    double* F = (double*)work;
-    FftLaunch f{};
-    f.plans = dplan(p);
-    f.rows_per_block = rows_per_block(p);
-    f.nblocks = (p.nlat + f.rows_per_block - 1) / f.rows_per_block;
-    f.points = f.rows_per_block * p.K;
-    f.grid_y = nfields;
-    f.K = p.K;
-    f.in = grid;
-    f.out = F;
-    f.nfields = nfields;
-    f.scale = adjoint ? 1.0 : 2.0 * 3.14159265358979323846 / p.nphi;
+    return SHTN_OK;
+}
+
+// Legendre analysis-type stage (analysis or adjoint of the synthesis): F -> Q.
+int f_to_leg(const Plan& p, const double* F, double* Q, int nfields, int adjoint, void* stream)
+{
     int e;
-    {
-        ProfScope ps(PK_R2C, stream);
-        e = launch_r2c(f, stream);
-    }
-    if (e) return hip_fail(e, "r2c launch");
     if (stored_analys(p.algo)) {
         PtabArgs a;
-        if ((rc = sp_args(p, F, Q, nfields, adjoint, a))) return rc;
+        int rc = sp_args(p, F, Q, nfields, adjoint, a);
+        if (rc) return rc;
         const int nbr_max = ((p.L + 2) / 2 + 15) / 16;  // block rows of order 0, even parity
         {
             ProfScope ps(PK_LEG_ANALYS, stream);
@@ -194,6 +198,63 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
     }
     if (e) return hip_fail(e, "legendre analysis launch");
     return SHTN_OK;
+}
+
+// Workspace of the vector transforms of nfields fields: F of the four scalar
+// passes, F of the two components, the four spectra, the rescaled spectra.
+struct VecLayout {
+    size_t f4, fv, q4, qs, total;
+};
+VecLayout vec_layout(const Plan& p, int nfields)
+{
+    const size_t fs = (size_t)f_layout(p.M, p.nlat).size * 16;
+    VecLayout v;
+    v.f4 = 0;
+    v.fv = v.f4 + align256(4 * (size_t)nfields * fs);
+    v.q4 = v.fv + align256(2 * (size_t)nfields * fs);
+    v.qs = v.q4 + align256(4 * (size_t)nfields * p.nlm * 16);
+    v.total = v.qs + align256((4 * (size_t)nfields * p.nlm + kTablePad) * 16);
+    return v;
+}
+
+int check_vec_call(shtn_plan_t plan, const void* a, const void* b, const void* c, const void* d, int nfields,
+                   const void* work)
+{
+    if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (!plan->p->uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
+    if (!a || !b || !c || !d || !work) return fail(SHTN_EINVAL, "null data or workspace pointer");
+    if (nfields < 1) return fail(SHTN_EINVAL, "nfields must be >= 1");
+    if (c == a || c == b || d == a || d == b || c == d)
+        return fail(SHTN_EINVAL, "outputs must not alias inputs or each other");
+    return SHTN_OK;
+}
+
+// Legendre synthesis-type pass (synthesis or adjoint of the analysis) then c2r.
+int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream,
+            int adjoint)
+{
+    int rc = check_call(plan, Q, grid, nfields, work);
+    if (rc) return rc;
+    const Plan& p = *plan->p;
+    WorkLayout wl = work_layout(p, nfields);
+    double* F = (double*)work;
+    double* Qs = (double*)((char*)work + wl.f_bytes);
+    if ((rc = leg_to_f(p, Q, F, Qs, nfields, adjoint, stream))) return rc;
+    return f_to_grid(p, F, grid, nfields, stream);
+}
+
+// r2c then Legendre analysis-type pass (analysis or adjoint of the synthesis).
+int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work, void* stream,
+            int adjoint)
+{
+    int rc = check_call(plan, grid, Q, nfields, work);
+    if (rc) return rc;
+    const Plan& p = *plan->p;
+    if ((rc = check_analys_stage(p))) return rc;
+    double* F = (double*)work;
+    if ((rc = grid_to_f(p, grid, F, nfields, adjoint ? 1.0 : 2.0 * 3.14159265358979323846 / p.nphi, stream)))
+        return rc;
+    return f_to_leg(p, F, Q, nfields, adjoint, stream);
 }
 
 }  // namespace
@@ -458,6 +519,57 @@ int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold)
     p.uploaded = false;
     p.dev = nullptr;
     p.ptab.built = false;  // the table follows the lane starts
+    return SHTN_OK;
+}
+
+size_t shtn_vec_work_bytes(shtn_plan_t plan, int nfields)
+{
+    if (!plan || !plan->p || nfields < 1) return 0;
+    return vec_layout(*plan->p, nfields).total;
+}
+
+int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* Vt, double* Vp, int nfields,
+                   void* work, void* stream)
+{
+    int rc = check_vec_call(plan, S, T, Vt, Vp, nfields, work);
+    if (rc) return rc;
+    const Plan& p = *plan->p;
+    const VecLayout v = vec_layout(p, nfields);
+    char* w = (char*)work;
+    double* F4 = (double*)(w + v.f4);
+    double* Fv = (double*)(w + v.fv);
+    double* Q4 = (double*)(w + v.q4);
+    double* Qs = (double*)(w + v.qs);
+    const long fs = f_layout(p.M, p.nlat).size;
+    int e = launch_vec_spec_in(dplan(p), p.L, p.M, S, T, Q4, nfields, stream);
+    if (e) return hip_fail(e, "vector spectra launch");
+    if ((rc = leg_to_f(p, Q4, F4, Qs, 4 * nfields, 0, stream))) return rc;
+    if ((e = launch_vec_f_out(dplan(p), fs, F4, Fv, nfields, stream))) return hip_fail(e, "vector combine launch");
+    if ((rc = f_to_grid(p, Fv, Vt, nfields, stream))) return rc;
+    return f_to_grid(p, Fv + 2 * (size_t)nfields * fs, Vp, nfields, stream);
+}
+
+int shtn_vec_analys(shtn_plan_t plan, const double* Vt, const double* Vp, double* S, double* T, int nfields,
+                    void* work, void* stream)
+{
+    int rc = check_vec_call(plan, Vt, Vp, S, T, nfields, work);
+    if (rc) return rc;
+    const Plan& p = *plan->p;
+    if ((rc = check_analys_stage(p))) return rc;
+    const VecLayout v = vec_layout(p, nfields);
+    char* w = (char*)work;
+    double* F4 = (double*)(w + v.f4);
+    double* Fv = (double*)(w + v.fv);
+    double* Q4 = (double*)(w + v.q4);
+    const long fs = f_layout(p.M, p.nlat).size;
+    const double sc = 2.0 * 3.14159265358979323846 / p.nphi;
+    if ((rc = grid_to_f(p, Vt, Fv, nfields, sc, stream))) return rc;
+    if ((rc = grid_to_f(p, Vp, Fv + 2 * (size_t)nfields * fs, nfields, sc, stream))) return rc;
+    int e = launch_vec_f_in(dplan(p), fs, Fv, F4, nfields, stream);
+    if (e) return hip_fail(e, "vector weights launch");
+    if ((rc = f_to_leg(p, F4, Q4, 4 * nfields, 0, stream))) return rc;
+    if ((e = launch_vec_spec_out(dplan(p), p.L, p.M, Q4, S, T, nfields, stream)))
+        return hip_fail(e, "vector spectra launch");
     return SHTN_OK;
 }
 

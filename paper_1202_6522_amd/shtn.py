@@ -69,6 +69,9 @@ _SIGS = {
     "shtn_batch_replay": (_c.c_int, [_vp, _c.c_int, _vp]),
     "shtn_batch_tune": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c.c_int, _c.c_char_p,
                                    _c.POINTER(_c.c_float)]),
+    "shtn_vec_work_bytes": (_sz, [_vp, _c.c_int]),
+    "shtn_vec_synth": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_vec_analys": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_int, _vp, _vp]),
     "shtn_ptable_bytes": (_c.c_long, [_vp]),
     "shtn_ptable_build": (_c.c_int, [_vp, _vp, _sz, _vp]),
     "shtn_ptable_release": (_c.c_int, [_vp]),
@@ -216,6 +219,18 @@ def shtn_fp64_probe_tflops(stream):
     if v < 0:
         raise RuntimeError("shtn_fp64_probe_tflops: HIP error")
     return v
+
+
+def shtn_vec_work_bytes(h, nfields):
+    return load_library().shtn_vec_work_bytes(h, nfields)
+
+
+def shtn_vec_synth(h, S, T, Vt, Vp, nfields, work, stream):
+    return check(load_library().shtn_vec_synth(h, S, T, Vt, Vp, nfields, work, stream), "shtn_vec_synth")
+
+
+def shtn_vec_analys(h, Vt, Vp, S, T, nfields, work, stream):
+    return check(load_library().shtn_vec_analys(h, Vt, Vp, S, T, nfields, work, stream), "shtn_vec_analys")
 
 
 def shtn_ptable_bytes(h):
@@ -395,6 +410,7 @@ class Plan:
         self.nlm = int(shtn_nlm(self.handle))
         self.npair = (self.nlat + 1) // 2
         self._work = {}
+        self._vwork = {}
         self._dev = None
         self._ptab = None
         if polar_log2 is not None:
@@ -553,6 +569,46 @@ class Plan:
         fn(self.handle, g.data_ptr(), out.data_ptr(), nf, self.workspace(nf),
            _stream_ptr(torch, g.device))
         return out
+
+    def vec_workspace(self, nfields):
+        import torch
+        w = self._vwork.get(nfields)
+        if w is None:
+            nb = shtn_vec_work_bytes(self.handle, nfields)
+            w = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self._vwork[nfields] = w
+        return w.data_ptr() + ((-w.data_ptr()) % 256)
+
+    def vec_synth(self, S, T):
+        """Vector synthesis (spheroidal S, toroidal T spectra [..., nlm]
+        complex128) -> (V_theta, V_phi), each [..., nlat, nphi] float64."""
+        import torch
+        S = self._spec_in(S)
+        T = self._spec_in(T)
+        if S.shape != T.shape:
+            raise ValueError("S and T must have the same shape")
+        lead = S.shape[:-1]
+        nf = int(np.prod(lead)) if len(lead) else 1
+        vt = torch.empty(lead + (self.nlat, self.nphi), dtype=torch.float64, device=S.device)
+        vp = torch.empty_like(vt)
+        shtn_vec_synth(self.handle, S.data_ptr(), T.data_ptr(), vt.data_ptr(), vp.data_ptr(), nf,
+                       self.vec_workspace(nf), _stream_ptr(torch, S.device))
+        return vt, vp
+
+    def vec_analys(self, vt, vp):
+        """Vector analysis (V_theta, V_phi) [..., nlat, nphi] -> (S, T) [..., nlm]."""
+        import torch
+        vt = self._grid_in(vt)
+        vp = self._grid_in(vp)
+        if vt.shape != vp.shape:
+            raise ValueError("V_theta and V_phi must have the same shape")
+        lead = vt.shape[:-2]
+        nf = int(np.prod(lead)) if len(lead) else 1
+        S = torch.empty(lead + (self.nlm,), dtype=torch.complex128, device=vt.device)
+        T = torch.empty_like(S)
+        shtn_vec_analys(self.handle, vt.data_ptr(), vp.data_ptr(), S.data_ptr(), T.data_ptr(), nf,
+                        self.vec_workspace(nf), _stream_ptr(torch, vt.device))
+        return S, T
 
     def synth(self, Q):
         """Synthesis S Q: [..., nlm] complex128 -> [..., nlat, nphi] float64."""

@@ -1,0 +1,112 @@
+"""GPU parity of the vector (spheroidal / toroidal) transforms against the
+oracle (oracle/vector.py, pinned by tests/test_oracle_vector_pins.py).
+
+Bars: max |gpu - oracle| / max |oracle| over each output array <= 1e-11 for
+lmax <= 255 (the combination divides by sin(theta) >= 0.009 at lmax 255, so
+the scalar floor of ~1e-14 grows by at most ~100); at lmax 1023, where the
+numpy oracle is too large, the round trip to 1e-9 and the longitude terms
+against the GPU scalar synthesis differentiated by an FFT to 1e-9.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import vector as V
+from paper_1202_6522_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1202_6522_amd import shtn
+    shtn.load_library()
+    return torch.device("cuda:0")
+
+
+def make_plan(L, M, nlat, nphi, dev):
+    from paper_1202_6522_amd.shtn import Plan
+    return Plan(L, M, nlat, nphi, device=dev)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def spectra(L, M, nf, seed):
+    rng = np.random.default_rng(seed)
+    return inputs.draw_spectrum(rng, L, M, 1.0, nf), inputs.draw_spectrum(rng, L, M, 1.0, nf)
+
+
+SHAPES = [(12, 12, 13, 32), (20, 9, 22, 32), (63, 63, 64, 128), (100, 80, 101, 256), (255, 255, 256, 512),
+          (1, 1, 2, 4), (0, 0, 1, 2)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("algo", ["onthefly", "stored"])
+def test_vector_matches_oracle(shape, algo, dev):
+    L, M, nlat, nphi = shape
+    nf = 3
+    S, T = spectra(L, M, nf, sum(shape))
+    S[:, :L + 1] += 0.3j  # Im of m = 0 must be ignored
+    plan = make_plan(L, M, nlat, nphi, dev)
+    plan.set_algorithm(algo)
+    vt, vp = plan.vec_synth(to_dev(S, dev), to_dev(T, dev))
+    et, ep = V.vec_synth(S, T, L, M, nlat, nphi)
+    scale = max(np.abs(et).max(), np.abs(ep).max())
+    assert np.max(np.abs(vt.cpu().numpy() - et)) <= 1e-11 * scale
+    assert np.max(np.abs(vp.cpu().numpy() - ep)) <= 1e-11 * scale
+    # analysis of an independent non-band-limited pair of grids
+    rng = np.random.default_rng(7)
+    gt = rng.standard_normal((nf, nlat, nphi))
+    gp = rng.standard_normal((nf, nlat, nphi))
+    S2, T2 = plan.vec_analys(to_dev(gt, dev), to_dev(gp, dev))
+    eS, eT = V.vec_analys(gt, gp, L, M, nlat, nphi)
+    scale = max(np.abs(eS).max(), np.abs(eT).max())
+    assert np.max(np.abs(S2.cpu().numpy() - eS)) <= 1e-11 * scale
+    assert np.max(np.abs(T2.cpu().numpy() - eT)) <= 1e-11 * scale
+
+
+def test_vector_round_trip_and_longitude_terms_lmax1023(dev):
+    L, M, nlat, nphi = 1023, 1023, 1024, 2048
+    S, T = spectra(L, M, 1, 11)
+    n_all, m_all = inputs.degree_order(L, M)
+    S[:, n_all == 0] = 0
+    T[:, n_all == 0] = 0
+    S[:, m_all == 0] = S[:, m_all == 0].real
+    T[:, m_all == 0] = T[:, m_all == 0].real
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Sd, Td = to_dev(S, dev), to_dev(T, dev)
+    vt, vp = plan.vec_synth(Sd, Td)
+    S2, T2 = plan.vec_analys(vt, vp)
+    assert rel(S2.cpu().numpy(), S) <= 1e-9
+    assert rel(T2.cpu().numpy(), T) <= 1e-9
+    # V_phi of S alone is (1/sin) dS/dphi of the scalar synthesis
+    _, vp_s = plan.vec_synth(Sd, torch.zeros_like(Td))
+    g = plan.synth(Sd).cpu().numpy()[0]
+    k = np.fft.fftfreq(nphi, 1.0 / nphi)
+    dphi = np.real(np.fft.ifft(1j * k * np.fft.fft(g, axis=-1), axis=-1))
+    x, _ = oracle.gauss(nlat)
+    s = np.sqrt((1 - x) * (1 + x))[:, None]
+    assert rel(vp_s.cpu().numpy()[0], dphi / s) <= 1e-9
+
+
+def test_vector_many_fields_stored_matches_onthefly(dev):
+    L, M, nlat, nphi = 127, 127, 128, 256
+    S, T = spectra(L, M, 16, 5)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Sd, Td = to_dev(S, dev), to_dev(T, dev)
+    ref = plan.vec_synth(Sd, Td)
+    ref_a = plan.vec_analys(*ref)
+    plan.set_algorithm("stored")
+    got = plan.vec_synth(Sd, Td)
+    got_a = plan.vec_analys(*got)
+    for a, b in zip(got + got_a, ref + ref_a):
+        assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
