@@ -234,6 +234,54 @@ def autograd_config(dev, reps):
                       "table_mb": round(plan.ptable_bytes() / 1e6, 1)}}
 
 
+def vector_config(dev, reps):
+    """Vector (spheroidal / toroidal) transforms: one field at lmax 1023, and
+    16 fields at lmax 511 with the on-the-fly algorithm and after the runtime
+    choice for the 64-field scalar Legendre passes they make.  Synthesis +
+    analysis round trip, library calls on one stream."""
+    import numpy as np
+    import torch
+    from paper_1202_6522_amd import inputs
+    from paper_1202_6522_amd import shtn as S
+
+    def timed(plan, Sd, Td):
+        for _ in range(2):
+            plan.vec_analys(*plan.vec_synth(Sd, Td))
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = plan.vec_analys(*plan.vec_synth(Sd, Td))
+        e1.record()
+        torch.cuda.synchronize(dev)
+        return 1e3 * e0.elapsed_time(e1) / reps, out
+
+    res = {}
+    for L, nf in ((1023, 1), (511, 16)):
+        rng = np.random.default_rng(inputs.SEED_BASE + 5)
+        Sh = inputs.draw_spectrum(rng, L, L, 1.5, nf)
+        Th = inputs.draw_spectrum(rng, L, L, 1.5, nf)
+        n_all, m_all = inputs.degree_order(L, L)
+        for a in (Sh, Th):
+            a[:, n_all == 0] = 0
+            a[:, m_all == 0] = a[:, m_all == 0].real
+        plan = S.Plan(L, L, L + 1, 2 * (L + 1), device=dev)
+        Sd = torch.from_numpy(Sh).to(dev)
+        Td = torch.from_numpy(Th).to(dev)
+        us, (S2, T2) = timed(plan, Sd, Td)
+        err = float(max((S2 - Sd).abs().max(), (T2 - Td).abs().max()) / max(Sd.abs().max(), Td.abs().max()))
+        r = {"round_trip_us": round(us, 1), "vector_transforms_per_s": round(2 * nf / (us * 1e-6), 1),
+             "round_trip_rel_err": err}
+        if nf > 1:
+            tune = plan.tune_algorithm(4 * nf, reps=3)
+            us_t, _ = timed(plan, Sd, Td)
+            r["tuned"] = {"algorithm": tune["algorithm"], "round_trip_us": round(us_t, 1),
+                          "speedup": round(us / us_t, 3)}
+        res["lmax%d_fields%d" % (L, nf)] = r
+    return res
+
+
 def polar_curve(lmaxes, thresholds, reps):
     """Accuracy against work of the polar threshold (Sec. 3.1): for each lmax
     (nlat = lmax + 1, nphi = 2 (lmax + 1), one field, spectrum
@@ -443,6 +491,7 @@ def main():
     out["batch"] = batch_measure(dev, max(10, args.steps // 4))
     out["small_configs"] = small_configs(dev, max(20, args.steps))
     out["autograd"] = autograd_config(dev, max(5, args.steps // 20))
+    out["vector"] = vector_config(dev, max(5, args.steps // 20))
     probe = S.shtn_fp64_probe_tflops(stream)
     out["fp64_probe"] = {"tflops": round(probe, 2),
                          "legendre_frac_of_probe": {k: round(flops / (kern[k]["avg_us"] * 1e-6) / 1e12 / probe, 4)
