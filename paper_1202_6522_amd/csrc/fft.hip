@@ -247,6 +247,30 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
 {
     const int run = nrows < kFTile ? nrows : kFTile;  // rows per tile in the block
     const bool pow2 = (run & (run - 1)) == 0;
+    if (LOAD && pow2 && nrows <= kFTile && (row0 & (nrows - 1)) == 0) {
+        // The block is one aligned run inside a tile: entry e is order
+        // e >> lg, row e & (nrows - 1).  Every thread owns at most
+        // kFftPerThread entries (nrows (M+1) <= nrows K <= kFftPerThread
+        // threads), all loaded, from valid addresses, before any LDS write:
+        // one memory round trip instead of one per entry.
+        const int lg = __builtin_ctz(nrows);
+        const int n = nrows * (M + 1);
+        const long tb = (long)(row0 >> kFTileLg) * ts + (row0 & (kFTile - 1));
+        double2 v[kFftPerThread];
+#pragma unroll
+        for (int k = 0; k < kFftPerThread; k++) {
+            const int e = threadIdx.x + k * blockDim.x;
+            const int ec = e < n ? e : 0;
+            v[k] = *(const double2*)(Fin + 2 * (tb + ((long)(ec >> lg) << kFTileLg) + (ec & (nrows - 1))));
+        }
+#pragma unroll
+        for (int k = 0; k < kFftPerThread; k++) {
+            const int e = threadIdx.x + k * blockDim.x;
+            const int m = e >> lg, r = e & (nrows - 1);
+            if (e < n) buf[at((r << lgK) + m)] = make_double2(v[k].x, m == 0 ? 0.0 : v[k].y);
+        }
+        return;
+    }
     if (pow2 && (row0 & (run - 1)) == 0 && (nrows & (run - 1)) == 0) {
         const int lgrun = __builtin_ctz(run);
         const int per_tile = (M + 1) << lgrun;
@@ -362,14 +386,19 @@ __global__ void __launch_bounds__(kFftMaxThreads) k_r2c(FftArgs a)
     double* F = a.out + (a.f_off ? a.f_off[rb.field] : (long)rb.field * 2 * D.f_size);
     const int npts = rb.nrows << lgK;
     stage_twiddles(twl, tw, lgK);
+    // Straight-line loads from valid addresses, then LDS writes without
+    // branches (idx < 16 blockDim stays inside the point buffer; slots past
+    // npts are never read), so every load is issued before the first wait.
+    double2 v[kFftPerThread];
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
-        if (idx < npts) {
-            const int r = idx >> lgK, k = idx & (K - 1);
-            buf[at(idx)] = *(const double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k);
-        }
+        const int ic = idx < npts ? idx : 0;
+        const int r = ic >> lgK, k = ic & (K - 1);
+        v[e] = *(const double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k);
     }
+#pragma unroll
+    for (int e = 0; e < kFftPerThread; e++) buf[at(threadIdx.x + e * blockDim.x)] = v[e];
 
     __syncthreads();
     complex_fft(buf, twl, lgK, npts, -1);
