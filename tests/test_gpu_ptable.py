@@ -232,3 +232,22 @@ def test_autograd_through_stored(dev):
     plan.set_algorithm("stored")
     g_sp = grad()
     assert rel(g_sp, g_otf) <= 1e-12
+
+
+def test_stored_lmax2047_matches_onthefly(dev):
+    """lmax 2047 (the underflow guard matters, the table is 17.6 GB): the
+    stored kernels against the on-the-fly ones, which the long-double oracle
+    pins at this size."""
+    L, M, nlat, nphi = 2047, 2047, 2048, 4096
+    rng = np.random.default_rng(2047)
+    Q = to_dev(inputs.draw_spectrum(rng, L, M, 1.5, 2), dev)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    g_otf = plan.synth(Q)
+    a_otf = plan.analys(g_otf)
+    plan.set_algorithm("stored")
+    assert plan.ptable_bytes() > 17e9
+    g_sp = plan.synth(Q)
+    a_sp = plan.analys(g_otf)
+    assert rel(g_sp.cpu().numpy(), g_otf.cpu().numpy()) <= 1e-12
+    assert rel(a_sp.cpu().numpy(), a_otf.cpu().numpy()) <= 1e-12
+    plan.release_ptable()
