@@ -32,6 +32,20 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // m-major index of (n = m, m): the first coefficient of order m.
 __device__ __forceinline__ long order_base(int L, int m) { return (long)m * (2 * L + 1 - m) / 2 + m; }
 
+// XCD-aware placement: workgroup b of a launch runs on XCD b % kXcds.  The
+// nu units of order m all go to XCD m % kXcds, one after another in that
+// XCD's share of the launch (orders ascending, longest first), so they share
+// its L2 for the order's inputs.  False past the last order.
+__device__ __forceinline__ bool xcd_unit(int nu, int M, int& u, int& m)
+{
+    const int b = blockIdx.x;
+    const int slot = b / kXcds;
+    const int k = slot / nu;
+    u = slot - k * nu;
+    m = b % kXcds + kXcds * k;
+    return m <= M;
+}
+
 __device__ __forceinline__ int ptab_in_block(int jl, int pl)
 {
     return (jl >> 2) * 64 + (pl >> 2) * 16 + (jl & 3) * 4 + (pl & 3);
@@ -98,7 +112,9 @@ template <int RT, int CT>
 __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
 {
     const DevPlan& P = *a.plan;
-    const int pg = blockIdx.x, m = blockIdx.y;
+    const int npg = (a.npt + RT - 1) / RT;
+    int pg, m;
+    if (!xcd_unit(npg, P.M, pg, m)) return;
     const int L = P.L, nlat = P.nlat, npair = P.npair;
     const int npt = a.npt;
     const int nj = L - m + 1;
@@ -112,7 +128,7 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
     int fld[CT];
 #pragma unroll
     for (int c = 0; c < CT; c++) {
-        const int f = (blockIdx.z * CT + c) * 8 + (col >> 1);
+        const int f = (blockIdx.y * CT + c) * 8 + (col >> 1);
         fv[c] = f < a.nfields;
         fld[c] = f;
         qp[c] = a.in + (long)(fv[c] ? f : 0) * 2 * P.nlm + 2 * base + comp;
@@ -225,7 +241,8 @@ template <int JT, int CT>
 __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
 {
     const DevPlan& P = *a.plan;
-    const int g = blockIdx.x, m = blockIdx.y;
+    int g, m;
+    if (!xcd_unit(a.nu, P.M, g, m)) return;
     const int L = P.L, nlat = P.nlat, npair = P.npair;
     const int npt = a.npt;
     const int nj = L - m + 1;
@@ -241,7 +258,7 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
     int fld[CT];
 #pragma unroll
     for (int c = 0; c < CT; c++) {
-        const int f = (blockIdx.z * CT + c) * 8 + (col >> 1);
+        const int f = (blockIdx.y * CT + c) * 8 + (col >> 1);
         fv[c] = f < a.nfields;
         fld[c] = f;
         fp[c] = a.in + (long)(fv[c] ? f : 0) * 2 * P.f_size + comp;
@@ -346,7 +363,8 @@ static int launch_sp_synth_t(const PtabArgs& a, int M, void* stream)
 {
     const int npg = (a.npt + RT - 1) / RT;
     const int nfg = (a.nfields + 8 * CT - 1) / (8 * CT);
-    hipLaunchKernelGGL((k_sp_synth<RT, CT>), dim3(npg, M + 1, nfg), dim3(64), 0, (hipStream_t)stream, a);
+    const int nx = kXcds * ((M + kXcds) / kXcds) * npg;
+    hipLaunchKernelGGL((k_sp_synth<RT, CT>), dim3(nx, nfg), dim3(64), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
@@ -355,7 +373,10 @@ static int launch_sp_analys_t(const PtabArgs& a, int M, int nbr_max, void* strea
 {
     const int ng = (nbr_max + JT - 1) / JT;
     const int nfg = (a.nfields + 8 * CT - 1) / (8 * CT);
-    hipLaunchKernelGGL((k_sp_analys<JT, CT>), dim3(ng, M + 1, nfg), dim3(64), 0, (hipStream_t)stream, a);
+    const int nx = kXcds * ((M + kXcds) / kXcds) * ng;
+    PtabArgs b = a;
+    b.nu = ng;
+    hipLaunchKernelGGL((k_sp_analys<JT, CT>), dim3(nx, nfg), dim3(64), 0, (hipStream_t)stream, b);
     return (int)hipGetLastError();
 }
 

@@ -260,7 +260,7 @@ struct PtabArgs {
     int nfields;
     int adjoint;
     int npt;
-    int pad;
+    int nu;              // analysis: units (groups of block rows) per order, set by the launcher
 };
 int launch_ptable_build(const DevPlan* plan, const long* boff, double* tab, int npt, int M, void* stream);
 int launch_sp_synth(const PtabArgs& a, int M, int rt, int ct, void* stream);
