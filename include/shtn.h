@@ -188,6 +188,14 @@ int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* V
                    void* work, void* stream);
 int shtn_vec_analys(shtn_plan_t plan, const double* Vtheta, const double* Vphi, double* S, double* T, int nfields,
                     void* work, void* stream);
+/* Adjoints (transposes) of the two vector maps, for gradients: the adjoint of
+ * the synthesis takes grids to spectra, that of the analysis spectra to
+ * grids, with the scalar adjoints' conventions (gradient dRe + i dIm; degree
+ * 0 and Im of order 0 carry nothing).  Same workspace and errors. */
+int shtn_vec_synth_adj(shtn_plan_t plan, const double* Vtheta, const double* Vphi, double* S, double* T,
+                       int nfields, void* work, void* stream);
+int shtn_vec_analys_adj(shtn_plan_t plan, const double* S, const double* T, double* Vtheta, double* Vphi,
+                        int nfields, void* work, void* stream);
 
 /* ---- stored-P Legendre stage (Sec. 3.1, precomputed P_n^m) ----
  *

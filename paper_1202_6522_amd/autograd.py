@@ -5,7 +5,9 @@ SynthFn.backward(g) = S^T g (shtn_synth_adj) and AnalysFn.backward(h) = A^T h
 (shtn_analys_adj).  Gradients of complex spectra follow PyTorch's convention
 dL/dRe Q + i dL/dIm Q, which is exactly what the adjoint entry points return.
 Both maps are linear, so their backward passes are themselves differentiable
-through the opposite Function (double backward).
+through the opposite Function (double backward).  The vector transforms
+(spheroidal / toroidal) follow the same pattern with shtn_vec_synth_adj and
+shtn_vec_analys_adj.
 """
 from __future__ import annotations
 
@@ -54,6 +56,64 @@ class AnalysAdjFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         return AnalysFn.apply(g.contiguous(), ctx.plan), None
+
+
+class VecSynthFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, S, T, plan):
+        ctx.plan = plan
+        return plan.vec_synth(S, T)
+
+    @staticmethod
+    def backward(ctx, gt, gp):
+        gS, gT = VecSynthAdjFn.apply(gt.contiguous(), gp.contiguous(), ctx.plan)
+        return gS, gT, None
+
+
+class VecSynthAdjFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, gt, gp, plan):
+        ctx.plan = plan
+        return plan.vec_synth_adj(gt, gp)
+
+    @staticmethod
+    def backward(ctx, hS, hT):
+        gt, gp = VecSynthFn.apply(hS.contiguous(), hT.contiguous(), ctx.plan)
+        return gt, gp, None
+
+
+class VecAnalysFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, vt, vp, plan):
+        ctx.plan = plan
+        return plan.vec_analys(vt, vp)
+
+    @staticmethod
+    def backward(ctx, hS, hT):
+        gt, gp = VecAnalysAdjFn.apply(hS.contiguous(), hT.contiguous(), ctx.plan)
+        return gt, gp, None
+
+
+class VecAnalysAdjFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, hS, hT, plan):
+        ctx.plan = plan
+        return plan.vec_analys_adj(hS, hT)
+
+    @staticmethod
+    def backward(ctx, gt, gp):
+        hS, hT = VecAnalysFn.apply(gt.contiguous(), gp.contiguous(), ctx.plan)
+        return hS, hT, None
+
+
+def vec_synth(S, T, plan):
+    """Differentiable vector synthesis: spheroidal and toroidal spectra -> (V_theta, V_phi)."""
+    return VecSynthFn.apply(S, T, plan)
+
+
+def vec_analys(vt, vp, plan):
+    """Differentiable vector analysis: (V_theta, V_phi) -> spheroidal and toroidal spectra."""
+    return VecAnalysFn.apply(vt, vp, plan)
 
 
 def synth(Q, plan):

@@ -528,8 +528,14 @@ size_t shtn_vec_work_bytes(shtn_plan_t plan, int nfields)
     return vec_layout(*plan->p, nfields).total;
 }
 
-int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* Vt, double* Vp, int nfields,
-                   void* work, void* stream)
+}  // extern "C"
+
+namespace {
+// Vector synthesis-type sequence: spectra (S, T) -> grids (Vt, Vp).  adjoint:
+// the adjoint of the vector analysis ((S, T) / n(n+1), scalar stages in
+// their adjoint mode).
+int vec_to_grid(shtn_plan_t plan, const double* S, const double* T, double* Vt, double* Vp, int nfields,
+                void* work, void* stream, int adjoint)
 {
     int rc = check_vec_call(plan, S, T, Vt, Vp, nfields, work);
     if (rc) return rc;
@@ -541,16 +547,19 @@ int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* V
     double* Q4 = (double*)(w + v.q4);
     double* Qs = (double*)(w + v.qs);
     const long fs = f_layout(p.M, p.nlat).size;
-    int e = launch_vec_spec_in(dplan(p), p.L, p.M, S, T, Q4, nfields, stream);
+    int e = launch_vec_spec_in(dplan(p), p.L, p.M, S, T, Q4, nfields, adjoint, stream);
     if (e) return hip_fail(e, "vector spectra launch");
-    if ((rc = leg_to_f(p, Q4, F4, Qs, 4 * nfields, 0, stream))) return rc;
+    if ((rc = leg_to_f(p, Q4, F4, Qs, 4 * nfields, adjoint, stream))) return rc;
     if ((e = launch_vec_f_out(dplan(p), fs, F4, Fv, nfields, stream))) return hip_fail(e, "vector combine launch");
     if ((rc = f_to_grid(p, Fv, Vt, nfields, stream))) return rc;
     return f_to_grid(p, Fv + 2 * (size_t)nfields * fs, Vp, nfields, stream);
 }
 
-int shtn_vec_analys(shtn_plan_t plan, const double* Vt, const double* Vp, double* S, double* T, int nfields,
-                    void* work, void* stream)
+// Vector analysis-type sequence: grids (Vt, Vp) -> spectra (S, T).  adjoint:
+// the adjoint of the vector synthesis (unnormalised DFT, scalar stages in
+// their adjoint mode, no division by n(n+1)).
+int vec_to_spec(shtn_plan_t plan, const double* Vt, const double* Vp, double* S, double* T, int nfields,
+                void* work, void* stream, int adjoint)
 {
     int rc = check_vec_call(plan, Vt, Vp, S, T, nfields, work);
     if (rc) return rc;
@@ -562,15 +571,42 @@ int shtn_vec_analys(shtn_plan_t plan, const double* Vt, const double* Vp, double
     double* Fv = (double*)(w + v.fv);
     double* Q4 = (double*)(w + v.q4);
     const long fs = f_layout(p.M, p.nlat).size;
-    const double sc = 2.0 * 3.14159265358979323846 / p.nphi;
+    const double sc = adjoint ? 1.0 : 2.0 * 3.14159265358979323846 / p.nphi;
     if ((rc = grid_to_f(p, Vt, Fv, nfields, sc, stream))) return rc;
     if ((rc = grid_to_f(p, Vp, Fv + 2 * (size_t)nfields * fs, nfields, sc, stream))) return rc;
     int e = launch_vec_f_in(dplan(p), fs, Fv, F4, nfields, stream);
     if (e) return hip_fail(e, "vector weights launch");
-    if ((rc = f_to_leg(p, F4, Q4, 4 * nfields, 0, stream))) return rc;
-    if ((e = launch_vec_spec_out(dplan(p), p.L, p.M, Q4, S, T, nfields, stream)))
+    if ((rc = f_to_leg(p, F4, Q4, 4 * nfields, adjoint, stream))) return rc;
+    if ((e = launch_vec_spec_out(dplan(p), p.L, p.M, Q4, S, T, nfields, !adjoint, stream)))
         return hip_fail(e, "vector spectra launch");
     return SHTN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* Vt, double* Vp, int nfields,
+                   void* work, void* stream)
+{
+    return vec_to_grid(plan, S, T, Vt, Vp, nfields, work, stream, 0);
+}
+
+int shtn_vec_analys(shtn_plan_t plan, const double* Vt, const double* Vp, double* S, double* T, int nfields,
+                    void* work, void* stream)
+{
+    return vec_to_spec(plan, Vt, Vp, S, T, nfields, work, stream, 0);
+}
+
+int shtn_vec_synth_adj(shtn_plan_t plan, const double* Vt, const double* Vp, double* S, double* T, int nfields,
+                       void* work, void* stream)
+{
+    return vec_to_spec(plan, Vt, Vp, S, T, nfields, work, stream, 1);
+}
+
+int shtn_vec_analys_adj(shtn_plan_t plan, const double* S, const double* T, double* Vt, double* Vp, int nfields,
+                        void* work, void* stream)
+{
+    return vec_to_grid(plan, S, T, Vt, Vp, nfields, work, stream, 1);
 }
 
 long shtn_ptable_bytes(shtn_plan_t plan)

@@ -268,11 +268,11 @@ int launch_sp_analys(const PtabArgs& a, int M, int nbr_max, int jt, int ct, void
 // Vector transforms (vector.hip): spectral and latitude combinations around
 // the scalar stages.
 int launch_vec_spec_in(const DevPlan* plan, int L, int M, const double* S, const double* T, double* Q4, int nfields,
-                       void* stream);
+                       int nn, void* stream);
 int launch_vec_f_out(const DevPlan* plan, long f_size, const double* F4, double* Fv, int nfields, void* stream);
 int launch_vec_f_in(const DevPlan* plan, long f_size, const double* Fv, double* F4, int nfields, void* stream);
 int launch_vec_spec_out(const DevPlan* plan, int L, int M, const double* A4, double* S, double* T, int nfields,
-                        void* stream);
+                        int nn, void* stream);
 int launch_legendre_synth(const LegLaunch& a, void* stream);
 int launch_legendre_analys(const LegLaunch& a, void* stream);
 

@@ -17,6 +17,14 @@
 // the four weighted inputs formed by k_vec_f_in, the combination by
 // k_vec_spec_out.  sin(theta) is taken as sqrt((1-x)(1+x)) of the node x the
 // Legendre stage uses.
+//
+// Adjoints (the same kernels, `nn` selects the n(n+1) scaling): the
+// transpose of the synthesis is the analysis combination without the
+// division by n(n+1), fed by the scalar stages in their adjoint mode (unit
+// weights, c_m, unnormalised longitude DFT); the transpose of the analysis
+// forms the synthesis spectra from (S, T) / (n(n+1)) and runs the scalar
+// synthesis in its adjoint mode.  Degree 0 and Im of order 0 carry nothing
+// in either direction.
 #include <hip/hip_runtime.h>
 
 #include "shtn_internal.h"
@@ -31,10 +39,14 @@ __device__ __forceinline__ double vec_c(int n, int m)
     return n > m ? sqrt((2.0 * n + 1) * ((double)n * n - (double)m * m) / (2.0 * n - 1)) : 0.0;
 }
 
+// 1/(n(n+1)), 0 at degree 0.
+__device__ __forceinline__ double inv_nn(int n) { return n > 0 ? 1.0 / ((double)n * (n + 1.0)) : 0.0; }
+
 // Q4[4f + k] from S[f], T[f]: k = 0: n S, 1: c_{n+1} S_{n+1} + i m T,
-// 2: n T, 3: c_{n+1} T_{n+1} - i m S.  One thread per (degree, order, field).
+// 2: n T, 3: c_{n+1} T_{n+1} - i m S; with nn, S and T are first divided by
+// n(n+1) (adjoint of the analysis).  One thread per (degree, order, field).
 __global__ void __launch_bounds__(256) k_vec_spec_in(const DevPlan* plan, const double* S, const double* T,
-                                                      double* Q4, int nfields)
+                                                      double* Q4, int nfields, int nn)
 {
     const DevPlan& P = *plan;
     const int m = blockIdx.y, f = blockIdx.z;
@@ -44,13 +56,16 @@ __global__ void __launch_bounds__(256) k_vec_spec_in(const DevPlan* plan, const 
     const long i = vec_base(P.L, m) + (n - m);
     const double2* s2 = (const double2*)(S + 2 * (long)f * nlm);
     const double2* t2 = (const double2*)(T + 2 * (long)f * nlm);
-    const double2 s = s2[i], t = t2[i];
+    const double w0 = nn ? inv_nn(n) : 1.0;
+    double2 s = s2[i], t = t2[i];
+    s = make_double2(w0 * s.x, w0 * s.y);
+    t = make_double2(w0 * t.x, w0 * t.y);
     double2 sn = make_double2(0.0, 0.0), tn = sn;
     double c = 0.0;
     if (n < P.L) {
         sn = s2[i + 1];
         tn = t2[i + 1];
-        c = vec_c(n + 1, m);
+        c = vec_c(n + 1, m) * (nn ? inv_nn(n + 1) : 1.0);
     }
     const double dn = n, dm = m;
     double2* q = (double2*)(Q4 + 2 * (long)(4 * f) * nlm);
@@ -122,9 +137,11 @@ __global__ void __launch_bounds__(256) k_vec_f_in(const DevPlan* plan, const dou
     o[3 * fs] = make_double2(p.x * r, p.y * r);
 }
 
-// S, T from the four analyses A4[4f + k] (k: x Ft/s, Ft/s, x Fp/s, Fp/s).
+// S, T from the four analyses A4[4f + k] (k: x Ft/s, Ft/s, x Fp/s, Fp/s),
+// divided by n(n+1) when nn (the analysis), not otherwise (the adjoint of
+// the synthesis); 0 at degree 0.
 __global__ void __launch_bounds__(256) k_vec_spec_out(const DevPlan* plan, const double* A4, double* S, double* T,
-                                                       int nfields)
+                                                       int nfields, int nn)
 {
     const DevPlan& P = *plan;
     const int m = blockIdx.y, f = blockIdx.z;
@@ -140,7 +157,7 @@ __global__ void __launch_bounds__(256) k_vec_spec_out(const DevPlan* plan, const
         a4p = a[3 * nlm + i - 1];
     }
     const double c = vec_c(n, m), dn = n, dm = m;
-    const double inv = n > 0 ? 1.0 / (dn * (dn + 1.0)) : 0.0;
+    const double inv = n == 0 ? 0.0 : (nn ? inv_nn(n) : 1.0);
     // n A1 - c A2(n-1) - i m A4 ;  i m A2 + n A3 - c A4(n-1)
     double2 sv = make_double2((dn * a1.x - c * a2p.x + dm * a4.y) * inv, (dn * a1.y - c * a2p.y - dm * a4.x) * inv);
     double2 tv = make_double2((-dm * a2.y + dn * a3.x - c * a4p.x) * inv, (dm * a2.x + dn * a3.y - c * a4p.y) * inv);
@@ -153,10 +170,10 @@ __global__ void __launch_bounds__(256) k_vec_spec_out(const DevPlan* plan, const
 }
 
 int launch_vec_spec_in(const DevPlan* plan, int L, int M, const double* S, const double* T, double* Q4, int nfields,
-                       void* stream)
+                       int nn, void* stream)
 {
     hipLaunchKernelGGL(k_vec_spec_in, dim3((L + 256) / 256, M + 1, nfields), dim3(256), 0, (hipStream_t)stream,
-                       plan, S, T, Q4, nfields);
+                       plan, S, T, Q4, nfields, nn);
     return (int)hipGetLastError();
 }
 
@@ -175,10 +192,10 @@ int launch_vec_f_in(const DevPlan* plan, long f_size, const double* Fv, double* 
 }
 
 int launch_vec_spec_out(const DevPlan* plan, int L, int M, const double* A4, double* S, double* T, int nfields,
-                        void* stream)
+                        int nn, void* stream)
 {
     hipLaunchKernelGGL(k_vec_spec_out, dim3((L + 256) / 256, M + 1, nfields), dim3(256), 0, (hipStream_t)stream,
-                       plan, A4, S, T, nfields);
+                       plan, A4, S, T, nfields, nn);
     return (int)hipGetLastError();
 }
 

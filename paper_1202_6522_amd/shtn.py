@@ -72,6 +72,8 @@ _SIGS = {
     "shtn_vec_work_bytes": (_sz, [_vp, _c.c_int]),
     "shtn_vec_synth": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_int, _vp, _vp]),
     "shtn_vec_analys": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_vec_synth_adj": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_vec_analys_adj": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_int, _vp, _vp]),
     "shtn_ptable_bytes": (_c.c_long, [_vp]),
     "shtn_ptable_build": (_c.c_int, [_vp, _vp, _sz, _vp]),
     "shtn_ptable_release": (_c.c_int, [_vp]),
@@ -231,6 +233,14 @@ def shtn_vec_synth(h, S, T, Vt, Vp, nfields, work, stream):
 
 def shtn_vec_analys(h, Vt, Vp, S, T, nfields, work, stream):
     return check(load_library().shtn_vec_analys(h, Vt, Vp, S, T, nfields, work, stream), "shtn_vec_analys")
+
+
+def shtn_vec_synth_adj(h, Vt, Vp, S, T, nfields, work, stream):
+    return check(load_library().shtn_vec_synth_adj(h, Vt, Vp, S, T, nfields, work, stream), "shtn_vec_synth_adj")
+
+
+def shtn_vec_analys_adj(h, S, T, Vt, Vp, nfields, work, stream):
+    return check(load_library().shtn_vec_analys_adj(h, S, T, Vt, Vp, nfields, work, stream), "shtn_vec_analys_adj")
 
 
 def shtn_ptable_bytes(h):
@@ -582,6 +592,21 @@ class Plan:
     def vec_synth(self, S, T):
         """Vector synthesis (spheroidal S, toroidal T spectra [..., nlm]
         complex128) -> (V_theta, V_phi), each [..., nlat, nphi] float64."""
+        return self._vec_to_grid(shtn_vec_synth, S, T)
+
+    def vec_analys_adj(self, S, T):
+        """Adjoint of the vector analysis: spectra -> grids."""
+        return self._vec_to_grid(shtn_vec_analys_adj, S, T)
+
+    def vec_analys(self, vt, vp):
+        """Vector analysis (V_theta, V_phi) [..., nlat, nphi] -> (S, T) [..., nlm]."""
+        return self._vec_to_spec(shtn_vec_analys, vt, vp)
+
+    def vec_synth_adj(self, vt, vp):
+        """Adjoint of the vector synthesis: grids -> spectra."""
+        return self._vec_to_spec(shtn_vec_synth_adj, vt, vp)
+
+    def _vec_to_grid(self, fn, S, T):
         import torch
         S = self._spec_in(S)
         T = self._spec_in(T)
@@ -591,12 +616,11 @@ class Plan:
         nf = int(np.prod(lead)) if len(lead) else 1
         vt = torch.empty(lead + (self.nlat, self.nphi), dtype=torch.float64, device=S.device)
         vp = torch.empty_like(vt)
-        shtn_vec_synth(self.handle, S.data_ptr(), T.data_ptr(), vt.data_ptr(), vp.data_ptr(), nf,
-                       self.vec_workspace(nf), _stream_ptr(torch, S.device))
+        fn(self.handle, S.data_ptr(), T.data_ptr(), vt.data_ptr(), vp.data_ptr(), nf,
+           self.vec_workspace(nf), _stream_ptr(torch, S.device))
         return vt, vp
 
-    def vec_analys(self, vt, vp):
-        """Vector analysis (V_theta, V_phi) [..., nlat, nphi] -> (S, T) [..., nlm]."""
+    def _vec_to_spec(self, fn, vt, vp):
         import torch
         vt = self._grid_in(vt)
         vp = self._grid_in(vp)
@@ -606,8 +630,8 @@ class Plan:
         nf = int(np.prod(lead)) if len(lead) else 1
         S = torch.empty(lead + (self.nlm,), dtype=torch.complex128, device=vt.device)
         T = torch.empty_like(S)
-        shtn_vec_analys(self.handle, vt.data_ptr(), vp.data_ptr(), S.data_ptr(), T.data_ptr(), nf,
-                        self.vec_workspace(nf), _stream_ptr(torch, vt.device))
+        fn(self.handle, vt.data_ptr(), vp.data_ptr(), S.data_ptr(), T.data_ptr(), nf,
+           self.vec_workspace(nf), _stream_ptr(torch, vt.device))
         return S, T
 
     def synth(self, Q):

@@ -110,3 +110,71 @@ def test_vector_many_fields_stored_matches_onthefly(dev):
     got_a = plan.vec_analys(*got)
     for a, b in zip(got + got_a, ref + ref_a):
         assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+
+
+def _dot_spec(a, b):
+    """Real inner product of complex spectra (the gradient convention dRe + i dIm)."""
+    return float(np.sum(a.real * b.real + a.imag * b.imag))
+
+
+@pytest.mark.parametrize("shape", [(20, 9, 22, 32), (63, 63, 64, 128), (40, 40, 41, 128)])
+@pytest.mark.parametrize("algo", ["onthefly", "stored"])
+def test_vector_adjoint_dot_products(shape, algo, dev):
+    L, M, nlat, nphi = shape
+    rng = np.random.default_rng(sum(shape) + 1)
+    S, T = spectra(L, M, 2, sum(shape) + 2)
+    gt = rng.standard_normal((2, nlat, nphi))
+    gp = rng.standard_normal((2, nlat, nphi))
+    plan = make_plan(L, M, nlat, nphi, dev)
+    plan.set_algorithm(algo)
+    Sd, Td, gtd, gpd = (to_dev(a, dev) for a in (S, T, gt, gp))
+    vt, vp = (a.cpu().numpy() for a in plan.vec_synth(Sd, Td))
+    aS, aT = (a.cpu().numpy() for a in plan.vec_synth_adj(gtd, gpd))
+    lhs = np.sum(gt * vt + gp * vp)
+    rhs = _dot_spec(S, aS) + _dot_spec(T, aT)
+    assert abs(lhs - rhs) <= 1e-12 * (np.sum(np.abs(gt * vt)) + np.sum(np.abs(gp * vp)))
+    hS, hT = (a.cpu().numpy() for a in plan.vec_analys(gtd, gpd))
+    bt, bp = (a.cpu().numpy() for a in plan.vec_analys_adj(Sd, Td))
+    lhs = _dot_spec(S, hS) + _dot_spec(T, hT)
+    rhs = np.sum(gt * bt + gp * bp)
+    assert abs(lhs - rhs) <= 1e-12 * (np.sum(np.abs(gt * bt)) + np.sum(np.abs(gp * bp)))
+
+
+def test_vector_autograd_finite_differences(dev):
+    from paper_1202_6522_amd.autograd import vec_analys, vec_synth
+    L, M, nlat, nphi = 31, 31, 32, 64
+    S0, T0 = spectra(L, M, 1, 77)
+    rng = np.random.default_rng(78)
+    tt, tp = rng.standard_normal((2, 1, nlat, nphi))
+    plan = make_plan(L, M, nlat, nphi, dev)
+    Sd = to_dev(S0, dev).requires_grad_(True)
+    Td = to_dev(T0, dev).requires_grad_(True)
+    ttd, tpd = to_dev(tt, dev), to_dev(tp, dev)
+
+    def loss(S, T):
+        vt, vp = vec_synth(S, T, plan)
+        aS, aT = vec_analys(vt * 0.5, vp, plan)  # a second differentiable map in the chain
+        return ((vt - ttd) ** 2).sum() + ((vp - tpd) ** 2).sum() + (aS.abs() ** 2).sum() + (aT.real ** 3).sum()
+
+    L0 = loss(Sd, Td)
+    L0.backward()
+    gS, gT = Sd.grad.cpu().numpy(), Td.grad.cpu().numpy()
+    n_all, m_all = inputs.degree_order(L, M)
+    h = 1e-6
+    idx = [i for i in rng.choice(len(n_all), 12, replace=False) if n_all[i] > 0]
+    with torch.no_grad():
+        for which, g in (("S", gS), ("T", gT)):
+            for i in idx:
+                for part in ((1.0, "re"), (1j, "im")):
+                    if m_all[i] == 0 and part[1] == "im":
+                        continue
+                    e = np.zeros_like(S0)
+                    e[0, i] = part[0] * h
+                    ed = to_dev(e, dev)
+                    if which == "S":
+                        lp, lm = loss(Sd + ed, Td), loss(Sd - ed, Td)
+                    else:
+                        lp, lm = loss(Sd, Td + ed), loss(Sd, Td - ed)
+                    fd = float(lp - lm) / (2 * h)
+                    an = g[0, i].real if part[1] == "re" else g[0, i].imag
+                    assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (which, i, part[1], fd, an)
