@@ -5,6 +5,13 @@
  * pseudo-spectral numerical simulations", arXiv 1202.6522.  Section numbers
  * below refer to that paper.
  *
+ * Contents: plans (Gauss grid, recurrence tables, lane starts); the four
+ * scalar transforms (synthesis, analysis and their adjoints) with the
+ * Legendre stage recomputing P_n^m on the fly (Sec. 3.2) or reading a stored
+ * table (Sec. 3.1), chosen per pass type by runtime tuning (Sec. 3.2); vector
+ * (spheroidal / toroidal) transforms and their adjoints; batches of fields
+ * of different truncations with graph capture and an autotuner; profiling.
+ *
  * Conventions shared by every entry point
  * ---------------------------------------
  *  Truncation: degree n <= lmax, order 0 <= m <= min(n, mmax).
