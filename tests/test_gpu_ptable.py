@@ -251,3 +251,35 @@ def test_stored_lmax2047_matches_onthefly(dev):
     assert rel(g_sp.cpu().numpy(), g_otf.cpu().numpy()) <= 1e-12
     assert rel(a_sp.cpu().numpy(), a_otf.cpu().numpy()) <= 1e-12
     plan.release_ptable()
+
+
+def test_stored_error_paths(dev):
+    """Short or misaligned table buffers are refused; a table made stale by a
+    new polar threshold (set through the C call, without the binding's
+    rebuild) makes the stored passes return SHTN_ESTATE until rebuilt."""
+    import ctypes
+    from paper_1202_6522_amd import shtn as S
+    lib = S.load_library()
+    L, M, nlat, nphi = 31, 31, 32, 64
+    plan = make_plan(L, M, nlat, nphi, dev)
+    nb = plan.ptable_bytes()
+    buf = torch.empty(nb + 512, dtype=torch.uint8, device=dev)
+    base = buf.data_ptr() + ((-buf.data_ptr()) % 256)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    assert lib.shtn_ptable_build(plan.handle, ctypes.c_void_p(base), nb - 8, ctypes.c_void_p(stream)) == S.SHTN_EINVAL
+    assert lib.shtn_ptable_build(plan.handle, ctypes.c_void_p(base + 8), nb, ctypes.c_void_p(stream)) == S.SHTN_EINVAL
+    assert lib.shtn_plan_set_algorithm(plan.handle, S.SHTN_ALGO_STORED) == S.SHTN_ESTATE
+    S.shtn_ptable_build(plan.handle, base, nb, stream)
+    S.shtn_plan_set_algorithm(plan.handle, S.SHTN_ALGO_STORED)
+    rng = np.random.default_rng(1)
+    Q = to_dev(inputs.draw_spectrum(rng, L, M, 1.0, 1), dev)
+    g_ok = plan.synth(Q)
+    S.shtn_plan_set_polar(plan.handle, -40)
+    plan._upload()
+    grid = torch.empty(1, nlat, nphi, dtype=torch.float64, device=dev)
+    rc = lib.shtn_synth(plan.handle, ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(grid.data_ptr()), 1,
+                        ctypes.c_void_p(plan.workspace(1)), ctypes.c_void_p(stream))
+    assert rc == S.SHTN_ESTATE
+    S.shtn_ptable_build(plan.handle, base, nb, stream)
+    assert rel(plan.synth(Q).cpu().numpy(), g_ok.cpu().numpy()) <= 1e-12
+    torch.cuda.synchronize(dev)
