@@ -316,6 +316,16 @@ int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpac
 int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int fw, int m_pairing, int analys_merge);
 /* tiling4 = {synth_lp, fw, m_pairing, analys_merge}. */
 int shtn_batch_get_tiling(shtn_batch_t batch, int* tiling4);
+/* Legendre algorithm of the batch: SHTN_ALGO_ONTHEFLY (default) or
+ * SHTN_ALGO_STORED, with which the fields of every plan that has a current
+ * stored-P table (shtn_ptable_build) run the stored kernels in both
+ * directions (launched per plan, the fields addressed through the batch's
+ * offset tables) and the other fields the on-the-fly kernels.  The plans'
+ * tables must stay built while the batch uses them (calls return
+ * SHTN_ESTATE otherwise).  Re-upload afterwards.  The tuner
+ * (shtn_batch_tune) tries both when any plan has a table. */
+int shtn_batch_set_algorithm(shtn_batch_t batch, int algo);
+int shtn_batch_get_algorithm(shtn_batch_t batch);
 /* Captures the launch sequence of one direction (which = 0 synthesis
  * in -> out, 1 analysis) into a hipGraph held by the batch, on a private
  * stream, for these exact buffers.  Replaying it (shtn_batch_replay) on any
@@ -325,7 +335,8 @@ int shtn_batch_capture(shtn_batch_t batch, int which, const double* in, double* 
 int shtn_batch_replay(shtn_batch_t batch, int which, void* stream);
 /* Autotuner: times a synthesis (Qpacked -> gridpacked) plus analysis
  * (gridpacked -> Qout) round trip of graph replays for every tiling
- * (synth_lp 1|2, fw 1|2|4, m_pairing 0|1, analys_merge 0|1; reps replays each,
+ * (synth_lp 1|2, fw 1|2|4, m_pairing 0|1, analys_merge 0|1, and both batch
+ * algorithms when a plan has a stored-P table; reps replays each,
  * default 10 when reps < 1), keeps the fastest, re-uploads and leaves both
  * graphs captured for these buffers.  Blocks until done.  With cache_path
  * (may be NULL), a tiling stored there for the same list of field shapes is

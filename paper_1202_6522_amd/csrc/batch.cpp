@@ -14,6 +14,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -35,6 +36,7 @@ struct BatchTiling {
     int fw = 1;            // fields per wave (fields of the same plan)
     int m_pairing = 0;     // synthesis unit order: 1 = long and short units alternate
     int analys_merge = 0;  // analysis: 1 = a single launch at the largest pairs-per-lane class
+    int stored = 0;        // 1 = plans with a current stored-P table use the stored kernels
 };
 
 struct AnalysClass {
@@ -66,6 +68,8 @@ struct shtn_batch_s {
     BatchTiling tiling;
     // unit tables of the current tiling
     std::vector<int> synth_units, analys_units, rowblocks;
+    // plans whose slots run the stored-P kernels: {plan index, first slot, slots}
+    std::vector<std::array<int, 3>> stored_runs;
     std::vector<AnalysClass> classes;
     int synth_wpg = 1;
     int fft_points = 1;  // most complex points in one FFT row block
@@ -108,6 +112,14 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
         r.first = std::min(r.first, s);
         r.second = std::max(r.second, s + 1);
     }
+    // plans served by the stored-P kernels: no on-the-fly units for their slots
+    std::vector<char> stored(b.plans.size(), 0);
+    b.stored_runs.clear();
+    for (size_t pi = 0; pi < b.plans.size(); pi++)
+        if (t.stored && b.plans[pi]->ptab.built && range[pi].first < range[pi].second) {
+            stored[pi] = 1;
+            b.stored_runs.push_back({(int)pi, range[pi].first, range[pi].second - range[pi].first});
+        }
 
     // ---- synthesis units ----
     struct SU {
@@ -117,6 +129,7 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
     std::vector<SU> su;
     int maxblk = 1;
     for (size_t pi = 0; pi < b.plans.size(); pi++) {
+        if (stored[pi]) continue;
         const Plan& p = *b.plans[pi];
         const int blk = 64 * t.synth_lp;
         const int nblk = (p.npair + blk - 1) / blk;
@@ -180,6 +193,7 @@ void build_tables(shtn_batch_s& b, const BatchTiling& t)
         std::vector<SU> au;
         for (size_t pi = 0; pi < b.plans.size(); pi++) {
             const Plan& p = *b.plans[pi];
+            if (stored[pi]) continue;
             if (!t.analys_merge && analys_class(p.npair) != cl) continue;
             for (int fg = range[pi].first; fg < range[pi].second; fg += fw) {
                 const int nf = std::min(fw, range[pi].second - fg);
@@ -258,6 +272,33 @@ int check_batch(const shtn_batch_s* b, const void* in, const void* out, const vo
     if (in == out) return set_error(SHTN_EINVAL, "input and output must not alias");
     for (auto* p : b->plans)
         if (!p->uploaded) return set_error(SHTN_ESTATE, "a plan of the batch is no longer uploaded");
+    for (const auto& r : b->stored_runs)
+        if (!b->plans[r[0]]->ptab.built)
+            return set_error(SHTN_ESTATE, "a stored-P table of the batch is no longer current (set the algorithm again)");
+    return SHTN_OK;
+}
+
+// Stored-P launches of the batch's stored plans (fields addressed through
+// the per-slot offset tables).
+int run_stored(const shtn_batch_s& b, const double* in, double* out, int synth, void* stream)
+{
+    const DevPlan* plans = dev_at<const DevPlan>(b, b.off_plans);
+    for (const auto& r : b.stored_runs) {
+        const Plan& p = *b.plans[r[0]];
+        PtabArgs a{plans + r[0], (const long*)p.ptab.dev,
+                   (const double*)((const char*)p.ptab.dev + p.ptab.head_bytes), in, out, r[2], 0, p.ptab.npt, 0};
+        a.q_off = dev_at<const long>(b, b.off_q) + r[1];
+        a.f_off = dev_at<const long>(b, b.off_f) + r[1];
+        int e;
+        if (synth) {
+            ProfScope ps(PK_LEG_SYNTH, stream);
+            e = launch_sp_synth(a, p.M, p.ptab.synth_rt, p.ptab.synth_ct, stream);
+        } else {
+            ProfScope ps(PK_LEG_ANALYS, stream);
+            e = launch_sp_analys(a, p.M, ((p.L + 2) / 2 + 15) / 16, p.ptab.analys_jt, p.ptab.analys_ct, stream);
+        }
+        if (e) return hip_error(e, "batch stored-P launch");
+    }
     return SHTN_OK;
 }
 
@@ -293,6 +334,8 @@ int run_synth(const shtn_batch_s& b, const double* Q, double* grid, void* work, 
         e = launch_legendre_synth(l, stream);
     }
     if (e) return hip_error(e, "batch legendre synthesis launch");
+    int rc = run_stored(b, Q, F, 1, stream);
+    if (rc) return rc;
     FftLaunch f{};
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
@@ -359,7 +402,7 @@ int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work,
         }
         if (e) return hip_error(e, "batch legendre analysis launch");
     }
-    return SHTN_OK;
+    return run_stored(b, F, Q, 0, stream);
 }
 
 int upload(shtn_batch_s& b, void* dev_buf, void* stream)
@@ -439,6 +482,7 @@ bool cache_lookup(const char* path, const std::string& key, BatchTiling& t)
         std::istringstream is(line.substr(key.size() + 1));
         BatchTiling c;
         if (is >> c.synth_lp >> c.fw >> c.m_pairing >> c.analys_merge) {
+            if (!(is >> c.stored)) c.stored = 0;
             t = c;
             return true;
         }
@@ -455,6 +499,7 @@ int validate(const BatchTiling& t)
     if (t.m_pairing != 0 && t.m_pairing != 1) return set_error(SHTN_EINVAL, "m_pairing must be 0 or 1");
     if (t.analys_merge != 0 && t.analys_merge != 1)
         return set_error(SHTN_EINVAL, "analys_merge must be 0 or 1");
+    if (t.stored != 0 && t.stored != 1) return set_error(SHTN_EINVAL, "stored must be 0 or 1");
     return SHTN_OK;
 }
 
@@ -591,7 +636,7 @@ int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpac
 int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int fw, int m_pairing, int analys_merge)
 {
     if (!batch) return set_error(SHTN_EINVAL, "null batch");
-    BatchTiling t{synth_lp, fw, m_pairing, analys_merge};
+    BatchTiling t{synth_lp, fw, m_pairing, analys_merge, batch->tiling.stored};
     int rc = validate(t);
     if (rc) return rc;
     try {
@@ -603,6 +648,30 @@ int shtn_batch_set_tiling(shtn_batch_t batch, int synth_lp, int fw, int m_pairin
     batch->uploaded = false;  // the unit tables changed: upload again
     drop_graphs(*batch);
     return SHTN_OK;
+}
+
+int shtn_batch_set_algorithm(shtn_batch_t batch, int algo)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    if (algo != SHTN_ALGO_ONTHEFLY && algo != SHTN_ALGO_STORED)
+        return set_error(SHTN_EINVAL, "batch algorithm must be SHTN_ALGO_ONTHEFLY or SHTN_ALGO_STORED");
+    BatchTiling t = batch->tiling;
+    t.stored = algo == SHTN_ALGO_STORED;
+    try {
+        batch->tiling = t;
+        build_tables(*batch, t);
+    } catch (const std::bad_alloc&) {
+        return set_error(SHTN_ENOMEM, "out of host memory");
+    }
+    batch->uploaded = false;
+    drop_graphs(*batch);
+    return SHTN_OK;
+}
+
+int shtn_batch_get_algorithm(shtn_batch_t batch)
+{
+    if (!batch) return set_error(SHTN_EINVAL, "null batch");
+    return batch->tiling.stored ? SHTN_ALGO_STORED : SHTN_ALGO_ONTHEFLY;
 }
 
 int shtn_batch_get_tiling(shtn_batch_t batch, int* tiling4)
@@ -649,11 +718,14 @@ int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacke
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return hip_error((int)hipGetLastError(), "tuner events");
+        bool any_table = false;
+        for (auto* p : b.plans) any_table = any_table || p->ptab.built;
         std::vector<BatchTiling> cands;
-        for (int lp : {1, 2})
-            for (int fw : {1, 2, 4})
-                for (int mp : {0, 1})
-                    for (int merge : {0, 1}) cands.push_back(BatchTiling{lp, fw, mp, merge});
+        for (int st = 0; st <= (any_table ? 1 : 0); st++)
+            for (int lp : {1, 2})
+                for (int fw : {1, 2, 4})
+                    for (int mp : {0, 1})
+                        for (int merge : {0, 1}) cands.push_back(BatchTiling{lp, fw, mp, merge, st});
         for (const BatchTiling& t : cands) {
             build_tables(b, t);
             b.tiling = t;
@@ -689,7 +761,7 @@ int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacke
         if (cache_path) {
             std::ofstream out(cache_path, std::ios::app);
             out << key << '|' << best.synth_lp << ' ' << best.fw << ' ' << best.m_pairing << ' '
-                << best.analys_merge << '\n';
+                << best.analys_merge << ' ' << best.stored << '\n';
         }
     }
     build_tables(b, best);

@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
         const int f = (blockIdx.y * CT + c) * 8 + (col >> 1);
         fv[c] = f < a.nfields;
         fld[c] = f;
-        qp[c] = a.in + (long)(fv[c] ? f : 0) * 2 * P.nlm + 2 * base + comp;
+        const int fc = fv[c] ? f : 0;
+        qp[c] = a.in + (a.q_off ? a.q_off[fc] : (long)fc * 2 * P.nlm) + 2 * base + comp;
     }
     // pair tiles past the last one read tile pg RT (always present) and
     // feed zeros
@@ -221,7 +222,7 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
 #pragma unroll
             for (int c = 0; c < CT; c++) {
                 if (!fv[c]) continue;
-                double* F = a.out + (long)fld[c] * 2 * P.f_size + comp;
+                double* F = a.out + (a.f_off ? a.f_off[fld[c]] : (long)fld[c] * 2 * P.f_size) + comp;
                 const double e = acc[0][r][c][i], o = acc[1][r][c][i];
                 F[2 * f_index(P.f_ts, m, pair)] = sc * (e + o);
                 if (is != pair) F[2 * f_index(P.f_ts, m, is)] = sc * (e - o);
@@ -261,7 +262,8 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
         const int f = (blockIdx.y * CT + c) * 8 + (col >> 1);
         fv[c] = f < a.nfields;
         fld[c] = f;
-        fp[c] = a.in + (long)(fv[c] ? f : 0) * 2 * P.f_size + comp;
+        const int fc = fv[c] ? f : 0;
+        fp[c] = a.in + (a.f_off ? a.f_off[fc] : (long)fc * 2 * P.f_size) + comp;
     }
     bool rv[2][JT];
     const double* tq[2][JT];
@@ -343,7 +345,7 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
                 for (int c = 0; c < CT; c++) {
                     if (!fv[c]) continue;
                     const double v = (m == 0 && comp == 1) ? 0.0 : cm * acc[q][t][c][i];
-                    a.out[(long)fld[c] * 2 * P.nlm + 2 * (base + j) + comp] = v;
+                    a.out[(a.q_off ? a.q_off[fld[c]] : (long)fld[c] * 2 * P.nlm) + 2 * (base + j) + comp] = v;
                 }
             }
 }

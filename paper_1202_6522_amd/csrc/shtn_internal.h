@@ -261,6 +261,8 @@ struct PtabArgs {
     int adjoint;
     int npt;
     int nu;              // analysis: units (groups of block rows) per order, set by the launcher
+    const long* q_off = nullptr;  // per-field spectrum offset (doubles), or null (f * 2 nlm)
+    const long* f_off = nullptr;  // per-field F offset (doubles), or null (f * 2 f_size)
 };
 int launch_ptable_build(const DevPlan* plan, const long* boff, double* tab, int npt, int M, void* stream);
 int launch_sp_synth(const PtabArgs& a, int M, int rt, int ct, void* stream);

@@ -65,6 +65,8 @@ _SIGS = {
     "shtn_batch_analys": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "shtn_batch_set_tiling": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
     "shtn_batch_get_tiling": (_c.c_int, [_vp, _c.POINTER(_c.c_int)]),
+    "shtn_batch_set_algorithm": (_c.c_int, [_vp, _c.c_int]),
+    "shtn_batch_get_algorithm": (_c.c_int, [_vp]),
     "shtn_batch_capture": (_c.c_int, [_vp, _c.c_int, _vp, _vp, _vp]),
     "shtn_batch_replay": (_c.c_int, [_vp, _c.c_int, _vp]),
     "shtn_batch_tune": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c.c_int, _c.c_char_p,
@@ -693,6 +695,23 @@ class Batch:
     def tiling(self):
         t = shtn_batch_get_tiling(self.handle)
         return dict(synth_lp=t[0], fw=t[1], m_pairing=t[2], analys_merge=t[3])
+
+    def build_ptables(self):
+        """Builds the stored-P table of every plan of the batch (see Plan.build_ptable)."""
+        for p in self.plans.values():
+            p.build_ptable()
+
+    def set_algorithm(self, algo):
+        """'onthefly' or 'stored' (the plans with a table use the stored kernels); re-uploads."""
+        a = {"onthefly": SHTN_ALGO_ONTHEFLY, "stored": SHTN_ALGO_STORED}.get(algo, algo)
+        check(load_library().shtn_batch_set_algorithm(self.handle, int(a)), "shtn_batch_set_algorithm")
+        self.upload()
+
+    def algorithm(self):
+        v = load_library().shtn_batch_get_algorithm(self.handle)
+        if v < 0:
+            raise ShtnError(v, "shtn_batch_get_algorithm")
+        return "stored" if v == SHTN_ALGO_STORED else "onthefly"
 
     @property
     def work(self):

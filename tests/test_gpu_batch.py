@@ -186,3 +186,57 @@ def test_batch_graph_faster_than_per_field_launches(mixed, dev):
     print("mixed batch round trip: per-field %.1f us, graph %.1f us, speed-up %.2f"
           % (1e3 * res["per_field"], 1e3 * res["graph"], res["per_field"] / res["graph"]))
     assert res["graph"] < res["per_field"]
+
+
+def test_batch_stored_plans(mixed, dev):
+    """Stored-P kernels inside a batch (plans with a table; the fields reached
+    through the batch's offset tables) against the per-field on-the-fly
+    calls, under several tilings, eagerly and from captured graphs, and with
+    the tuner free to pick either algorithm."""
+    from paper_1202_6522_amd import shtn as S
+    b = mixed["b"]
+    b.build_ptables()
+    try:
+        b.set_algorithm("stored")
+        assert b.algorithm() == "stored"
+        for tiling in (dict(synth_lp=1, fw=2, m_pairing=0, analys_merge=1),
+                       dict(synth_lp=2, fw=1, m_pairing=1, analys_merge=0)):
+            b.set_tiling(**tiling)
+            assert b.algorithm() == "stored"
+            g = b.synth(mixed["Qp"])
+            a = b.analys(mixed["g_ref"])
+            assert rel(g.cpu().numpy(), mixed["g_ref"].cpu().numpy()) <= 1e-12
+            for f in range(len(b.shapes)):
+                assert rel(b.field_spectrum(a, f).cpu().numpy(),
+                           b.field_spectrum(mixed["a_ref"], f).cpu().numpy()) <= 1e-12
+        Qin = mixed["Qp"].clone()
+        gg = b.new_grids()
+        aa = b.new_spectra()
+        b.capture(0, Qin, gg)
+        b.capture(1, gg, aa)
+        for rep in range(3):
+            Qin.copy_(mixed["Qp"] * (1.0 + 0.5 * rep))
+            g_eager = b.synth(Qin)
+            a_eager = b.analys(g_eager)
+            torch.cuda.synchronize()
+            b.replay(0)
+            b.replay(1)
+            torch.cuda.synchronize()
+            assert torch.equal(gg, g_eager) and torch.equal(aa, a_eager), rep
+        Qin.copy_(mixed["Qp"])
+        assert b.tune(Qin, gg, aa, reps=2) > 0
+        assert b.algorithm() in ("stored", "onthefly")
+        b.replay(0)
+        b.replay(1)
+        torch.cuda.synchronize()
+        assert rel(gg.cpu().numpy(), mixed["g_ref"].cpu().numpy()) <= 1e-12
+        # a table released under the batch: its calls are refused
+        b.set_algorithm("stored")
+        next(iter(b.plans.values())).release_ptable()
+        lib = S.load_library()
+        assert lib.shtn_batch_synth(b.handle, mixed["Qp"].data_ptr(), gg.data_ptr(), b.work,
+                                    torch.cuda.current_stream(dev).cuda_stream) == S.SHTN_ESTATE
+    finally:
+        for p in b.plans.values():
+            p.release_ptable()
+        b.set_algorithm("onthefly")

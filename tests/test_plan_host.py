@@ -499,7 +499,13 @@ def test_batch_layout_and_state_errors(lib):
             assert lib.shtn_batch_upload(b, ctypes.c_void_p(4097), None) == S.SHTN_EINVAL
             for bad in [(3, 1, 0, 0), (1, 3, 0, 0), (1, 1, 2, 0), (1, 1, 0, 2), (4, 4, 0, 0)]:
                 assert lib.shtn_batch_set_tiling(b, *bad) == S.SHTN_EINVAL
+            assert lib.shtn_batch_get_algorithm(b) == S.SHTN_ALGO_ONTHEFLY
+            assert lib.shtn_batch_set_algorithm(b, 2) == S.SHTN_EINVAL
+            assert lib.shtn_batch_set_algorithm(b, S.SHTN_ALGO_STORED) == S.SHTN_OK  # no table yet: all on the fly
+            assert lib.shtn_batch_get_algorithm(b) == S.SHTN_ALGO_STORED
             S.shtn_batch_set_tiling(b, 2, 4, 0, 0)
+            assert lib.shtn_batch_get_algorithm(b) == S.SHTN_ALGO_STORED  # the tiling keeps the algorithm
+            assert lib.shtn_batch_set_algorithm(b, S.SHTN_ALGO_ONTHEFLY) == S.SHTN_OK
             assert S.shtn_batch_get_tiling(b) == [2, 4, 0, 0]
             S.shtn_batch_set_tiling(b, 2, 2, 1, 1)
             assert S.shtn_batch_get_tiling(b) == [2, 2, 1, 1]
