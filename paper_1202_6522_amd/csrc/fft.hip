@@ -271,6 +271,26 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
         }
         return;
     }
+    if (!LOAD && pow2 && nrows <= kFTile && (row0 & (nrows - 1)) == 0) {
+        // store side of the same run: all LDS reads first, then the stores
+        const int lg = __builtin_ctz(nrows);
+        const int n = nrows * (M + 1);
+        const long tb = (long)(row0 >> kFTileLg) * ts + (row0 & (kFTile - 1));
+        double2 v[kFftPerThread];
+#pragma unroll
+        for (int k = 0; k < kFftPerThread; k++) {
+            const int e = threadIdx.x + k * blockDim.x;
+            const int ec = e < n ? e : 0;
+            v[k] = buf[at(((ec & (nrows - 1)) << lgK) + (ec >> lg))];
+        }
+#pragma unroll
+        for (int k = 0; k < kFftPerThread; k++) {
+            const int e = threadIdx.x + k * blockDim.x;
+            if (e < n)
+                *(double2*)(Fout + 2 * (tb + ((long)(e >> lg) << kFTileLg) + (e & (nrows - 1)))) = v[k];
+        }
+        return;
+    }
     if (pow2 && (row0 & (run - 1)) == 0 && (nrows & (run - 1)) == 0) {
         const int lgrun = __builtin_ctz(run);
         const int per_tile = (M + 1) << lgrun;
@@ -411,30 +431,27 @@ __global__ void __launch_bounds__(kFftMaxThreads) k_r2c(FftArgs a)
     const double sc = a.scale > 0.0 ? a.scale : 2.0 * 3.14159265358979323846 / nphi;
     // X_m from Z_m and Z_{K-m}, computed in registers, then written over the
     // buffer so that F leaves in tile order
+    // (straight-line: every index below stays inside the point buffer, a
+    // row of K points lying within its 16 blockDim slots; points past npts
+    // are computed from unused slots and never read back)
     double2 x[kFftPerThread];
 #pragma unroll
     for (int e = 0; e < kFftPerThread; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
-        x[e] = make_double2(0.0, 0.0);
-        if (idx < npts) {
-            const int m = idx & (K - 1);
-            const double2 zm = buf[at(idx)];
-            const double2 zc = cconj(buf[at(idx - m + ((K - m) & (K - 1)))]);
-            const double2 A = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
-            const double2 Dd = csub(zm, zc);
-            const double2 B = make_double2(0.5 * Dd.y, -0.5 * Dd.x);  // (Z_m - conj Z_{K-m}) / (2i)
-            double2 X = cadd(A, cmul(cconj(rw[e]), B));
-            X.x *= sc;
-            X.y = m == 0 ? 0.0 : X.y * sc;
-            x[e] = X;
-        }
+        const int m = idx & (K - 1);
+        const double2 zm = buf[at(idx)];
+        const double2 zc = cconj(buf[at(idx - m + ((K - m) & (K - 1)))]);
+        const double2 A = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
+        const double2 Dd = csub(zm, zc);
+        const double2 B = make_double2(0.5 * Dd.y, -0.5 * Dd.x);  // (Z_m - conj Z_{K-m}) / (2i)
+        double2 X = cadd(A, cmul(cconj(rw[e]), B));
+        X.x *= sc;
+        X.y = m == 0 ? 0.0 : X.y * sc;
+        x[e] = X;
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * blockDim.x;
-        if (idx < npts) buf[at(idx)] = x[e];
-    }
+    for (int e = 0; e < kFftPerThread; e++) buf[at(threadIdx.x + e * blockDim.x)] = x[e];
     __syncthreads();
     move_f<false>(buf, nullptr, F, D.f_ts, M, lgK, rb.row0, rb.nrows);
 }
