@@ -123,16 +123,20 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
     const int col = lane & 15, kk = lane >> 4;
     const int comp = col & 1;
 
+    // Every address, plan value and weight the epilogue needs is read here,
+    // before the first store: the output may alias them for all the compiler
+    // knows, so reads placed between the stores would each wait on memory.
+    const long ts = P.f_ts;
     const double* qp[CT];
+    double* fo[CT];
     bool fv[CT];
-    int fld[CT];
 #pragma unroll
     for (int c = 0; c < CT; c++) {
         const int f = (blockIdx.y * CT + c) * 8 + (col >> 1);
         fv[c] = f < a.nfields;
-        fld[c] = f;
         const int fc = fv[c] ? f : 0;
         qp[c] = a.in + (a.q_off ? a.q_off[fc] : (long)fc * 2 * P.nlm) + 2 * base + comp;
+        fo[c] = a.out + (a.f_off ? a.f_off[fc] : (long)fc * 2 * P.f_size) + comp;
     }
     // pair tiles past the last one read tile pg RT (always present) and
     // feed zeros
@@ -211,21 +215,25 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
 
     // For the adjoint of the analysis the output carries (2 pi/nphi) w_i / c_m.
     const double cm = a.adjoint ? (2.0 * M_PI / P.nphi) * (m == 0 ? 1.0 : 0.5) : 1.0;
+    double sc[RT][4];
+#pragma unroll
+    for (int r = 0; r < RT; r++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            sc[r][i] = a.adjoint ? cm * P.wfull[min((pg * RT + r) * 16 + kk + 4 * i, npair - 1)] : 1.0;
 #pragma unroll
     for (int r = 0; r < RT; r++) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int pair = (pg * RT + r) * 16 + kk + 4 * i;
             if (pair >= npair) continue;
-            const double sc = a.adjoint ? cm * P.wfull[pair] : 1.0;
             const int is = nlat - 1 - pair;
 #pragma unroll
             for (int c = 0; c < CT; c++) {
                 if (!fv[c]) continue;
-                double* F = a.out + (a.f_off ? a.f_off[fld[c]] : (long)fld[c] * 2 * P.f_size) + comp;
                 const double e = acc[0][r][c][i], o = acc[1][r][c][i];
-                F[2 * f_index(P.f_ts, m, pair)] = sc * (e + o);
-                if (is != pair) F[2 * f_index(P.f_ts, m, is)] = sc * (e - o);
+                fo[c][2 * f_index(ts, m, pair)] = sc[r][i] * (e + o);
+                if (is != pair) fo[c][2 * f_index(ts, m, is)] = sc[r][i] * (e - o);
             }
         }
     }
@@ -254,16 +262,18 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
     const int col = lane & 15, kk = lane >> 4;
     const int comp = col & 1;
 
+    // Output bases are read here, before the first store (which, for all the
+    // compiler knows, may alias them).
     const double* fp[CT];
+    double* qo[CT];
     bool fv[CT];
-    int fld[CT];
 #pragma unroll
     for (int c = 0; c < CT; c++) {
         const int f = (blockIdx.y * CT + c) * 8 + (col >> 1);
         fv[c] = f < a.nfields;
-        fld[c] = f;
         const int fc = fv[c] ? f : 0;
         fp[c] = a.in + (a.f_off ? a.f_off[fc] : (long)fc * 2 * P.f_size) + comp;
+        qo[c] = a.out + (a.q_off ? a.q_off[fc] : (long)fc * 2 * P.nlm) + 2 * base + comp;
     }
     bool rv[2][JT];
     const double* tq[2][JT];
@@ -345,7 +355,7 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
                 for (int c = 0; c < CT; c++) {
                     if (!fv[c]) continue;
                     const double v = (m == 0 && comp == 1) ? 0.0 : cm * acc[q][t][c][i];
-                    a.out[(a.q_off ? a.q_off[fld[c]] : (long)fld[c] * 2 * P.nlm) + 2 * (base + j) + comp] = v;
+                    qo[c][2 * j] = v;
                 }
             }
 }
