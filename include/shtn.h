@@ -236,7 +236,8 @@ int shtn_ptable_release(shtn_plan_t plan);
 /* Work decomposition of the stored-P kernels (one wave each): synthesis
  * synth_rt (1, 2, 4) tiles of 16 latitude pairs x synth_ct (1, 2) tiles of 8
  * fields; analysis analys_jt (1, 2, 4) tiles of 16 degrees of each parity x
- * analys_ct (1, 2) tiles of 8 fields.  Default 4, 2, 4, 2.  SHTN_EINVAL for
+ * analys_ct (1, 2) tiles of 8 fields.  Default 4, 2, 4, 2.  A call of at most 8
+ * fields runs with one field tile whatever the setting.  SHTN_EINVAL for
  * other values.  Takes effect at the next call. */
 int shtn_ptable_set_tiling(shtn_plan_t plan, int synth_rt, int synth_ct, int analys_jt, int analys_ct);
 /* tiling4 = {synth_rt, synth_ct, analys_jt, analys_ct}. */

@@ -1,7 +1,7 @@
 """Builds libshtn.so (HIP for gfx950) in-tree with hipcc.
 
 Every source is compiled for gfx950 only, with packed-FP32 instructions
-disabled, then linked into paper_1202_6522_amd/libshtn.so.
+disabled (plus the per-file flags of FILE_FLAGS), then linked into paper_1202_6522_amd/libshtn.so.
 """
 from __future__ import annotations
 
@@ -26,6 +26,16 @@ FLAGS = [
 ]
 
 
+# Per-file additions.  The stored-P kernels keep their MFMA accumulators
+# loop-carried; in the default (accumulator-register) form the compiler
+# copies every accumulator between register files at each step and needs
+# 296-320 registers per lane for the widest tilings (one wave per SIMD).  The
+# VGPR form needs no copies and 226-252 registers (two waves per SIMD).
+FILE_FLAGS = {
+    "ptable.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -42,7 +52,7 @@ def _compile(src):
     if src.endswith(".cpp"):  # host-only sources
         cmd = ["g++"] + HOST_FLAGS + ["-c", src, "-o", obj]
     else:
-        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines()
                     if "packed-fp32-ops" not in l)  # host pass does not know the feature

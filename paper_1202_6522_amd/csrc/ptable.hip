@@ -138,15 +138,11 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
         qp[c] = a.in + (a.q_off ? a.q_off[fc] : (long)fc * 2 * P.nlm) + 2 * base + comp;
         fo[c] = a.out + (a.f_off ? a.f_off[fc] : (long)fc * 2 * P.f_size) + comp;
     }
-    // pair tiles past the last one read tile pg RT (always present) and
-    // feed zeros
-    bool tv[RT];
+    // pair tiles past the last one read tile pg RT (always present): their
+    // output rows are never stored
     int tr[RT];
 #pragma unroll
-    for (int r = 0; r < RT; r++) {
-        tv[r] = pg * RT + r < npt;
-        tr[r] = tv[r] ? r : 0;
-    }
+    for (int r = 0; r < RT; r++) tr[r] = pg * RT + r < npt ? r : 0;
     const int a_off = ptab_in_block(kk, lane & 15);  // + 64 s for step s of a block
 
     d4 acc[2][RT][CT];
@@ -159,13 +155,16 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
 
     // Step br covers block row br of both parities (the odd parity has as
     // many rows as the even one, or one fewer: its missing row reloads the
-    // even row and feeds zeros).  All operands of a step are loaded before
-    // its first matrix instruction, every load unconditional from a valid
-    // address (one memory round trip per step; the waves resident on a SIMD
-    // overlap them): degrees past the order's last are masked by a factor 0
-    // (the clamped coefficient belongs to the same order, so this can only
-    // turn an output that already involves a non-finite input into NaN),
-    // other invalid operands by selects.
+    // even row).  All operands of a step are loaded before its first matrix
+    // instruction, every load unconditional from a valid address (one memory
+    // round trip per step; the waves resident on a SIMD overlap them).  Only
+    // the contraction index needs a mask: degrees past the order's last
+    // (among them the whole missing odd row) get a factor 0 on B (the clamped
+    // coefficient belongs to the same order, so this can only turn an output
+    // that already involves a non-finite input into NaN; every table entry is
+    // finite).  Operands of pair rows past the last and of field columns past
+    // the last are left as loaded: they only reach outputs that are never
+    // stored.
     const int nbr0 = (((nj + 1) >> 1) + 15) >> 4, nbr1 = ((nj >> 1) + 15) >> 4;
     const double* t0 = a.tab + a.boff[2 * m] * 256 + (long)pg * RT * 256 + a_off;
     const double* t1 = a.tab + a.boff[2 * m + 1] * 256 + (long)pg * RT * 256 + a_off;
@@ -190,20 +189,17 @@ __global__ void __launch_bounds__(64) k_sp_synth(PtabArgs a)
     auto run = [&](const Ops& o, int br) {
 #pragma unroll
         for (int q = 0; q < 2; q++) {
-            const bool rowv = q == 0 || br < nbr1;
 #pragma unroll
             for (int s = 0; s < 4; s++) {
                 const double mj = 2 * (br * 16 + s * 4 + kk) + q < nj ? 1.0 : 0.0;
-                double av[RT], bv[CT];
+                double bv[CT];
 #pragma unroll
-                for (int c = 0; c < CT; c++) bv[c] = o.b[q][s][c] * (fv[c] ? mj : 0.0);
-#pragma unroll
-                for (int r = 0; r < RT; r++) av[r] = (tv[r] && rowv) ? o.a[q][s][r] : 0.0;
+                for (int c = 0; c < CT; c++) bv[c] = o.b[q][s][c] * mj;
 #pragma unroll
                 for (int r = 0; r < RT; r++)
 #pragma unroll
                     for (int c = 0; c < CT; c++)
-                        acc[q][r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r], bv[c], acc[q][r][c], 0, 0, 0);
+                        acc[q][r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[q][s][r], bv[c], acc[q][r][c], 0, 0, 0);
             }
         }
     };
@@ -284,7 +280,8 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
             const int br = g * JT + t;
             rv[q][t] = br < (q ? nbr1 : nbr0);
             // a block row past the last of its parity (the odd parity of
-            // order lmax has none) reads the first even one and feeds zeros
+            // order lmax has none) reads the first even one: its accumulator
+            // rows are degrees past the order's last, never stored
             const long blk = rv[q][t] ? a.boff[2 * m + q] + (long)br * npt : a.boff[2 * m];
             tq[q][t] = a.tab + blk * 256 + ptab_in_block(lane & 15, kk);  // + 256 pt + 16 (step % 4)
         }
@@ -317,27 +314,26 @@ __global__ void __launch_bounds__(64) k_sp_analys(PtabArgs a)
 #pragma unroll
                 for (int t = 0; t < JT; t++) pa[s][q][t] = tq[q][t][pt * 256 + s * 16];
         }
+        // keep every load of the tile ahead of its matrix instructions: left
+        // alone, the scheduler interleaves them with one wait per group
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 4; s++) {
             const int pair = pt * 16 + s * 4 + kk;
             const bool middle = (nlat & 1) && pair == npair - 1;
             const double wt = pair >= npair ? 0.0 : (a.adjoint ? (middle ? 0.5 : 1.0) : wv[s]);
-            double ge[CT], go[CT], av[2][JT];
+            double ge[CT], go[CT];
 #pragma unroll
             for (int c = 0; c < CT; c++) {
                 ge[c] = wt * (vn[s][c] + vs[s][c]);
                 go[c] = wt * (vn[s][c] - vs[s][c]);
             }
 #pragma unroll
-            for (int q = 0; q < 2; q++)
-#pragma unroll
-                for (int t = 0; t < JT; t++) av[q][t] = rv[q][t] ? pa[s][q][t] : 0.0;
-#pragma unroll
             for (int t = 0; t < JT; t++)
 #pragma unroll
                 for (int c = 0; c < CT; c++) {
-                    acc[0][t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][t], ge[c], acc[0][t][c], 0, 0, 0);
-                    acc[1][t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][t], go[c], acc[1][t][c], 0, 0, 0);
+                    acc[0][t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[s][0][t], ge[c], acc[0][t][c], 0, 0, 0);
+                    acc[1][t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[s][1][t], go[c], acc[1][t][c], 0, 0, 0);
                 }
         }
     }
@@ -392,8 +388,11 @@ static int launch_sp_analys_t(const PtabArgs& a, int M, int nbr_max, void* strea
     return (int)hipGetLastError();
 }
 
+// A call of at most 8 fields fills one column tile: a second would only
+// add columns that are never stored.
 int launch_sp_synth(const PtabArgs& a, int M, int rt, int ct, void* stream)
 {
+    if (a.nfields <= 8) ct = 1;
 #define SHTN_SP(RV, CV) \
     if (rt == RV && ct == CV) return launch_sp_synth_t<RV, CV>(a, M, stream);
     SHTN_SP(1, 1) SHTN_SP(2, 1) SHTN_SP(4, 1) SHTN_SP(1, 2) SHTN_SP(2, 2) SHTN_SP(4, 2)
@@ -403,6 +402,7 @@ int launch_sp_synth(const PtabArgs& a, int M, int rt, int ct, void* stream)
 
 int launch_sp_analys(const PtabArgs& a, int M, int nbr_max, int jt, int ct, void* stream)
 {
+    if (a.nfields <= 8) ct = 1;
 #define SHTN_SP(JV, CV) \
     if (jt == JV && ct == CV) return launch_sp_analys_t<JV, CV>(a, M, nbr_max, stream);
     SHTN_SP(1, 1) SHTN_SP(2, 1) SHTN_SP(4, 1) SHTN_SP(1, 2) SHTN_SP(2, 2) SHTN_SP(4, 2)
