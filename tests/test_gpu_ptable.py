@@ -139,6 +139,23 @@ def test_stored_tilings_agree_with_onthefly(tiling, dev):
         assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
 
 
+@pytest.mark.parametrize("nf", [8, 9, 16])
+def test_stored_field_tile_boundary(nf, dev):
+    """Calls of at most 8 fields run with one field tile whatever the tiling;
+    9 and 16 fields use two (the second partly or wholly filled)."""
+    L, M, nlat, nphi = 95, 95, 97, 256
+    rng = np.random.default_rng(300 + nf)
+    Q = to_dev(inputs.draw_spectrum(rng, L, M, 1.5, nf), dev)
+    grid = to_dev(rng.standard_normal((nf, nlat, nphi)), dev)
+    plan = make_plan(L, M, nlat, nphi, dev)
+    ref = [plan.synth(Q), plan.analys(grid), plan.synth_adj(grid), plan.analys_adj(Q)]
+    plan.set_ptable_tiling(4, 2, 4, 2)
+    plan.set_algorithm("stored")
+    got = [plan.synth(Q), plan.analys(grid), plan.synth_adj(grid), plan.analys_adj(Q)]
+    for a, b in zip(got, ref):
+        assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+
+
 def test_stored_lmax1023_sampled(dev):
     p, Q1 = inputs.scalar_case(2)
     L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
