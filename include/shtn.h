@@ -54,6 +54,13 @@ extern "C" {
 #define SHTN_EHIP (-4)         /* the HIP runtime reported an error                           */
 #define SHTN_ENOMEM (-5)       /* host allocation failed                                      */
 
+/* Fields per call: 1 .. SHTN_MAX_FIELDS for the scalar transforms (one
+ * launch row per field), 1 .. SHTN_MAX_VEC_FIELDS for the vector transforms
+ * (four scalar fields each); more give SHTN_EINVAL: split the call.
+ * Batches have no such limit. */
+#define SHTN_MAX_FIELDS 65535
+#define SHTN_MAX_VEC_FIELDS 16383
+
 typedef struct shtn_plan_s* shtn_plan_t;
 
 /* Builds a transform plan on the host (no device call).

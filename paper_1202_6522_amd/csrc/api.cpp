@@ -54,9 +54,10 @@ const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.de
 int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, const void* work)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (nfields < 1 || nfields > SHTN_MAX_FIELDS)
+        return fail(SHTN_EINVAL, "nfields must be in [1, SHTN_MAX_FIELDS = 65535]: split the call");
     if (!plan->p->uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
     if (!in || !out || !work) return fail(SHTN_EINVAL, "null data or workspace pointer");
-    if (nfields < 1) return fail(SHTN_EINVAL, "nfields must be >= 1");
     if (in == out) return fail(SHTN_EINVAL, "input and output must not alias");
     return SHTN_OK;
 }
@@ -221,9 +222,10 @@ int check_vec_call(shtn_plan_t plan, const void* a, const void* b, const void* c
                    const void* work)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
+    if (nfields < 1 || nfields > SHTN_MAX_VEC_FIELDS)
+        return fail(SHTN_EINVAL, "nfields must be in [1, SHTN_MAX_VEC_FIELDS = 16383]: split the call");
     if (!plan->p->uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
     if (!a || !b || !c || !d || !work) return fail(SHTN_EINVAL, "null data or workspace pointer");
-    if (nfields < 1) return fail(SHTN_EINVAL, "nfields must be >= 1");
     if (c == a || c == b || d == a || d == b || c == d)
         return fail(SHTN_EINVAL, "outputs must not alias inputs or each other");
     return SHTN_OK;

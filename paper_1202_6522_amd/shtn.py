@@ -25,6 +25,8 @@ SHTN_EUNSUPPORTED = -2
 SHTN_ESTATE = -3
 SHTN_EHIP = -4
 SHTN_ENOMEM = -5
+SHTN_MAX_FIELDS = 65535      # fields per scalar call (include/shtn.h)
+SHTN_MAX_VEC_FIELDS = 16383  # fields per vector call
 SHTN_ALGO_ONTHEFLY = 0
 SHTN_ALGO_STORED = 1
 SHTN_ALGO_STORED_SYNTH = 2

@@ -51,6 +51,15 @@ def test_calls_before_upload_and_null_pointers(lib):
         one = ctypes.c_void_p(16)
         assert lib.shtn_synth(h, one, ctypes.c_void_p(32), 1, one, None) == S.SHTN_ESTATE
         assert lib.shtn_synth(None, one, one, 1, one, None) == S.SHTN_EINVAL
+        # field counts past one launch row per field are refused before anything else
+        for fn in (lib.shtn_synth, lib.shtn_analys, lib.shtn_synth_adj, lib.shtn_analys_adj):
+            assert fn(h, one, ctypes.c_void_p(32), 0, one, None) == S.SHTN_EINVAL
+            assert fn(h, one, ctypes.c_void_p(32), 65536, one, None) == S.SHTN_EINVAL
+            assert fn(h, one, ctypes.c_void_p(32), 65535, one, None) == S.SHTN_ESTATE
+        v = [ctypes.c_void_p(16 * k) for k in range(1, 5)]
+        for fn in (lib.shtn_vec_synth, lib.shtn_vec_analys, lib.shtn_vec_synth_adj, lib.shtn_vec_analys_adj):
+            assert fn(h, *v, 16384, one, None) == S.SHTN_EINVAL
+            assert fn(h, *v, 16383, one, None) == S.SHTN_ESTATE
         assert lib.shtn_work_bytes(h, 0) == 0
         assert lib.shtn_lm_index(h, 3, 4) == -1
         assert lib.shtn_lm_index(h, 8, 8) == S.shtn_nlm(h) - 1
