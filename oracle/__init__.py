@@ -17,7 +17,11 @@ colatitude theta_i increasing and column k the longitude 2 pi k / nphi.
 
 Parity status: every function here is pinned by tests/test_oracle_pins.py
 (closed forms, identities, scipy brute force, quadrature exactness), and
-those of vector.py by tests/test_oracle_vector_pins.py.
+those of vector.py by tests/test_oracle_vector_pins.py.  The long-double
+instantiation (precision="ld", the reference where P_m^m falls below the
+range of double) is pinned by tests/test_oracle_ld_pins.py against 40-digit
+mpmath: its unrounded P_n^m (``plm_raw``) and its rounded ones at lmax 2047
+and 4095, its Gauss nodes, and its synthesis.
 """
 from __future__ import annotations
 
@@ -64,6 +68,10 @@ def _load():
         for name in ("oracle_gauss", "oracle_plm", "oracle_synth", "oracle_analys",
                      "oracle_synth_adj", "oracle_analys_adj"):
             getattr(lib, name + sfx).restype = ctypes.c_int
+    lib.oracle_plm_raw_d.argtypes = [i, i, ip, i, dp, dp]
+    lib.oracle_plm_raw_d.restype = ctypes.c_int
+    lib.oracle_plm_raw_ld.argtypes = [i, i, ip, i, dp, ctypes.POINTER(ctypes.c_longdouble)]
+    lib.oracle_plm_raw_ld.restype = ctypes.c_int
     lib.oracle_nlm.argtypes = [i, i]
     lib.oracle_nlm.restype = ctypes.c_long
     _lib = lib
@@ -118,6 +126,22 @@ def plm(L: int, M: int, x, precision="double"):
     rc = getattr(_load(), "oracle_plm" + _sfx(precision))(L, M, x.size, _dp(x), _dp(out))
     if rc:
         raise ValueError("oracle_plm failed")
+    return out
+
+
+def plm_raw(L: int, mlist, x, precision="ld"):
+    """P_n^m(x_j) in the oracle's working type, without the final rounding to
+    double: an array [len(mlist), L+1, len(x)] (entries n < m are 0) of
+    numpy.longdouble for precision "ld" (float64 for "double")."""
+    x = np.ascontiguousarray(np.atleast_1d(x), dtype=np.float64)
+    ml = np.ascontiguousarray(np.atleast_1d(mlist), dtype=np.int32)
+    sfx = _sfx(precision)
+    dt = np.longdouble if sfx == "_ld" else np.float64
+    out = np.zeros((ml.size, L + 1, x.size), dtype=dt)
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_longdouble if sfx == "_ld" else ctypes.c_double))
+    rc = getattr(_load(), "oracle_plm_raw" + sfx)(L, ml.size, _ip(ml), x.size, _dp(x), ptr)
+    if rc:
+        raise ValueError("oracle_plm_raw failed")
     return out
 
 

@@ -159,6 +159,30 @@ int OR_FN(oracle_plm)(int L, int M, int nx, const double* x, double* out)
     return 0;
 }
 
+/* The same values left in the working type REAL (no rounding to double), for
+ * the orders in mlist only: out[(t * (L+1) + n) * nx + j] = P_n^m(x_j) with
+ * m = mlist[t] (entries n < m are set to 0).  Lets the long-double
+ * instantiation be compared with a high-precision reference below the
+ * rounding of double, and where P_n^m lies outside the range of double. */
+int OR_FN(oracle_plm_raw)(int L, int nm, const int* mlist, int nx, const double* x, REAL* out)
+{
+    if (L < 0 || nm < 0 || nx < 0 || (nm && !mlist) || (nx && nm && (!x || !out))) return -1;
+    for (int t = 0; t < nm; t++)
+        if (mlist[t] < 0 || mlist[t] > L) return -1;
+    REAL* col = (REAL*)malloc(sizeof(REAL) * (size_t)(L + 1));
+    if (!col) return -2;
+    for (int t = 0; t < nm; t++) {
+        const int m = mlist[t];
+        for (int j = 0; j < nx; j++) {
+            OR_FN(or_plm_column)(L, m, (REAL)x[j], col);
+            for (int n = 0; n <= L; n++)
+                out[((size_t)t * (L + 1) + n) * nx + j] = n < m ? (REAL)0 : col[n - m];
+        }
+    }
+    free(col);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* DFT tables: c_j = cos(2 pi j / nphi), s_j = sin(2 pi j / nphi); the       */
 /* argument of e^{i m phi_k} is reduced exactly as j = (m k) mod nphi.       */
