@@ -50,11 +50,36 @@ def _traffic(kernel_name, launches_bytes_scale=None):
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(L, M, nlat, nphi, Q, min_seconds=10.0):
-    """The oracle (plain C, OpenMP over host threads) doing full synthesis +
-    analysis round trips of the same workload until min_seconds have passed."""
+def _host_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    """Threads for the all-cores leg: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS when it is set (the share of the host that
+    goes with one GPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def cpu_baseline(L, M, nlat, nphi, Q, min_seconds=8.0):
+    """The oracle (plain C, OpenMP) on the host, as it stands: full synthesis
+    + analysis round trips of the same workload on all the host threads this
+    process may use until min_seconds have passed, and one full synthesis on
+    a single thread (a bounded sample: the oracle's analysis of this workload
+    takes about 0.8 of its synthesis time)."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = _host_threads()
     oracle.build()
     n = 0
     t0 = time.perf_counter()
@@ -65,11 +90,18 @@ def cpu_baseline(L, M, nlat, nphi, Q, min_seconds=10.0):
         dt = time.perf_counter() - t0
         if dt >= min_seconds:
             break
+    t1 = time.perf_counter()
+    oracle.synth(Q, L, M, nlat, nphi, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": round(2.0 * n / dt, 4), "unit": "transforms/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d full synthesis + analysis round trip(s) of the timed workload "
-                      "(lmax=1023, 1024x2048 grid, 1 field; direct DFT in longitude), %.1f s"
-                      % (n, dt)}
+                      "(lmax=1023, 1024x2048 grid, 1 field; direct DFT in longitude) on %d threads, %.1f s"
+                      % (n, threads, dt),
+            "host_model": _host_model(), "host_cpus_visible": os.cpu_count(),
+            "single_thread": {"value": round(1.0 / dt1, 5), "unit": "transforms/s", "cores": 1,
+                              "sample": "one full synthesis of the timed workload on one thread, %.1f s "
+                                        "(one transform; the analysis is cheaper)" % dt1}}
 
 
 def copy_calibration(mib, dev):
@@ -349,6 +381,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scalar-only", action="store_true",
+                    help="only the timed lmax-1023 workload (no graph, batch, small, autograd, vector or "
+                         "CPU legs): for profiler runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain copy kernel over MIB MiB (for counter scaling)")
     ap.add_argument("--polar-curve", default="", metavar="LMAX,...",
@@ -465,6 +500,9 @@ def main():
         "fft_tb_per_s": {k: round((nlat * (M + 1) * 16 + nlat * nphi * 8) / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
                          for k in ("c2r", "r2c")},
     }
+    if args.scalar_only:
+        print(json.dumps(out))
+        return
     # the same step replayed from a captured graph (library calls on a
     # capturing stream; profiling off): launch overhead against the eager loop
     try:

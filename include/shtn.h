@@ -174,9 +174,13 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
  * scale of P, so results match the plain definition to rounding.  Raising it
  * (say -40 to -20) skips more of the polar work at large lmax, at an error
  * of the order of 2^log2_threshold times the spectrum norm.  log2_threshold
- * must lie in [-1000, -1], else SHTN_EINVAL.  Host only: recomputes the lane
- * starts, unit lists and restart tables; re-upload afterwards (the plan is
- * not uploaded until then, calls return SHTN_ESTATE). */
+ * must lie in [-1000, -1], else SHTN_EINVAL.  A threshold so low that some
+ * stored lane start state would fall below the normal double range (a
+ * denormal that has lost bits; about -900 at lmax 1023, -940 at lmax 255) is
+ * refused with SHTN_EINVAL and the plan keeps its previous threshold.  Host
+ * only: recomputes the lane starts, unit lists and restart tables; re-upload
+ * afterwards (the plan is not uploaded until then, calls return
+ * SHTN_ESTATE). */
 int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
 
 /* ---- vector (spheroidal / toroidal) transforms ----
@@ -289,8 +293,12 @@ double shtn_fp64_probe_tflops(void* stream);
 typedef struct shtn_batch_s* shtn_batch_t;
 
 /* A batch of nfields fields; field f is transformed with plans[f] (plans may
- * repeat).  The plans must stay alive, uploaded and untouched (no
- * shtn_plan_set_tiling, no re-upload) while the batch is used.  Host only;
+ * repeat).  The plans must stay alive and uploaded while the batch is used.
+ * The batch copies each plan's device descriptor at its upload and builds its
+ * unit tables from the plans' lane starts: after any change to a plan
+ * (shtn_plan_upload, shtn_plan_set_tiling, shtn_plan_set_polar,
+ * shtn_ptable_build or shtn_ptable_release) batch calls and replays return
+ * SHTN_ESTATE until shtn_batch_upload, which rebuilds the tables.  Host only;
  * NULL on error (shtn_last_error_detail).  Packed buffers hold the fields
  * back to back in field order: spectra at q_off[f] doubles (2 per
  * coefficient, m-major as for a plan), grids at grid_off[f] doubles. */
@@ -304,8 +312,10 @@ int shtn_batch_offsets(shtn_batch_t batch, size_t* q_off, size_t* grid_off);
 size_t shtn_batch_device_bytes(shtn_batch_t batch);
 size_t shtn_batch_work_bytes(shtn_batch_t batch);
 /* Copies the batch tables to dev_buf (caller-owned, 256-byte aligned, at least
- * shtn_batch_device_bytes) and waits for the copy.  Needed after creation and
- * after every shtn_batch_set_tiling; drops captured graphs. */
+ * shtn_batch_device_bytes) and waits for the copy.  Needed after creation,
+ * after every shtn_batch_set_tiling and after a change to one of the plans
+ * (the unit tables are rebuilt first; SHTN_ESTATE if they no longer fit the
+ * size shtn_batch_device_bytes gave at creation); drops captured graphs. */
 int shtn_batch_upload(shtn_batch_t batch, void* dev_buf, void* stream);
 /* Batched synthesis / analysis of every field on `stream` (asynchronous).
  * Errors as for the plan calls; ESTATE if not uploaded. */
@@ -338,7 +348,8 @@ int shtn_batch_get_algorithm(shtn_batch_t batch);
  * in -> out, 1 analysis) into a hipGraph held by the batch, on a private
  * stream, for these exact buffers.  Replaying it (shtn_batch_replay) on any
  * stream runs the transform on those buffers.  The graph holds kernel nodes
- * only (no memset or copy nodes).  Uploading again drops the graphs. */
+ * only (no memset or copy nodes).  Uploading again drops the graphs; a
+ * replay after a change to one of the plans returns SHTN_ESTATE. */
 int shtn_batch_capture(shtn_batch_t batch, int which, const double* in, double* out, void* work);
 int shtn_batch_replay(shtn_batch_t batch, int which, void* stream);
 /* Autotuner: times a synthesis (Qpacked -> gridpacked) plus analysis
@@ -347,8 +358,10 @@ int shtn_batch_replay(shtn_batch_t batch, int which, void* stream);
  * algorithms when a plan has a stored-P table; reps replays each,
  * default 10 when reps < 1), keeps the fastest, re-uploads and leaves both
  * graphs captured for these buffers.  Blocks until done.  With cache_path
- * (may be NULL), a tiling stored there for the same list of field shapes is
- * used without timing, and a new result is appended.  *best_us (may be NULL)
+ * (may be NULL), a tiling stored there for the same list of field shapes and
+ * the same GPU architecture is used without timing, and a new result is
+ * appended; entries that do not parse or name a tiling outside the values
+ * above are ignored (the candidates are timed).  *best_us (may be NULL)
  * receives the best round-trip time, or -1 when taken from the cache.  The
  * batch must be uploaded; Qout must not alias the other buffers. */
 int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacked, double* Qout,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -359,6 +360,7 @@ int shtn_plan_upload(shtn_plan_t plan, void* dev_buf, void* stream)
     if (e != hipSuccess) return hip_fail((int)e, "plan upload sync");
     p.dev = dev_buf;
     p.uploaded = true;
+    p.gen++;
     return SHTN_OK;
 }
 
@@ -490,6 +492,7 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
     build_image(p);
     p.uploaded = false;
     p.dev = nullptr;
+    p.gen++;
     return SHTN_OK;
 }
 
@@ -509,6 +512,17 @@ int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold)
         lane_starts(p);
         return fail(SHTN_ENOMEM, "polar threshold: out of host memory");
     }
+    // The stored start states must stay normal doubles: a denormal start has
+    // lost bits, and the recurrence would carry that error to where P_n^m
+    // grows to O(1).  How low a threshold keeps them normal depends on the
+    // plan (about -900 at lmax 1023).
+    const double lo = min_start_state(p);
+    if (lo > 0.0 && lo < DBL_MIN) {
+        p.polar_log2 = old;
+        lane_starts(p);
+        return fail(SHTN_EINVAL, "polar threshold too low for this plan: lane start states fall below the "
+                                 "normal double range");
+    }
     std::string err;
     if (rebuild_units(p, err)) {
         p.polar_log2 = old;
@@ -521,6 +535,7 @@ int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold)
     p.uploaded = false;
     p.dev = nullptr;
     p.ptab.built = false;  // the table follows the lane starts
+    p.gen++;
     return SHTN_OK;
 }
 
@@ -628,6 +643,7 @@ int shtn_ptable_build(shtn_plan_t plan, void* dev_buf, size_t bytes, void* strea
     const size_t need = p.ptab.head_bytes + (size_t)p.ptab.nblocks * 256 * sizeof(double);
     if (bytes < need) return fail(SHTN_EINVAL, "stored-P buffer smaller than shtn_ptable_bytes");
     p.ptab.built = false;
+    p.gen++;
     hipError_t e = hipMemcpyAsync(dev_buf, p.ptab.boff.data(), p.ptab.boff.size() * sizeof(long),
                                   hipMemcpyHostToDevice, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail((int)e, "stored-P offsets copy");
@@ -638,6 +654,7 @@ int shtn_ptable_build(shtn_plan_t plan, void* dev_buf, size_t bytes, void* strea
     if (e != hipSuccess) return hip_fail((int)e, "stored-P build sync");
     p.ptab.dev = dev_buf;
     p.ptab.built = true;
+    p.gen++;
     return SHTN_OK;
 }
 
@@ -647,6 +664,7 @@ int shtn_ptable_release(shtn_plan_t plan)
     plan->p->ptab.dev = nullptr;
     plan->p->ptab.built = false;
     plan->p->algo = SHTN_ALGO_ONTHEFLY;
+    plan->p->gen++;
     return SHTN_OK;
 }
 

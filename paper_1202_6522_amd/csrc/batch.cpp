@@ -81,6 +81,10 @@ struct shtn_batch_s {
     size_t max_image = 0;
     void* dev = nullptr;
     bool uploaded = false;
+    // generation of every distinct plan when the unit tables were built and
+    // when the batch was uploaded (Plan::gen): a plan changed since either
+    // makes the batch's copies stale
+    std::vector<unsigned long> tables_gen, upload_gen;
     // captured graphs: 0 synthesis, 1 analysis
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -101,9 +105,17 @@ size_t put_vec(std::vector<unsigned char>& img, size_t off, const std::vector<T>
     return put_bytes(img, off, v.data(), v.size() * sizeof(T));
 }
 
+std::vector<unsigned long> plan_gens(const shtn_batch_s& b)
+{
+    std::vector<unsigned long> g;
+    for (auto* p : b.plans) g.push_back(p->gen);
+    return g;
+}
+
 // Builds the unit tables and the device image for tiling t.
 void build_tables(shtn_batch_s& b, const BatchTiling& t)
 {
+    b.tables_gen = plan_gens(b);
     const int ns = (int)b.slot_field.size();
     // slot ranges per plan (slots of one plan are consecutive)
     std::vector<std::pair<int, int>> range(b.plans.size(), {ns, 0});
@@ -272,6 +284,9 @@ int check_batch(const shtn_batch_s* b, const void* in, const void* out, const vo
     if (in == out) return set_error(SHTN_EINVAL, "input and output must not alias");
     for (auto* p : b->plans)
         if (!p->uploaded) return set_error(SHTN_ESTATE, "a plan of the batch is no longer uploaded");
+    if (plan_gens(*b) != b->upload_gen)
+        return set_error(SHTN_ESTATE, "a plan of the batch changed since the batch upload (upload, tiling, polar "
+                                      "threshold or stored-P table): call shtn_batch_upload again");
     for (const auto& r : b->stored_runs)
         if (!b->plans[r[0]]->ptab.built)
             return set_error(SHTN_ESTATE, "a stored-P table of the batch is no longer current (set the algorithm again)");
@@ -407,10 +422,23 @@ int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work,
 
 int upload(shtn_batch_s& b, void* dev_buf, void* stream)
 {
+    for (auto* p : b.plans)
+        if (!p->uploaded) return set_error(SHTN_ESTATE, "plan of the batch not uploaded");
+    // unit tables built from an earlier state of a plan (lane starts, tiling,
+    // stored-P table): rebuild them for the current one
+    if (plan_gens(b) != b.tables_gen) {
+        try {
+            build_tables(b, b.tiling);
+        } catch (const std::bad_alloc&) {
+            return set_error(SHTN_ENOMEM, "out of host memory");
+        }
+        if (b.image.size() > b.max_image)
+            return set_error(SHTN_ESTATE, "the batch's plans changed so that its tables no longer fit the buffer "
+                                          "sized by shtn_batch_device_bytes: create the batch again");
+    }
     // descriptors of the plans as uploaded (device pointers to their tables)
     for (size_t i = 0; i < b.plans.size(); i++) {
         const Plan& p = *b.plans[i];
-        if (!p.uploaded) return set_error(SHTN_ESTATE, "plan of the batch not uploaded");
         DevPlan d;
         std::memcpy(&d, p.image.data(), sizeof(DevPlan));
         std::memcpy(b.image.data() + b.off_plans + i * sizeof(DevPlan), &d, sizeof(DevPlan));
@@ -422,6 +450,7 @@ int upload(shtn_batch_s& b, void* dev_buf, void* stream)
     if (e != hipSuccess) return hip_error((int)e, "batch upload sync");
     b.dev = dev_buf;
     b.uploaded = true;
+    b.upload_gen = plan_gens(b);
     drop_graphs(b);
     return SHTN_OK;
 }
@@ -460,34 +489,27 @@ int capture(shtn_batch_s& b, int which, const double* in, double* out, void* wor
     return SHTN_OK;
 }
 
+// Tuner cache key: format version, the GPU's architecture name (a tiling
+// tuned on one chip is no answer for another) and the field shapes.
 std::string cache_key(const shtn_batch_s& b)
 {
     std::ostringstream os;
-    os << "shtn-batch-v1";
+    os << "shtn-batch-v2";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::string arch(prop.gcnArchName);
+        for (char& c : arch)
+            if (c == ' ' || c == '|') c = '_';
+        os << ' ' << arch;
+    } else {
+        os << " unknown-arch";
+    }
     for (int f = 0; f < b.nfields; f++) {
         const Plan& p = *b.field_plan[f]->p;
         os << ' ' << p.L << ',' << p.M << ',' << p.nlat << ',' << p.nphi;
     }
     return os.str();
-}
-
-bool cache_lookup(const char* path, const std::string& key, BatchTiling& t)
-{
-    if (!path) return false;
-    std::ifstream in(path);
-    std::string line;
-    while (std::getline(in, line)) {
-        if (line.size() <= key.size() || line.compare(0, key.size(), key) != 0 || line[key.size()] != '|')
-            continue;
-        std::istringstream is(line.substr(key.size() + 1));
-        BatchTiling c;
-        if (is >> c.synth_lp >> c.fw >> c.m_pairing >> c.analys_merge) {
-            if (!(is >> c.stored)) c.stored = 0;
-            t = c;
-            return true;
-        }
-    }
-    return false;
 }
 
 int validate(const BatchTiling& t)
@@ -502,6 +524,30 @@ int validate(const BatchTiling& t)
     if (t.stored != 0 && t.stored != 1) return set_error(SHTN_EINVAL, "stored must be 0 or 1");
     return SHTN_OK;
 }
+
+// A cached tiling for key, or false.  Entries that do not parse or that name
+// a tiling outside the built kernels (a damaged or foreign cache file) are
+// treated as misses, so the tuner times the candidates instead.
+bool cache_lookup(const char* path, const std::string& key, BatchTiling& t)
+{
+    if (!path) return false;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.size() <= key.size() || line.compare(0, key.size(), key) != 0 || line[key.size()] != '|')
+            continue;
+        std::istringstream is(line.substr(key.size() + 1));
+        BatchTiling c;
+        if (is >> c.synth_lp >> c.fw >> c.m_pairing >> c.analys_merge) {
+            if (!(is >> c.stored)) c.stored = 0;
+            if (validate(c) != SHTN_OK) continue;
+            t = c;
+            return true;
+        }
+    }
+    return false;
+}
+
 
 }  // namespace
 
@@ -696,6 +742,9 @@ int shtn_batch_replay(shtn_batch_t batch, int which, void* stream)
     if (which != 0 && which != 1) return set_error(SHTN_EINVAL, "which must be 0 or 1");
     if (!batch->uploaded || !batch->exec[which])
         return set_error(SHTN_ESTATE, "no captured graph (call shtn_batch_capture after the upload)");
+    if (plan_gens(*batch) != batch->upload_gen)
+        return set_error(SHTN_ESTATE, "a plan of the batch changed since the graphs were captured: upload and "
+                                      "capture again");
     hipError_t e = hipGraphLaunch(batch->exec[which], (hipStream_t)stream);
     if (e != hipSuccess) return hip_error((int)e, "graph launch");
     return SHTN_OK;

@@ -85,8 +85,12 @@ static int log2_floor(ld v)
 // shifts, same fused multiply-adds).  The lane starts at the checkpoint
 // (multiple of kInject) that opens the first block of kInject steps in which
 // |P_n^m| reaches 2^polar_log2; the state entering that step, converted to a
-// plain double (exact: it is far inside the normal range), is stored.  A lane
-// that never reaches the threshold gets the start step nj = lmax - m + 1.
+// plain double, is stored.  The conversion is exact while the state stays in
+// the normal range, which holds at the default threshold (the states lie
+// within about 2^-100 of it); for very low thresholds it need not, and
+// shtn_plan_set_polar refuses a threshold whose states fall below DBL_MIN
+// (min_start_state).  A lane that never reaches the threshold gets the start
+// step nj = lmax - m + 1.
 static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double& yb)
 {
     const int nj = p.L - m + 1;
@@ -155,6 +159,16 @@ void lane_starts(Plan& p)
         });
     }
     for (auto& th : pool) th.join();
+}
+
+double min_start_state(const Plan& p)
+{
+    double lo = 0.0;
+    for (double v : p.inj_y) {
+        const double a = std::fabs(v);
+        if (a > 0.0 && (lo == 0.0 || a < lo)) lo = a;
+    }
+    return lo;
 }
 
 Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)

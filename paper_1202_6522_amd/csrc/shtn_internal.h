@@ -168,7 +168,15 @@ struct Plan {
     bool uploaded = false;
     PTable ptab;
     int algo = 0;  // Legendre stage: 0 on-the-fly recurrence, 1 stored P
+    // Bumped by every change that moves the plan's device state or its lane
+    // starts (upload, tiling, polar threshold, stored-P build or release):
+    // batches that copied the plan's device descriptor or built unit tables
+    // from its lane starts compare it to refuse stale copies.
+    unsigned long gen = 0;
 };
+// Smallest nonzero |state| among the stored lane starts (inj_y), or 0 if all
+// are 0: below DBL_MIN a start state is a denormal that has lost precision.
+double min_start_state(const Plan& p);
 void ptable_layout(Plan& p);  // geometry of the stored-P table
 
 // Error reporting shared by the C-ABI sources (api.cpp): sets the detail

@@ -677,6 +677,7 @@ class Batch:
                                 device=self.device)
         self._work = torch.empty(shtn_batch_work_bytes(self.handle) + 256, dtype=torch.uint8,
                                  device=self.device)
+        self._captured = {}
         self.upload()
 
     @staticmethod
@@ -699,9 +700,12 @@ class Batch:
         return dict(synth_lp=t[0], fw=t[1], m_pairing=t[2], analys_merge=t[3])
 
     def build_ptables(self):
-        """Builds the stored-P table of every plan of the batch (see Plan.build_ptable)."""
+        """Builds the stored-P table of every plan of the batch (see
+        Plan.build_ptable), then uploads the batch again (a plan that changed
+        makes the batch's copies stale until then)."""
         for p in self.plans.values():
             p.build_ptable()
+        self.upload()
 
     def set_algorithm(self, algo):
         """'onthefly' or 'stored' (the plans with a table use the stored kernels); re-uploads."""
@@ -765,16 +769,22 @@ class Batch:
         return out
 
     def capture(self, which, inp, out):
-        """Captures one direction (0 synthesis, 1 analysis) for these buffers."""
+        """Captures one direction (0 synthesis, 1 analysis) for these buffers
+        (kept referenced while the graph exists)."""
         shtn_batch_capture(self.handle, which, inp.data_ptr(), out.data_ptr(), self.work)
+        self._captured[which] = (inp, out)
 
     def replay(self, which):
         shtn_batch_replay(self.handle, which, self._stream())
 
     def tune(self, Qp, gp, Qout, reps=10, cache_path=None):
-        """Autotunes the tiling on these buffers; leaves both graphs captured."""
-        return shtn_batch_tune(self.handle, Qp.data_ptr(), gp.data_ptr(), Qout.data_ptr(),
-                               self.work, self._stream(), reps, cache_path)
+        """Autotunes the tiling on these buffers; leaves both graphs captured
+        (the buffers kept referenced).  Returns the best round-trip time in
+        microseconds, or -1 when the tiling came from the cache."""
+        us = shtn_batch_tune(self.handle, Qp.data_ptr(), gp.data_ptr(), Qout.data_ptr(),
+                             self.work, self._stream(), reps, cache_path)
+        self._captured = {0: (Qp, gp), 1: (gp, Qout)}
+        return us
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -90,7 +90,7 @@ def test_gradient_vs_oracle_transpose(grad_setup):
     s = grad_setup
     p = s["p"]
     L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
-    fields = [0, 7]
+    fields = list(range(16))
     _, w = oracle.gauss(nlat)
     Q0 = s["Q0"][fields]
     QT = s["QT"][fields]

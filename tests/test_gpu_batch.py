@@ -185,7 +185,8 @@ def test_batch_graph_faster_than_per_field_launches(mixed, dev):
         res[name] = e0.elapsed_time(e1) / 10
     print("mixed batch round trip: per-field %.1f us, graph %.1f us, speed-up %.2f"
           % (1e3 * res["per_field"], 1e3 * res["graph"], res["per_field"] / res["graph"]))
-    assert res["graph"] < res["per_field"]
+    # the workload's target: the batched graph at least 3x faster
+    assert res["per_field"] / res["graph"] >= 3.0
 
 
 def test_batch_stored_plans(mixed, dev):
@@ -240,3 +241,72 @@ def test_batch_stored_plans(mixed, dev):
         for p in b.plans.values():
             p.release_ptable()
         b.set_algorithm("onthefly")
+
+
+SMALL = [(31, 31, 32, 64), (63, 63, 64, 128), (31, 31, 32, 64), (47, 40, 49, 128)]
+
+
+def small_batch(dev, seed=3):
+    from paper_1202_6522_amd.shtn import Batch
+    b = Batch(SMALL, device=dev)
+    rng = np.random.default_rng(seed)
+    specs = [inputs.draw_spectrum(rng, L, M, 1.0, 1)[0] for (L, M, _, _) in SMALL]
+    return b, b.pack_spectra(specs), specs
+
+
+def test_batch_refuses_a_changed_plan(dev):
+    # A plan of the batch re-uploaded with another polar threshold (its
+    # tables move and its lane starts change): batch calls and replays are
+    # refused until the batch is uploaded again, which rebuilds its unit
+    # tables; the results then follow the plan's new state.
+    from paper_1202_6522_amd import shtn as S
+    b, Qp, specs = small_batch(dev)
+    g = b.new_grids()
+    a = b.new_spectra()
+    b.capture(0, Qp, g)
+    b.capture(1, g, a)
+    plan = b.plans[SMALL[1]]
+    plan.set_polar(-20)
+    with pytest.raises(S.ShtnError) as ei:
+        b.synth(Qp)
+    assert ei.value.code == S.SHTN_ESTATE
+    with pytest.raises(S.ShtnError) as ei:
+        b.replay(0)
+    assert ei.value.code == S.SHTN_ESTATE
+    b.upload()
+    gb = b.synth(Qp)
+    for f, s in enumerate(SMALL):
+        ref = b.plans[s].synth(b.field_spectrum(Qp, f).view(1, -1))[0]
+        assert torch.equal(b.field_grid(gb, f), ref), f
+    # the threshold of 2^-20 moves the changed field's result
+    fresh = S.Plan(*SMALL[1], device=dev)
+    assert not torch.equal(b.field_grid(gb, 1), fresh.synth(b.field_spectrum(Qp, 1).view(1, -1))[0])
+
+
+def test_tuner_ignores_damaged_cache_entries(dev, tmp_path):
+    # entries with the batch's key but a tiling outside the built kernels
+    # (zero pairs per lane, zero fields per wave, a kernel that does not
+    # exist) or unreadable numbers are misses: the tuner times the
+    # candidates and leaves a valid tiling
+    b, Qp, _ = small_batch(dev, seed=4)
+    g = b.new_grids()
+    a = b.new_spectra()
+    cache = str(tmp_path / "tune.txt")
+    assert b.tune(Qp, g, a, reps=2, cache_path=cache) > 0
+    good = open(cache).read().strip().splitlines()[-1]
+    key = good.split("|")[0]
+    assert "gfx" in key  # the GPU architecture is part of the key
+    for bad in ("0 1 0 0 0", "1 0 0 0 0", "8 1 0 0 0", "4 4 0 0 0", "1 1 2 0 0", "x y"):
+        with open(cache, "w") as f:
+            f.write(key + "|" + bad + "\n")
+        assert b.tune(Qp, g, a, reps=2, cache_path=cache) > 0, bad
+        t = b.tiling()
+        assert t["synth_lp"] in (1, 2, 4) and t["fw"] in (1, 2, 4), bad
+    b.replay(0)
+    b.replay(1)
+    torch.cuda.synchronize()
+    assert rel(a.cpu().numpy(), Qp.cpu().numpy()) <= 1e-11
+    # a valid entry is used as it is
+    with open(cache, "w") as f:
+        f.write(good + "\n")
+    assert b.tune(Qp, g, a, reps=2, cache_path=cache) == -1.0

@@ -1,0 +1,167 @@
+"""GPU parity at the high-resolution workload, every output element compared.
+
+lmax = mmax = 1023, nlat = 1024 Gauss nodes, nphi = 2048, the seeded spectrum
+of the workload (N(0,1)(n+1)^-1.5).  All four transforms of the HIP path
+(through the C interface) against the CPU oracle on full arrays, for the
+on-the-fly Legendre stage under several tilings and for the stored-P one:
+
+- synthesis S Q against oracle.synth;
+- analysis A f of an independent non-band-limited N(0,1) grid against
+  oracle.analys, with the error by degree n (Sec. 3.5 measures accuracy on the
+  spectrum): e_n = max_m |dQ_n^m|, printed and bounded;
+- adjoint of the synthesis S^T g and of the analysis A^T h against the
+  oracle's adjoints;
+- the round trip A S Q against Q, by degree.
+
+Bar: max |gpu - oracle| / max |oracle| <= 1e-9 over each output array (the
+tolerance the workload states for lmax 1023); per degree e_n / max |oracle|
+<= 1e-9 as well.  The oracle results are computed once per module (a few
+seconds on the host cores).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1202_6522_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-9
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1202_6522_amd import shtn
+    shtn.load_library()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ref1023(dev):
+    p, Q = inputs.scalar_case(2)
+    L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+    grid = inputs.random_grid(5, 1, nlat, nphi)
+    g2 = inputs.random_grid(6, 1, nlat, nphi)
+    h = inputs.draw_spectrum(np.random.default_rng(inputs.SEED_BASE + 60), L, M, 1.5, 1)
+    return dict(shape=(L, M, nlat, nphi), Q=Q, grid=grid, g2=g2, h=h,
+                S=oracle.synth(Q, L, M, nlat, nphi),
+                A=oracle.analys(grid, L, M, nlat, nphi),
+                St=oracle.synth_adj(g2, L, M, nlat, nphi),
+                At=oracle.analys_adj(h, L, M, nlat, nphi))
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def by_degree(err, L, M):
+    """max over m of |err_n^m| for every degree n."""
+    n_all, _ = inputs.degree_order(L, M)
+    e = np.zeros(L + 1)
+    np.maximum.at(e, n_all, np.abs(err).ravel())
+    return e
+
+
+def check_all(plan, r, dev, label):
+    L, M, nlat, nphi = r["shape"]
+    g = plan.synth(to_dev(r["Q"], dev))
+    es = rel(g.cpu().numpy(), r["S"])
+    A = plan.analys(to_dev(r["grid"], dev)).cpu().numpy()
+    ea = rel(A, r["A"])
+    St = plan.synth_adj(to_dev(r["g2"], dev)).cpu().numpy()
+    est = rel(St, r["St"])
+    At = plan.analys_adj(to_dev(r["h"], dev)).cpu().numpy()
+    eat = rel(At, r["At"])
+    en = by_degree(A - r["A"], L, M) / np.max(np.abs(r["A"]))
+    R = plan.analys(g).cpu().numpy()
+    rn = by_degree(R - r["Q"], L, M) / np.max(np.abs(r["Q"]))
+    worst = np.argsort(en)[-3:][::-1]
+    print("%s: synth %.2e analys %.2e synth_adj %.2e analys_adj %.2e; analysis error by degree: "
+          "max %.2e (n = %s), median %.2e; round trip by degree max %.2e"
+          % (label, es, ea, est, eat, en.max(), list(worst), np.median(en), rn.max()))
+    assert es <= BAR and ea <= BAR and est <= BAR and eat <= BAR, (es, ea, est, eat)
+    assert en.max() <= BAR and rn.max() <= BAR
+    assert np.all(A[0, :L + 1].imag == 0)
+
+
+@pytest.mark.parametrize("tiling", [
+    None,
+    dict(synth_lp=1, analys_lp=8, m_pairing=0, split=128),
+    dict(synth_lp=4, analys_lp=8, m_pairing=1, split=512, fft_rows=2),
+    dict(synth_lp=2, analys_lp=4, analys_waves=2, m_pairing=0, split=256),
+    dict(synth_lp=1, analys_lp=4, analys_waves=4, m_pairing=0),
+])
+def test_lmax1023_full_onthefly(tiling, ref1023, dev):
+    from paper_1202_6522_amd.shtn import Plan
+    plan = Plan(*ref1023["shape"], device=dev, tiling=tiling)
+    check_all(plan, ref1023, dev, "on the fly %s" % (tiling or "default"))
+
+
+@pytest.mark.parametrize("ptiling", [None, dict(synth_rt=2, synth_ct=1, analys_jt=2, analys_ct=1)])
+def test_lmax1023_full_stored(ptiling, ref1023, dev):
+    from paper_1202_6522_amd.shtn import Plan
+    plan = Plan(*ref1023["shape"], device=dev)
+    if ptiling:
+        plan.set_ptable_tiling(**ptiling)
+    plan.set_algorithm("stored")
+    assert plan.algorithm() == "stored"
+    check_all(plan, ref1023, dev, "stored P %s" % (ptiling or "default"))
+    plan.release_ptable()
+
+
+def test_lmax255_adjoints_full(dev):
+    from paper_1202_6522_amd.shtn import Plan
+    p, Q = inputs.scalar_case(1)
+    L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
+    rng = np.random.default_rng(inputs.SEED_BASE + 61)
+    g = rng.standard_normal((2, nlat, nphi))
+    h = inputs.draw_spectrum(rng, L, M, 1.0, 2)
+    St_ref = oracle.synth_adj(g, L, M, nlat, nphi)
+    At_ref = oracle.analys_adj(h, L, M, nlat, nphi)
+    for algo in ("onthefly", "stored"):
+        plan = Plan(L, M, nlat, nphi, device=dev)
+        plan.set_algorithm(algo)
+        St = plan.synth_adj(to_dev(g, dev)).cpu().numpy()
+        At = plan.analys_adj(to_dev(h, dev)).cpu().numpy()
+        print("lmax 255 %s: synth_adj %.2e analys_adj %.2e" % (algo, rel(St, St_ref), rel(At, At_ref)))
+        assert rel(St, St_ref) <= 1e-11
+        assert rel(At, At_ref) <= 1e-11
+
+
+def test_lmax4095_underflow_guard(dev):
+    # lmax 4095: for large m the start P_m^m lies far below the range of
+    # double near the poles while P_n^m still reaches O(1) by n = 4095 (the
+    # guard of Sec. 3.5, resolved by the plan-time lane starts).  Synthesis on
+    # selected orders against the long-double oracle at rows of both
+    # hemispheres; analysis units span 2048 latitude pairs (four waves of 8
+    # pairs per lane); round trip in full.
+    from paper_1202_6522_amd.shtn import Plan
+    L, nlat, nphi = 4095, 4096, 8192
+    plan = Plan(L, L, nlat, nphi, device=dev)
+    assert plan.tiling()["analys_waves"] == 4
+    rng = np.random.default_rng(4095)
+    ms = [0, 700, 1200, 1600, 2000, 3000, 4000, 4095]
+    Q = np.zeros((1, plan.nlm), complex)
+    n_all, m_all = inputs.degree_order(L, L)
+    sel = np.isin(m_all, ms)
+    Q[0, sel] = (rng.standard_normal(sel.sum()) + 1j * rng.standard_normal(sel.sum())) \
+        * (n_all[sel] + 1.0) ** -1.0
+    Q[0, m_all == 0] = Q[0, m_all == 0].real
+    g = plan.synth(to_dev(Q, dev))
+    rows = np.array([0, 1, 5, 40, 235, 408, 702, 1144, 2047, 2048, 3000, 4090, 4095])
+    gref = oracle.synth(Q, L, L, nlat, nphi, mlist=ms, rows=rows, precision="ld")
+    es = rel(g.cpu().numpy()[0][rows], gref[0])
+    R = plan.analys(g).cpu().numpy()
+    er = rel(R, Q)
+    rn = by_degree(R - Q, L, L) / np.max(np.abs(Q))
+    print("lmax 4095: synthesis rows vs long-double oracle %.3e, round trip %.3e (worst degree %d)"
+          % (es, er, int(np.argmax(rn))))
+    assert es <= 1e-10
+    assert er <= 1e-10

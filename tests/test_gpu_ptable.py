@@ -6,7 +6,8 @@ largest |P| (both sides run an FP64 three-term recurrence; its rounding floor
 against long double is about 3e-13 of max |P| at lmax 255, 1.4e-13 measured
 here at lmax 100), exact 0 where the polar threshold drops a term, which
 needs |P| < 2^-200; the four transforms against the oracle to 1e-11 relative to
-the largest output (1e-9 at lmax 1023, sampled orders); stored against
+the largest output (the full-array lmax 1023 comparison of the stored path is
+in test_gpu_parity_full.py); stored against
 on-the-fly results to 1e-12 (the two sum the same terms in other orders).
 """
 import numpy as np
@@ -156,7 +157,10 @@ def test_stored_field_tile_boundary(nf, dev):
         assert rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
 
 
-def test_stored_lmax1023_sampled(dev):
+def test_stored_lmax1023_three_fields(dev):
+    # several fields per call at lmax 1023 (one 8-field column tile): stored
+    # against on-the-fly results and the round trip; the full-array oracle
+    # comparison of the stored path is in test_gpu_parity_full.py
     p, Q1 = inputs.scalar_case(2)
     L, M, nlat, nphi = p["L"], p["M"], p["nlat"], p["nphi"]
     rng = np.random.default_rng(7)
@@ -164,21 +168,13 @@ def test_stored_lmax1023_sampled(dev):
     plan = make_plan(L, M, nlat, nphi, dev)
     Qd = to_dev(Q, dev)
     g_otf = plan.synth(Qd)
+    a_otf = plan.analys(g_otf)
     plan.set_algorithm("stored")
     g = plan.synth(Qd)
     assert rel(g.cpu().numpy(), g_otf.cpu().numpy()) <= 1e-12
-    rows = np.array([0, 1, 17, 255, 511, 512, 1000, 1023])
-    gref = oracle.synth(Q[:1], L, M, nlat, nphi, rows=rows)
-    assert rel(g[0].cpu().numpy()[rows], gref[0]) <= 1e-9
-    R = plan.analys(g).cpu().numpy()
-    assert rel(R, Q) <= 1e-9
-    grid = inputs.random_grid(5, 1, nlat, nphi)[0]
-    A = plan.analys(to_dev(grid, dev)).cpu().numpy()
-    ms = [0, 1, 300, 777, 1023]
-    Aref = oracle.analys(grid, L, M, nlat, nphi, mlist=ms)
-    _, m_all = inputs.degree_order(L, M)
-    sel = np.isin(m_all, ms)
-    assert rel(A[sel], Aref[sel]) <= 1e-9
+    R = plan.analys(g)
+    assert rel(R.cpu().numpy(), a_otf.cpu().numpy()) <= 1e-12
+    assert rel(R.cpu().numpy(), Q) <= 1e-9
 
 
 def test_stored_follows_polar_threshold(dev):

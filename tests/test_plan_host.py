@@ -559,6 +559,32 @@ def test_polar_threshold_setting():
         S.shtn_plan_destroy(h)
 
 
+def test_polar_threshold_keeps_start_states_normal(lib):
+    # A very low threshold (lanes start far into the evanescent region)
+    # would store start states below DBL_MIN, denormals that have lost bits;
+    # shtn_plan_set_polar refuses such a threshold and leaves the plan as it
+    # was.  At lmax 1023 the lowest accepted one is about -900; every stored
+    # state there is 0 or a normal double.
+    L = 1023
+    h = S.shtn_plan(L, L, L + 1, 2 * (L + 1))
+    try:
+        base = _tables(h)
+        for t in (-1000, -960, -920):
+            assert lib.shtn_plan_set_polar(h, t) == S.SHTN_EINVAL, t
+            now = _tables(h)
+            assert int(now[T_TIL][8]) == -200
+            for k in (T_INJJ, T_INJY, T_AU, T_SU, T_RSTY):
+                assert np.array_equal(now[k], base[k]), (t, k)
+        S.shtn_plan_set_polar(h, -900)
+        y = _tables(h)[T_INJY]
+        nz = np.abs(y[y != 0])
+        assert nz.size and nz.min() >= np.finfo(np.float64).tiny
+        # lanes start earlier than at the default threshold, never later
+        assert np.all(_tables(h)[T_INJJ] <= base[T_INJJ])
+    finally:
+        S.shtn_plan_destroy(h)
+
+
 @pytest.mark.parametrize("shape", [(0, 0, 1, 2), (31, 31, 32, 64), (63, 40, 65, 128), (1023, 1023, 1024, 2048)])
 def test_ptable_geometry_and_states(lib, shape):
     """Stored-P table size: per order m (nj = lmax - m + 1) ceil(nj/2) even and
