@@ -183,6 +183,25 @@ int shtn_plan_set_tiling(shtn_plan_t plan, int synth_lp, int analys_lp, int anal
  * SHTN_ESTATE). */
 int shtn_plan_set_polar(shtn_plan_t plan, int log2_threshold);
 
+/* ---- synthesis without a workspace, for callers that cannot allocate ----
+ *
+ * For callers that cannot allocate device memory or provide a workspace:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same result as shtn_synth (bitwise: the same kernels), with the
+ * workspace taken from a static device array of SHTN_NOALLOC_MAX_BYTES bytes
+ * that every GPU the library runs on holds from the library's load until
+ * the process ends.  Allocates nothing and calls no allocating routine.
+ * SHTN_EINVAL when shtn_work_bytes(plan, nfields) exceeds
+ * SHTN_NOALLOC_MAX_BYTES (one field at lmax 1023 fits, or five at lmax 511,
+ * twenty at lmax 255); other errors as for shtn_synth.  All calls of one
+ * process on one GPU share that GPU's array, which keeps the last call's
+ * contents: calls that can overlap in time (on different streams, or from
+ * host threads without ordering between them) race and give undefined
+ * results; calls ordered on one stream do not.  Each process has its own
+ * copy. */
+#define SHTN_NOALLOC_MAX_BYTES ((size_t)32 << 20)
+int shtn_synth_noalloc(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* stream);
+
 /* ---- vector (spheroidal / toroidal) transforms ----
  *
  * The paper names vector transforms but gives no formulas; the definition

@@ -262,6 +262,14 @@ int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* 
 
 }  // namespace
 
+namespace shtn {
+// The synthesis call sequence on a workspace chosen by the caller (noalloc.hip).
+int synth_on_work(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream)
+{
+    return to_grid(plan, Q, grid, nfields, work, stream, 0);
+}
+}  // namespace shtn
+
 extern "C" {
 
 shtn_plan_t shtn_plan(int lmax, int mmax, int nlat, int nphi)

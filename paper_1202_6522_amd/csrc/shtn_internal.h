@@ -312,3 +312,8 @@ int launch_r2c(const FftLaunch& a, void* stream);
 struct shtn_plan_s {
     shtn::Plan* p;
 };
+
+namespace shtn {
+// shtn_synth's checks and launches with `work` as the workspace (api.cpp).
+int synth_on_work(shtn_plan_s* plan, const double* Q, double* grid, int nfields, void* work, void* stream);
+}  // namespace shtn

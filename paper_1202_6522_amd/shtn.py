@@ -47,6 +47,7 @@ _SIGS = {
     "shtn_plan_upload": (_c.c_int, [_vp, _vp, _vp]),
     "shtn_work_bytes": (_sz, [_vp, _c.c_int]),
     "shtn_synth": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "shtn_synth_noalloc": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp]),
     "shtn_analys": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
     "shtn_synth_adj": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
     "shtn_analys_adj": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
@@ -165,6 +166,13 @@ def shtn_work_bytes(h, nfields):
 
 def shtn_synth(h, Q, grid, nfields, work, stream):
     return check(load_library().shtn_synth(h, Q, grid, nfields, work, stream), "shtn_synth")
+
+
+def shtn_synth_noalloc(h, Q, grid, nfields, stream):
+    return check(load_library().shtn_synth_noalloc(h, Q, grid, nfields, stream), "shtn_synth_noalloc")
+
+
+SHTN_NOALLOC_MAX_BYTES = 32 << 20  # static workspace of shtn_synth_noalloc (include/shtn.h)
 
 
 def shtn_analys(h, grid, Q, nfields, work, stream):
