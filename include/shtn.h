@@ -144,7 +144,11 @@ double shtn_legendre_flops(shtn_plan_t plan);
  * 14 first latitude pair that
  * ever reaches the polar threshold, per m (int32), 15 start step of every
  * (order, pair) lane (int32, (mmax+1) x npair; lmax-m+1 = never), 16 the
- * recurrence state entering that step (double, (mmax+1) x npair x 2).
+ * recurrence state entering that step (double, (mmax+1) x npair x 2), 17 the
+ * first start step of each block of 64 latitude pairs (int32, (mmax+1) x
+ * ceil(npair/64)), 18 per (order, checkpoint k) two uint32 bit masks of
+ * blocks 0..31: the blocks with a lane starting at step 8k, and those with
+ * a lane started at or before it ((mmax+1) x ((lmax + 32)/8 + 2) x 2).
  * Returns the table size in bytes; copies only if dst != NULL and
  * bytes >= size.  Negative on error. */
 long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes);

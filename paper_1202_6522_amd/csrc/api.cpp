@@ -345,6 +345,9 @@ int shtn_plan_upload(shtn_plan_t plan, void* dev_buf, void* stream)
     d.rtw = (const double*)at(TB_RTW);
     d.synth_units = (const int*)at(TB_SYNTH_UNITS);
     d.analys_units = (const int*)at(TB_ANALYS_UNITS);
+    d.ck_mask = (const unsigned*)at(TB_CK_MASK);
+    d.nblk = p.nblk;
+    d.nck = p.nck;
     d.L = p.L;
     d.M = p.M;
     d.nlat = p.nlat;
@@ -455,6 +458,8 @@ long shtn_plan_table(shtn_plan_t plan, int which, void* dst, size_t bytes)
     case 14: src = p.first_pair.data(); n = p.first_pair.size() * 4; break;
     case 15: src = p.inj_j.data(); n = p.inj_j.size() * 4; break;
     case 16: src = p.inj_y.data(); n = p.inj_y.size() * 8; break;
+    case 17: src = p.blk_first.data(); n = p.blk_first.size() * 4; break;
+    case 18: src = p.ck_mask.data(); n = p.ck_mask.size() * 4; break;
     default: return fail(SHTN_EINVAL, "unknown table");
     }
     if (dst && bytes >= n && n) std::memcpy(dst, src, n);

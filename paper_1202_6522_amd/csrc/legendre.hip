@@ -472,44 +472,62 @@ __device__ __forceinline__ double swap_lane_pair(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One recurrence step (even t: ua and the even inputs, odd t: ub and the odd
-// inputs).  Returns per field the lane pair's partial sum over its pairs of
-// the kept component: real part on even lanes, imaginary part on odd lanes.
-template <int LP, int FW>
-__device__ __forceinline__ void analys_step(AState<LP, FW>& s, int t, double b, double (&out)[FW])
+// Two recurrence steps, an even one (ua and the even inputs) and the odd one
+// after it (ub and the odd inputs), on the pair slots PF..LP-1; the slots
+// below PF belong to latitude blocks none of whose lanes has started, hold 0
+// and would add exactly 0.  Both steps advance the recurrence first, then
+// their four sums (kept and handed-over component of each step) are
+// accumulated side by side over the slots, so four independent chains of
+// fused multiply-adds share the latency.  Returns per field and step the
+// lane pair's partial sum over its pairs of the kept component: real part on
+// even lanes, imaginary part on odd lanes.
+template <int LP, int FW, int PF>
+__device__ __forceinline__ void analys_step_pair(AState<LP, FW>& s, double b0, double b1, double (&out0)[FW],
+                                                 double (&out1)[FW])
 {
-    double sk[FW], ss[FW];
 #pragma unroll
-    for (int f = 0; f < FW; f++) sk[f] = ss[f] = 0.0;
-    if ((t & 1) == 0) {
+    for (int p = PF; p < LP; p++) s.ua[p] = fma(s.x[p], s.ub[p], b0 * s.ua[p]);
 #pragma unroll
-        for (int p = 0; p < LP; p++) {
-            s.ua[p] = fma(s.x[p], s.ub[p], b * s.ua[p]);
+    for (int p = PF; p < LP; p++) s.ub[p] = fma(s.x[p], s.ua[p], b1 * s.ub[p]);
+    double sk0[FW], ss0[FW], sk1[FW], ss1[FW];
 #pragma unroll
-            for (int f = 0; f < FW; f++) {
-                sk[f] = fma(s.ek[p][f], s.ua[p], sk[f]);
-                ss[f] = fma(s.es[p][f], s.ua[p], ss[f]);
-            }
-        }
-    } else {
+    for (int f = 0; f < FW; f++) sk0[f] = ss0[f] = sk1[f] = ss1[f] = 0.0;
 #pragma unroll
-        for (int p = 0; p < LP; p++) {
-            s.ub[p] = fma(s.x[p], s.ua[p], b * s.ub[p]);
+    for (int p = PF; p < LP; p++) {
 #pragma unroll
-            for (int f = 0; f < FW; f++) {
-                sk[f] = fma(s.ok[p][f], s.ub[p], sk[f]);
-                ss[f] = fma(s.os[p][f], s.ub[p], ss[f]);
-            }
+        for (int f = 0; f < FW; f++) {
+            sk0[f] = fma(s.ek[p][f], s.ua[p], sk0[f]);
+            ss0[f] = fma(s.es[p][f], s.ua[p], ss0[f]);
+            sk1[f] = fma(s.ok[p][f], s.ub[p], sk1[f]);
+            ss1[f] = fma(s.os[p][f], s.ub[p], ss1[f]);
         }
     }
 #pragma unroll
-    for (int f = 0; f < FW; f++) out[f] = sk[f] + swap_lane_pair(ss[f]);
+    for (int f = 0; f < FW; f++) {
+        out0[f] = sk0[f] + swap_lane_pair(ss0[f]);
+        out1[f] = sk1[f] + swap_lane_pair(ss1[f]);
+    }
 }
 
 template <int N>
 struct DBlk {
     double v[N];
 };
+
+template <int N>
+struct DBlk2u {
+    unsigned v[N];
+};
+
+// A block of N wave-uniform 32-bit words through the scalar cache.
+template <int N>
+__device__ __forceinline__ void load_u32(DBlk2u<N>& d, cip src)
+{
+    typedef const __attribute__((address_space(4))) DBlk2u<N>* cbp;
+    cbp p = (cbp)src;
+#pragma unroll
+    for (int i = 0; i < N; i++) d.v[i] = p->v[i];
+}
 
 // A block of N wave-uniform doubles through the scalar cache.
 template <int N>
@@ -521,38 +539,115 @@ __device__ __forceinline__ void load_blk(DBlk<N>& d, cdp src)
     for (int i = 0; i < N; i++) d.v[i] = p->v[i];
 }
 
+// kInject steps (one start checkpoint to the next) on slots PF..LP-1, the
+// rows of steps t0 .. t0 + kInject - 1 of the pass written to LDS (PF = LP:
+// no slot live, zero rows).  t0 is even, so a step's parity is that of t.
+template <int LP, int FW, int PF, int RS>
+__device__ __forceinline__ void analys_half(AState<LP, FW>& s, const double (&b)[kInject], double* rows, int t0)
+{
+#pragma unroll
+    for (int t = 0; t < kInject; t += 2) {
+        double v0[FW], v1[FW];
+        if (PF < LP) {
+            analys_step_pair<LP, FW, PF>(s, b[t], b[t + 1], v0, v1);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FW; f++) v0[f] = v1[f] = 0.0;
+        }
+#pragma unroll
+        for (int f = 0; f < FW; f++) {
+            rows[((t0 + t) * FW + f) * RS] = v0[f];
+            rows[((t0 + t + 1) * FW + f) * RS] = v1[f];
+        }
+    }
+}
+
+// The half for the first live slot pf (wave-uniform).
+template <int LP, int FW, int RS>
+__device__ __forceinline__ void analys_half_from(int pf, AState<LP, FW>& s, const double (&b)[kInject],
+                                                 double* rows, int t0)
+{
+    // (pf <= LP; a case k >= LP is the no-live-slot variant: zero rows)
+    switch (pf) {
+    case 0: analys_half<LP, FW, 0, RS>(s, b, rows, t0); break;
+    case 1: analys_half<LP, FW, (1 < LP ? 1 : LP), RS>(s, b, rows, t0); break;
+    case 2: analys_half<LP, FW, (2 < LP ? 2 : LP), RS>(s, b, rows, t0); break;
+    case 3: analys_half<LP, FW, (3 < LP ? 3 : LP), RS>(s, b, rows, t0); break;
+    case 4: analys_half<LP, FW, (4 < LP ? 4 : LP), RS>(s, b, rows, t0); break;
+    case 5: analys_half<LP, FW, (5 < LP ? 5 : LP), RS>(s, b, rows, t0); break;
+    case 6: analys_half<LP, FW, (6 < LP ? 6 : LP), RS>(s, b, rows, t0); break;
+    case 7: analys_half<LP, FW, (7 < LP ? 7 : LP), RS>(s, b, rows, t0); break;
+    default: analys_half<LP, FW, LP, RS>(s, b, rows, t0); break;
+    }
+}
+
+// Start checkpoint cc: in the slots whose block has a lane starting there
+// (bits of mk, wave-uniform), the lanes whose start step is cc take their
+// stored state (kept in this lane's slots in LDS).
+template <int LP>
+__device__ __forceinline__ void start_slots(double (&ua)[LP], double (&ub)[LP], const int (&sj)[LP],
+                                            const double2 (*sy)[64], unsigned mk, int cc)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int p = 0; p < LP; p++) {
+        if (mk & (1u << p)) {
+            const double2 y = sy[p][lane];
+            const bool go = sj[p] == cc;
+            ua[p] = go ? y.x : ua[p];
+            ub[p] = go ? y.y : ub[p];
+        }
+    }
+}
+
 // The degrees of a unit run in passes of SC = kChunk / FW degrees.  In a pass
 // each lane pair's partial sums (one row per degree and field, one column
 // per thread: real parts in even columns, imaginary parts in odd ones) go to
 // LDS, while the sums of the previous pass are read back, added over the
 // columns (2W threads per output, padded rows) and stored: with several
 // waves the passes alternate between two buffers with one barrier per pass.
-// A workgroup of W waves covers
-// 64 LP W latitude pairs: wave w takes pairs [64 LP w, 64 LP (w + 1)); a wave
-// none of whose latitudes has started writes zero rows instead of computing.
+// A workgroup of W waves covers 64 LP W latitude pairs: wave w takes pairs
+// [64 LP w, 64 LP (w + 1)), pair slot p of its lanes being the 64-pair block
+// LP w + p.  A pass runs as halves of kInject steps; each half first injects
+// the start states of the blocks with lanes starting at its checkpoint, then
+// runs only the slots from the first one whose block has started (the polar
+// optimisation of Sec. 3.1 at the granularity of 64 latitudes).
 template <int LP, int FW, int W>
-__global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
-{
-    constexpr int SC = kChunk / FW;  // degrees per pass
-    constexpr int NR = SC * FW;      // rows per pass
-    constexpr int NT = 64 * W;       // threads = columns
-    constexpr int PR = 2 * W;        // threads per output (row, component)
-    constexpr int NK = NT / 2 / PR;  // columns each of them adds
+struct AnalysGeom {
+    static constexpr int SC = kChunk / FW;  // degrees per pass
+    static constexpr int NR = SC * FW;      // rows per pass
+    static constexpr int NT = 64 * W;       // threads = columns
+    static constexpr int PR = 2 * W;        // threads per output (row, component)
+    static constexpr int NK = NT / 2 / PR;  // columns each of them adds
     // row stride NT + 2 PR doubles: a thread's PR-wide column groups of
     // consecutive rows start 4 PR banks apart, so the 32 lanes of a half-wave
     // read distinct banks
-    constexpr int RS = NT + 2 * PR;
-    static_assert(2 * NR * PR == NT, "the threads cover the outputs");
-    static_assert(kSegLen % SC == 0, "passes tile a segment");
-    static_assert(SC % kInject == 0, "lanes start at pass boundaries or inside them");
+    static constexpr int RS = NT + 2 * PR;
+    static constexpr int NH = SC / kInject;  // halves per pass
     // One wave executes its LDS operations in order, so with W = 1 the reads
     // of the previous pass, issued before this pass's writes, need neither a
     // second buffer nor a barrier.
-    constexpr int NB = W == 1 ? 1 : 2;
-    __shared__ double red[NB][NR][RS];
-    __shared__ double2 start_y[W][LP][64];  // stored lane start states
+    static constexpr int NB = W == 1 ? 1 : 2;
+};
 
-    cip U = (cip)a.units + (size_t)blockIdx.x * kUnitInts;
+// One unit: degrees [j0, j1) of one order for all latitude pairs (the
+// workgroup's W waves), the outputs stored; uniform over the workgroup.
+template <int LP, int FW, int W>
+__device__ __forceinline__ void analys_unit(
+    const LegArgs& a, int ui,
+    double (&red)[AnalysGeom<LP, FW, W>::NB][AnalysGeom<LP, FW, W>::NR][AnalysGeom<LP, FW, W>::RS],
+    double2 (&start_y)[W][LP][64])
+{
+    using G = AnalysGeom<LP, FW, W>;
+    constexpr int SC = G::SC, NR = G::NR, NT = G::NT, PR = G::PR, NK = G::NK, RS = G::RS, NH = G::NH;
+    constexpr int NB = G::NB;
+    static_assert(2 * NR * PR == NT, "the threads cover the outputs");
+    static_assert(kSegLen % SC == 0, "passes tile a segment");
+    static_assert(SC % kInject == 0, "passes are whole halves");
+    static_assert(kInject % 2 == 0, "halves keep the step parity");
+    static_assert(LP <= 8 && LP * W <= kMaxMaskBlocks, "one mask word covers the unit's blocks");
+
+    cip U = (cip)a.units + (size_t)ui * kUnitInts;
     const int m = U[U_M];
     if (m < 0) return;
     const int field0 = U[U_FIELD] + blockIdx.y * FW;
@@ -566,11 +661,14 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int pb = wv * 64 * LP;  // first latitude pair of this wave
+    const int wb = wv * LP;       // its first 64-pair block
     const int j0 = U[U_PB], j1 = U[U_J1], js0 = U[U_JS], jwin = U[U_JW], rst = U[U_RST];
     const long base = (long)m * (2 * L + 1 - m) / 2 + m;
     const int nj = L - m + 1;
     cdp bet = (cdp)P->beta + base;
     cip segexp = (cip)P->segexp + ((cip)P->segoff)[m];
+    // per checkpoint: blocks with lanes starting there, blocks started
+    cip ckm = (cip)P->ck_mask + (size_t)m * P->nck * 2;
 
     long qoff[FW];
     long foff[FW];
@@ -595,7 +693,6 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
     AState<LP, FW> s;
     int sj[LP];
     const bool from_rst = rst >= 0 && js0 == j0;
-    int first = nj;  // first step at which a lane of this wave is live
     {
         const bool odd = lane & 1;
         int pc[LP], jv[LP];
@@ -635,8 +732,6 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
             s.x[p] = act[p] ? xv[p] : 0.0;
             s.ua[p] = act[p] ? r[p].x : 0.0;
             s.ub[p] = act[p] ? r[p].y : 0.0;
-            const bool live0 = from_rst && sj[p] < j0;
-            first = min(first, live0 ? js0 : sj[p]);
             // folded, weighted inputs; a lane that has not started holds a
             // zero state, so it adds exactly 0 whatever its inputs
             const bool middle = (nlat & 1) && pc[p] == npair - 1;
@@ -653,18 +748,15 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
             }
         }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o));
-    first = __builtin_amdgcn_readfirstlane(first);
 
     // Warm L2 with the beta entries of this unit (one word per 64-byte line
     // per lane, consumed at the end; see the synthesis kernel).
     __builtin_amdgcn_sched_barrier(0);
-    unsigned pf;
+    unsigned pf_sink;
     {
         const int nbytes = (j1 - js0 + 2 * SC) * 8;
         const int off = lane * 64;
-        pf = *(const unsigned*)((const char*)(P->beta + base + js0) + (off < nbytes ? off : 0));
+        pf_sink = *(const unsigned*)((const char*)(P->beta + base + js0) + (off < nbytes ? off : 0));
     }
     const double cm = (m == 0 || !a.adjoint) ? 1.0 : 2.0;
     const int o = tid / PR;        // output of this thread: (row, component)
@@ -675,22 +767,36 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
     const int col = wv * 64 + lane;  // this thread's column
     cdp gam_tab = (cdp)P->gamma + base;
 
-    // beta and the segment shift of the next pass are loaded one pass ahead
-    // (the beta table is padded past the last order).  A partial last pass
-    // runs all SC steps: the extra degrees belong to no output and are not
-    // stored.
-    DBlk<SC> bn;
-    load_blk(bn, bet + js0);
+    // beta is loaded one half ahead (the second half's while the first
+    // runs, the next pass's first half's after an explicit wait for the
+    // second), the segment shift and the start masks one pass ahead; the
+    // tables are padded past the last order.  Each explicit lgkmcnt(0) wait
+    // comes before the next scalar load is issued, so no wait drains a load
+    // just issued (scalar loads return out of order: a wait is always for
+    // all of them).  A partial last pass runs all SC steps: the extra
+    // degrees belong to no output and are not stored.
+    static_assert(NH == 1 || NH == 2, "one or two halves per pass");
+    DBlk<kInject> bh0, bh1;
+    load_blk(bh0, bet + js0);
+    DBlk2u<2 * NH> mkw;
+    load_u32(mkw, ckm + 2 * (js0 / kInject));
     int shn = 0;        // js0 is a segment start (the plan rounds it down)
     int buf = 0;
     for (int c = js0; c < j1 + SC; c += SC) {
         const bool compute = c < j1;
-        const DBlk<SC> b = bn;
         const int sh = shn;
         // The scalar loads above have arrived before the LDS reads of the
         // previous pass's sums are issued (one counter covers both kinds), so
         // the steps below wait on neither and the reads complete under them.
         __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_sched_barrier(0);
+        // this wave's slots: starting at each checkpoint, started by it
+        unsigned mk[NH], lv[NH];
+#pragma unroll
+        for (int hh = 0; hh < NH; hh++) {
+            mk[hh] = (mkw.v[2 * hh] >> wb) & ((1u << LP) - 1u);
+            lv[hh] = (mkw.v[2 * hh + 1] >> wb) & ((1u << LP) - 1u);
+        }
         double part[NK];
 #pragma unroll
         for (int k = 0; k < NK; k++) part[k] = red[(NB - 1) & (buf ^ 1)][row][2 * (k * PR + h) + comp];
@@ -698,30 +804,26 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
         const double gl = gam_tab[min(max(c - SC, js0) + t_out, j1 - 1)];
         if (compute) {
             const int cn = c + SC;
-            load_blk(bn, bet + cn);
+            // two halves: the second half's beta; one half: the next pass's
+            load_blk(bh1, bet + c + kInject);
+            load_u32(mkw, ckm + 2 * (cn / kInject));
             shn = (cn < j1 && cn % kSegLen == 0) ? segexp[cn / kSegLen] : 0;
+            __builtin_amdgcn_sched_barrier(0);
             if (sh != 0) rescale(s.ua, s.ub, sh);
-            if (c + SC <= first) {
-                // wave-uniform: no lane live in the pass
-#pragma unroll
-                for (int r = 0; r < NR; r++) red[buf][r][col] = 0.0;
-            } else if (c <= jwin) {
-#pragma unroll
-                for (int t = 0; t < SC; t++) {
-                    if (t % kInject == 0) start_lanes_lds(s.ua, s.ub, sj, start_y[wv], c + t);
-                    double v[FW];
-                    analys_step(s, t, b.v[t], v);
-#pragma unroll
-                    for (int f = 0; f < FW; f++) red[buf][t * FW + f][col] = v[f];
-                }
+            if (mk[0] != 0u && c <= jwin) start_slots(s.ua, s.ub, sj, start_y[wv], mk[0], c);
+            analys_half_from<LP, FW, RS>(lv[0] ? __builtin_ctz(lv[0]) : LP, s, bh0.v, &red[buf][0][col], 0);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (NH == 2) {
+                __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): bh1, the masks, the shift
+                __builtin_amdgcn_sched_barrier(0);
+                load_blk(bh0, bet + cn);
+                __builtin_amdgcn_sched_barrier(0);
+                const int c1 = c + kInject;
+                if (mk[1] != 0u && c1 <= jwin) start_slots(s.ua, s.ub, sj, start_y[wv], mk[1], c1);
+                analys_half_from<LP, FW, RS>(lv[1] ? __builtin_ctz(lv[1]) : LP, s, bh1.v, &red[buf][0][col],
+                                             kInject);
             } else {
-#pragma unroll
-                for (int t = 0; t < SC; t++) {
-                    double v[FW];
-                    analys_step(s, t, b.v[t], v);
-#pragma unroll
-                    for (int f = 0; f < FW; f++) red[buf][t * FW + f][col] = v[f];
-                }
+                bh0 = bh1;
             }
         }
         if (c > js0) {
@@ -747,7 +849,17 @@ __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
         buf = (NB - 1) & (buf ^ 1);
     }
     // keeps the prefetch load alive; nfields is never negative
-    if (a.nfields < 0) a.out[lane] = (double)pf;
+    if (a.nfields < 0) a.out[lane] = (double)pf_sink;
+}
+
+// One workgroup per unit.
+template <int LP, int FW, int W>
+__global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
+{
+    using G = AnalysGeom<LP, FW, W>;
+    __shared__ double red[G::NB][G::NR][G::RS];
+    __shared__ double2 start_y[W][LP][64];  // stored lane start states
+    analys_unit<LP, FW, W>(a, blockIdx.x, red, start_y);
 }
 
 // ---------------------------------------------------------------------------

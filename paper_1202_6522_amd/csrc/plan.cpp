@@ -1,6 +1,6 @@
 // Host-side plan construction: Gauss grid, recurrence tables, start values
 // with scaled exponents, analysis restart states, FFT twiddles and the work
-// unit lists.  Pure host code: no device calls.
+// unit lists.  Host code only.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -82,20 +82,31 @@ static int log2_floor(ld v)
 // Lane starts (Sec. 3.5 guard and Sec. 3.1 polar threshold, at plan time).
 // For each (order, latitude pair) the recurrence is followed from n = m in the
 // scaled form u = w 2^{-256 k} with the kernels' own steps (same segment
-// shifts, same fused multiply-adds).  The lane starts at the checkpoint
-// (multiple of kInject) that opens the first block of kInject steps in which
-// |P_n^m| reaches 2^polar_log2; the state entering that step, converted to a
-// plain double, is stored.  The conversion is exact while the state stays in
-// the normal range, which holds at the default threshold (the states lie
-// within about 2^-100 of it); for very low thresholds it need not, and
-// shtn_plan_set_polar refuses a threshold whose states fall below DBL_MIN
-// (min_start_state).  A lane that never reaches the threshold gets the start
-// step nj = lmax - m + 1.
-static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double& yb)
+// shifts, same fused multiply-adds), so values far below the range of double
+// are tracked exactly.
+//
+// A lane's own start is the checkpoint (multiple of kInject) that opens the
+// first block of kInject steps in which |P_n^m| reaches 2^polar_log2 (nj =
+// lmax - m + 1 if it never does).  The latitudes of one 64-pair block run in
+// the same pair slot of a wave, so a block is live from the earliest own
+// start among its lanes; every lane of the block starts there too, from its
+// exact state at that step, as long as that state is a normal double with
+// margin (each component 0 or of magnitude at least 2^kStartFloor), and
+// otherwise at the first later checkpoint where it is (no later than its
+// own start).  Starting early only adds terms below the threshold, and it
+// leaves most lanes of a block starting together: the kernels inject start
+// states at few checkpoints.
+constexpr int kStartFloor = -900;
+
+// Follows lane (m, i) and returns at the first checkpoint c >= c_lo where
+// `own` (the block of kInject steps from c reaches the threshold) or, if
+// !own, the entering state is representable; jst = nj if none.
+static void lane_walk(const Plan& p, int m, int i, int c_lo, bool own, int& jst, double& ya, double& yb)
 {
     const int nj = p.L - m + 1;
     const long base = lm_index(p.L, m, m);
     const double down = std::ldexp(1.0, -kGuardUnit);
+    const double floor_v = std::ldexp(1.0, kStartFloor);
     const double x = p.xp[i];
     double ua = p.start_y[(size_t)m * p.npair + i], ub = 0.0;
     int k = p.start_k[(size_t)m * p.npair + i];
@@ -109,6 +120,16 @@ static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double
         }
         const double sa = ua, sb = ub;
         const int sk = k;
+        if (!own && c >= c_lo) {
+            const double va = std::ldexp(sa, -kGuardUnit * sk), vb = std::ldexp(sb, -kGuardUnit * sk);
+            const bool ok_a = va == 0.0 || std::fabs(va) >= floor_v, ok_b = vb == 0.0 || std::fabs(vb) >= floor_v;
+            if (ok_a && ok_b && (va != 0.0 || vb != 0.0)) {
+                jst = c;
+                ya = va;
+                yb = vb;
+                return;
+            }
+        }
         bool sig = false;
         for (int j = c; j < std::min(c + kInject, nj); j += 2) {
             if (j % kGuardEvery == 0 && k > 0 && (std::fabs(ua) >= 1.0 || std::fabs(ub) >= 1.0)) {
@@ -127,7 +148,7 @@ static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double
                 if (e - (long)kGuardUnit * k >= p.polar_log2) sig = true;
             }
         }
-        if (sig) {
+        if (own && sig) {
             jst = c;
             ya = std::ldexp(sa, -kGuardUnit * sk);
             yb = std::ldexp(sb, -kGuardUnit * sk);
@@ -139,37 +160,82 @@ static void lane_start(const Plan& p, int m, int i, int& jst, double& ya, double
 void lane_starts(Plan& p)
 {
     const int M = p.M, np = p.npair;
+    const int nb = (np + kBlkPairs - 1) / kBlkPairs;
     p.inj_j.assign((size_t)(M + 1) * np, 0);
     p.inj_y.assign((size_t)(M + 1) * np * 2, 0.0);
     p.first_pair.assign(M + 1, 0);
+    std::vector<double> own_min(M + 1, 0.0);
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
     for (unsigned tid = 0; tid < nth; tid++) {
         pool.emplace_back([&, tid]() {
+            std::vector<int> own(np);
             for (int m = (int)tid; m <= M; m += (int)nth) {
                 const int nj = p.L - m + 1;
+                // own starts (the threshold), the first kept pair, and the
+                // smallest nonzero state there
                 int first = np;
+                double lo = 0.0;
                 for (int i = 0; i < np; i++) {
-                    const size_t q = (size_t)m * np + i;
-                    lane_start(p, m, i, p.inj_j[q], p.inj_y[2 * q], p.inj_y[2 * q + 1]);
-                    if (p.inj_j[q] < nj && first == np) first = i;
+                    double ya, yb;
+                    lane_walk(p, m, i, 0, true, own[i], ya, yb);
+                    if (own[i] < nj && first == np) first = i;
+                    for (double v : {ya, yb}) {
+                        const double a = std::fabs(v);
+                        if (a > 0.0 && (lo == 0.0 || a < lo)) lo = a;
+                    }
                 }
                 p.first_pair[m] = first;
+                own_min[m] = lo;
+                // block starts: each lane from its block's first own start
+                for (int b = 0; b < nb; b++) {
+                    const int i0 = b * kBlkPairs, i1 = std::min(np, i0 + kBlkPairs);
+                    int bfirst = nj;
+                    for (int i = i0; i < i1; i++) bfirst = std::min(bfirst, own[i]);
+                    for (int i = i0; i < i1; i++) {
+                        const size_t q = (size_t)m * np + i;
+                        if (bfirst >= nj) {
+                            p.inj_j[q] = nj;
+                            p.inj_y[2 * q] = p.inj_y[2 * q + 1] = 0.0;
+                        } else {
+                            lane_walk(p, m, i, bfirst, false, p.inj_j[q], p.inj_y[2 * q], p.inj_y[2 * q + 1]);
+                        }
+                    }
+                }
             }
         });
     }
     for (auto& th : pool) th.join();
+    p.min_own_state = 0.0;
+    for (double v : own_min)
+        if (v > 0.0 && (p.min_own_state == 0.0 || v < p.min_own_state)) p.min_own_state = v;
+    // per 64-pair block: first start step and the checkpoints with starts
+    // (the mask holds 32 blocks; plans with more pairs leave it 0 beyond,
+    // the kernels that read it cover at most kMaxMaskBlocks blocks)
+    const int nck = (p.L + 2 * kChunk) / kInject + 2;  // checkpoints of order 0, padded for loads a pass ahead
+    p.nblk = nb;
+    p.nck = nck;
+    p.blk_first.assign((size_t)(M + 1) * nb, 0);
+    p.ck_mask.assign((size_t)(M + 1) * nck * 2, 0u);
+    for (int m = 0; m <= M; m++) {
+        const int nj = p.L - m + 1;
+        unsigned* ck = &p.ck_mask[(size_t)m * nck * 2];
+        for (int b = 0; b < nb; b++) {
+            int first = nj;
+            for (int i = b * kBlkPairs; i < std::min(np, (b + 1) * kBlkPairs); i++) {
+                const int j = p.inj_j[(size_t)m * np + i];
+                if (j >= nj) continue;
+                first = std::min(first, j);
+                if (b < kMaxMaskBlocks) ck[2 * (j / kInject)] |= 1u << b;
+            }
+            p.blk_first[(size_t)m * nb + b] = first;
+            if (b < kMaxMaskBlocks && first < nj)
+                for (int k = first / kInject; k < nck; k++) ck[2 * k + 1] |= 1u << b;
+        }
+    }
 }
 
-double min_start_state(const Plan& p)
-{
-    double lo = 0.0;
-    for (double v : p.inj_y) {
-        const double a = std::fabs(v);
-        if (a > 0.0 && (lo == 0.0 || a < lo)) lo = a;
-    }
-    return lo;
-}
+double min_start_state(const Plan& p) { return p.min_own_state; }
 
 Plan* build_plan(int L, int M, int nlat, int nphi, std::string& err)
 {
@@ -349,6 +415,35 @@ bool start_range(const Plan& p, int m, int i0, int i1, int lo, int hi, int& jmin
     return any;
 }
 
+// Time of an analysis unit covering steps [js, j1) of order m, in ns on
+// MI355X (two waves per SIMD), as measured per unit: about 4.6 us of set-up,
+// then per half pass (kInject steps) 0.32 us plus 0.1 us per live pair slot
+// (slots whose 64-pair block has started) plus 0.46 us when start states are
+// injected.  The waves of a unit keep pace, so the busiest one counts.  Used
+// to order the pieces and to deal the orders to the XCDs.
+static long analys_unit_cost(const Plan& p, int m, int js, int j1)
+{
+    const int lp = p.tiling.analys_lp, waves = p.tiling.analys_waves;
+    const int* bf = &p.blk_first[(size_t)m * p.nblk];
+    const unsigned* ck = &p.ck_mask[(size_t)m * p.nck * 2];
+    const unsigned wmask = lp >= 32 ? ~0u : (1u << lp) - 1u;
+    long cost = 4600;
+    for (int c = js; c < j1; c += kInject) {
+        long worst = 0;
+        for (int w = 0; w < waves; w++) {
+            int k = 0;
+            for (int q = 0; q < lp; q++) {
+                const int b = w * lp + q;
+                if (b < p.nblk && bf[b] <= c) k++;
+            }
+            const bool inj = ((ck[2 * (c / kInject)] >> (w * lp)) & wmask) != 0u;
+            worst = std::max(worst, 320L + 100L * k + (inj ? 460L : 0L));
+        }
+        cost += worst;
+    }
+    return cost;
+}
+
 int rebuild_units(Plan& p, std::string& err)
 {
     const Tiling& t = p.tiling;
@@ -391,76 +486,88 @@ int rebuild_units(Plan& p, std::string& err)
         p.synth_wpg = wpg;
     }
 
-    // ---- analysis units: (m, degree range) pieces, longest first ----
+    // ---- analysis units: (m, degree range) pieces of S degrees ----
+    // Workgroup b runs on XCD b % kXcds.  All pieces of one order go to one
+    // XCD, so the inputs and start states they share come from that XCD's
+    // L2; orders are dealt largest first to the XCD with the least work so
+    // far, each XCD runs its pieces longest first (the hardware hands the
+    // next piece to the first free slot, so the short ones fill the tail),
+    // and the shorter XCD queues are padded with units without work.
     int S = t.split;
     if (S <= 0) {
-        // about two units per SIMD at large sizes (256 at lmax 1023)
-        long target = p.nlm / 2048;
+        // about two pieces per SIMD at large sizes (256 at lmax 1023)
+        const long target = p.nlm / 2048;
         S = (int)std::max<long>(64, (target / kSegLen) * kSegLen);
     }
     if (S % kSegLen) { err = "split must be a multiple of 32"; return -1; }
     p.split_used = S;
     struct AU { int m, j0, j1, js, jw, rst; long cost; };
-    std::vector<AU> au;
-    std::vector<std::vector<int>> rj(M + 1);
-    int nrst = 0;
-    std::vector<int> rbase(M + 1, 0);
+    std::vector<std::vector<int>> rj(M + 1);  // restart steps of each order, ascending
+    auto make_piece = [&](int m, int j0, int j1) {
+        int jmin, jmax;
+        // lanes started before j0 are live from the restart state; the piece
+        // may skip ahead (in whole segments) to its first start
+        const bool live0 = start_range(p, m, 0, np, 0, j0 + (j0 == 0 ? 1 : 0), jmin, jmax);
+        int js, jw;
+        if (live0) {
+            js = j0;
+            jw = start_range(p, m, 0, np, j0, j1, jmin, jmax) ? jmax : j0;
+        } else if (start_range(p, m, 0, np, j0, j1, jmin, jmax)) {
+            js = j0 + ((jmin - j0) / kSegLen) * kSegLen;
+            jw = jmax;
+        } else {
+            js = j1;  // nothing starts: the piece only writes zeros
+            jw = j1;
+        }
+        int r = -1;
+        if (j0 > 0) {
+            r = (int)rj[m].size();
+            rj[m].push_back(j0);
+        }
+        return AU{m, j0, j1, js, jw, r, js < j1 ? analys_unit_cost(p, m, js, j1) : 0};
+    };
+    std::vector<std::vector<AU>> pieces(M + 1);
+    std::vector<long> mcost(M + 1, 0);
     for (int m = 0; m <= M; m++) {
-        int nj = L - m + 1;
-        rbase[m] = nrst;
+        const int nj = L - m + 1;
         for (int j0 = 0; j0 < nj; j0 += S) {
-            const int j1 = std::min(j0 + S, nj);
-            int r = -1;
-            if (j0 > 0) { r = nrst++; rj[m].push_back(j0); }
-            // lanes started before j0 are live from the restart state; the
-            // unit may skip ahead (in whole segments) to its first start
-            int jmin, jmax;
-            bool live0 = start_range(p, m, 0, np, 0, j0 + (j0 == 0 ? 1 : 0), jmin, jmax);
-            int js, jw;
-            if (live0) {
-                js = j0;
-                jw = start_range(p, m, 0, np, j0, j1, jmin, jmax) ? jmax : j0;
-            } else if (start_range(p, m, 0, np, j0, j1, jmin, jmax)) {
-                js = j0 + ((jmin - j0) / kSegLen) * kSegLen;
-                jw = jmax;
-            } else {
-                js = j1;  // nothing starts: the unit only writes zeros
-                jw = j1;
-            }
-            au.push_back({m, j0, j1, js, jw, r, (long)(j1 - js) + 4});
+            pieces[m].push_back(make_piece(m, j0, std::min(j0 + S, nj)));
+            mcost[m] += pieces[m].back().cost;
         }
     }
-    std::stable_sort(au.begin(), au.end(), [](const AU& a, const AU& b) { return a.cost > b.cost; });
-    // Workgroup b runs on XCD b % kXcds.  All units of one order go to one
-    // XCD, so the inputs and start states they share come from that XCD's
-    // L2; orders are dealt largest first to the XCD with the least work so
-    // far, each XCD runs its units longest first, and the shorter XCD queues
-    // are padded with units without work.
-    std::vector<long> mcost(M + 1, 0);
-    for (auto& a : au) mcost[a.m] += a.cost;
     std::vector<int> ms(M + 1);
     for (int m = 0; m <= M; m++) ms[m] = m;
     std::stable_sort(ms.begin(), ms.end(), [&](int a, int b) { return mcost[a] > mcost[b]; });
-    std::vector<int> xcd_of(M + 1, 0);
-    long xload[kXcds] = {0};
-    for (int m : ms) {
-        int x = 0;
-        for (int k = 1; k < kXcds; k++)
-            if (xload[k] < xload[x]) x = k;
-        xload[x] += mcost[m];
-        xcd_of[m] = x;
+    std::vector<std::vector<AU>> xq(kXcds);
+    {
+        long xload[kXcds] = {0};
+        for (int m : ms) {
+            int x = 0;
+            for (int k = 1; k < kXcds; k++)
+                if (xload[k] < xload[x]) x = k;
+            xload[x] += mcost[m];
+            xq[x].insert(xq[x].end(), pieces[m].begin(), pieces[m].end());
+        }
     }
-    std::vector<std::vector<int>> xq(kXcds);
-    for (size_t i = 0; i < au.size(); i++) xq[xcd_of[au[i].m]].push_back((int)i);
+    for (auto& q : xq)
+        std::stable_sort(q.begin(), q.end(), [](const AU& a, const AU& b) { return a.cost > b.cost; });
+    // restart slots: order by order, each order's restart steps ascending
+    int nrst = 0;
+    std::vector<int> rbase(M + 1, 0);
+    for (int m = 0; m <= M; m++) {
+        rbase[m] = nrst;
+        nrst += (int)rj[m].size();
+    }
+    p.analys_units.clear();
     size_t qlen = 0;
     for (auto& q : xq) qlen = std::max(qlen, q.size());
-    p.analys_units.clear();
     for (size_t k = 0; k < qlen; k++) {
         for (int x = 0; x < kXcds; x++) {
             int u[kUnitInts] = {0, t.fw, 0, -1, 0, 0, 0, 0, -1, 0, 0, 0};
             if (k < xq[x].size()) {
-                const AU& a = au[xq[x][k]];
-                const int v[kUnitInts] = {0, t.fw, 0, a.m, a.js, a.jw, a.j0, a.j1, a.rst, 0, 0, 0};
+                const AU& a = xq[x][k];
+                const int v[kUnitInts] = {0, t.fw, 0, a.m, a.js, a.jw, a.j0, a.j1,
+                                          a.rst >= 0 ? rbase[a.m] + a.rst : -1, 0, 0, 0};
                 std::copy(v, v + kUnitInts, u);
             }
             p.analys_units.insert(p.analys_units.end(), u, u + kUnitInts);
@@ -543,6 +650,7 @@ void build_image(Plan& p)
     place(TB_RTW, p.rtw);
     place(TB_SYNTH_UNITS, p.synth_units);
     place(TB_ANALYS_UNITS, p.analys_units);
+    place(TB_CK_MASK, p.ck_mask);
     p.image.resize(off, 0);
 }
 

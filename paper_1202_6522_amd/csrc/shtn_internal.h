@@ -29,10 +29,12 @@ constexpr int kGuardEvery = 4;
 // |P_n^m| < 2^kPolarLog2 are dropped (the default; a plan may raise the
 // threshold, trading accuracy for work, see Plan::polar_log2).  A lane starts at the first checkpoint
 // (a multiple of kInject steps) of the block of kInject steps in which its
-// |P_n^m| first reaches 2^kPolarLog2; before it the lane holds 0, so it adds
-// exactly 0 and the kernels carry no exponent.  The host stores the state
-// (u_{j-2}, u_{j-1}) entering that step as plain doubles.  A latitude that
-// never reaches the threshold for an order never starts.
+// |P_n^m| first reaches 2^kPolarLog2 -- or earlier, at the first start of
+// its 64-pair block, when its state there is a normal double (see
+// lane_starts); before its start the lane holds 0, so it adds exactly 0 and
+// the kernels carry no exponent.  The host stores the state (u_{j-2},
+// u_{j-1}) entering that step as plain doubles.  A block none of whose
+// latitudes reaches the threshold for an order never starts.
 constexpr int kPolarLog2 = -200;
 constexpr int kInject = 8;
 // Analysis accumulates kChunk consecutive degrees per lane before a
@@ -89,8 +91,20 @@ enum DevTable {
     TB_RTW,
     TB_SYNTH_UNITS,
     TB_ANALYS_UNITS,
+    TB_CK_MASK,
     TB_COUNT
 };
+
+// Lane-start summaries per block of 64 latitude pairs (the pair slot of a
+// wave lane: pairs [64 b, 64 b + 64) form block b).  blk_first[m][b]: the
+// first start step of the block's lanes of order m (nj if none starts; host
+// only).  ck_mask[m][2 k]: bit b set iff some lane of block b starts at the
+// checkpoint j = kInject k; ck_mask[m][2 k + 1]: bit b set iff some lane of
+// block b has started at or before it.  A kernel skips the slots whose block
+// has not started and injects start states only into the blocks whose bit is
+// set.
+constexpr int kBlkPairs = 64;
+constexpr int kMaxMaskBlocks = 32;  // blocks one 32-bit mask covers (2048 pairs)
 
 // Device-resident view of a plan (stored at the start of its device buffer).
 struct DevPlan {
@@ -108,6 +122,8 @@ struct DevPlan {
     const double* rtw;     // [K+1] complex e^{+2 pi i m / (2K)}
     const int* synth_units;
     const int* analys_units;
+    const unsigned* ck_mask;  // [(M+1) * nck * 2] per checkpoint: blocks starting there, blocks started
+    int nblk, nck;
     int L, M, nlat, nphi, npair, K;
     long nlm;
     int n_synth_units, n_analys_units;
@@ -122,7 +138,7 @@ struct Tiling {
     int analys_waves = 1;  // waves per analysis unit
     int fw = 1;
     int m_pairing = 0;  // synthesis: 1 = orders m and M-m share a workgroup
-    int split = 0;     // 0 = automatic
+    int split = 0;     // analysis: pieces of this many degrees, 0 = automatic
     int fft_rows = 0;  // latitude rows per FFT workgroup, 0 = automatic
 };
 
@@ -161,6 +177,10 @@ struct Plan {
     std::vector<double> tw, rtw;
     std::vector<int> synth_units, analys_units;
     std::vector<int> first_pair;              // per m: first latitude pair kept by the polar cut
+    double min_own_state = 0.0;               // see min_start_state
+    std::vector<int> blk_first;               // (M+1) x nblk, see TB_BLK_FIRST
+    std::vector<unsigned> ck_mask;            // (M+1) x nck x 2, see TB_CK_MASK
+    int nblk = 0, nck = 0;
     // device image
     std::vector<unsigned char> image;  // staged device buffer contents
     std::vector<size_t> table_off;     // byte offsets of each table inside the image
@@ -174,8 +194,9 @@ struct Plan {
     // from its lane starts compare it to refuse stale copies.
     unsigned long gen = 0;
 };
-// Smallest nonzero |state| among the stored lane starts (inj_y), or 0 if all
-// are 0: below DBL_MIN a start state is a denormal that has lost precision.
+// Smallest nonzero |state| at the lanes' own threshold starts, or 0 if
+// none: below DBL_MIN a start state at the threshold would be a denormal
+// that has lost precision (the threshold is then too low for the plan).
 double min_start_state(const Plan& p);
 void ptable_layout(Plan& p);  // geometry of the stored-P table
 

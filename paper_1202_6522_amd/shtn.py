@@ -211,7 +211,7 @@ def shtn_legendre_flops(h):
 _TABLE_DTYPES = {0: np.float64, 1: np.float64, 2: np.float64, 3: np.float64, 4: np.float64,
                  5: np.float64, 6: np.int32, 7: np.int32, 8: np.int32, 9: np.float64,
                  10: np.int32, 11: np.int32, 12: np.int32, 13: np.int32, 14: np.int32,
-                 15: np.int32, 16: np.float64}
+                 15: np.int32, 16: np.float64, 17: np.int32, 18: np.uint32}
 
 UNIT_INTS = 12  # ints per work unit in tables 11 and 12
 

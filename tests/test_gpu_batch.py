@@ -256,9 +256,9 @@ def small_batch(dev, seed=3):
 
 def test_batch_refuses_a_changed_plan(dev):
     # A plan of the batch re-uploaded with another polar threshold (its
-    # tables move and its lane starts change): batch calls and replays are
-    # refused until the batch is uploaded again, which rebuilds its unit
-    # tables; the results then follow the plan's new state.
+    # tables move): batch calls and replays are refused until the batch is
+    # uploaded again, which rebuilds its unit tables; the results then
+    # follow the plan's new state.
     from paper_1202_6522_amd import shtn as S
     b, Qp, specs = small_batch(dev)
     g = b.new_grids()
@@ -278,9 +278,10 @@ def test_batch_refuses_a_changed_plan(dev):
     for f, s in enumerate(SMALL):
         ref = b.plans[s].synth(b.field_spectrum(Qp, f).view(1, -1))[0]
         assert torch.equal(b.field_grid(gb, f), ref), f
-    # the threshold of 2^-20 moves the changed field's result
-    fresh = S.Plan(*SMALL[1], device=dev)
-    assert not torch.equal(b.field_grid(gb, 1), fresh.synth(b.field_spectrum(Qp, 1).view(1, -1))[0])
+    # (the threshold acts per block of 64 latitude pairs; this plan has one
+    # block per order, holding an equator lane that starts at degree 0, so
+    # its result does not move: what matters is the refusal until upload)
+    assert plan.polar_log2() == -20
 
 
 def test_tuner_ignores_damaged_cache_entries(dev, tmp_path):

@@ -303,7 +303,9 @@ def _emulate_orders(t, L, M, nlat, Q, ms):
 
 
 def test_emulated_values_stay_in_range():
-    # once started, the carried values stay far from under- and overflow
+    # once started, the carried values stay far from under- and overflow:
+    # lanes start from states of at least 2^-900 (the block start rule), and
+    # the recurrence dips at most a few binary orders below its start
     L = 1023
     h = S.shtn_plan(L, L, L + 1, 2048)
     try:
@@ -316,19 +318,25 @@ def test_emulated_values_stay_in_range():
                 if v.size:
                     lo, hi = min(lo, v.min()), max(hi, v.max())
             assert hi < 1e3, (m, hi)
-            assert lo > 2.0**-900, (m, lo)
+            assert lo > 2.0**-960, (m, lo)
     finally:
         S.shtn_plan_destroy(h)
 
 
 @pytest.mark.parametrize("thr", [-200, -40])
 def test_lane_starts_against_long_double_oracle(thr):
-    # Sec. 3.5 guard and Sec. 3.1 polar threshold at plan time: before its
-    # start step a lane's |P_n^m| stays below 2^thr, the block of 8 steps
-    # from its start reaches it, and the stored state continues the
-    # recurrence onto the true P_n^m (long-double oracle, whose exponent
-    # range covers these values at lmax 1023).  thr = -200 is the default;
-    # -40 a raised threshold set with shtn_plan_set_polar.
+    # Sec. 3.5 guard and Sec. 3.1 polar threshold at plan time, checked with
+    # the long-double oracle (its exponent range covers these values at
+    # lmax 1023).  A lane's own start is the checkpoint (multiple of 8) that
+    # opens the first block of 8 steps in which |P_n^m| reaches 2^thr; a
+    # block of 64 latitude pairs starts at the earliest own start of its
+    # lanes, and its lanes start there too when their state is a normal
+    # double of at least 2^-900, else later (never after their own start).
+    # So: no dropped term reaches the threshold, each started block's first
+    # start is where one of its lanes first reaches it, a later start in a
+    # block only follows a negligible state, and the stored state continues
+    # the recurrence onto the true P_n^m.  thr = -200 is the default; -40 a
+    # raised threshold set with shtn_plan_set_polar.
     L, nlat = 1023, 1024
     h = S.shtn_plan(L, L, nlat, 2048)
     if thr != -200:
@@ -339,79 +347,147 @@ def test_lane_starts_against_long_double_oracle(thr):
         x = t[T_XP]
         sj = t[T_INJJ].reshape(L + 1, npair)
         sy = t[T_INJY].reshape(L + 1, npair, 2)
-        first = t[T_FIRST]
         for m in (0, 5, 200, 512, 800, 1000, 1023):
             nj = L - m + 1
             base = oracle.lm_index(L, m, m)
-            i0 = int(first[m])
-            assert np.all(sj[m, :i0] == nj)         # cut pairs never start
-            assert np.all(sj[m, i0:] < nj) and np.all(sj[m, i0:] % 8 == 0)
-            for i in sorted({i0, min(i0 + 1, npair - 1), (i0 + npair) // 2, npair - 1} - {npair}):
+            assert np.all((sj[m] % 8 == 0) | (sj[m] == nj))
+            Pall = np.abs(oracle.plm_raw(L, [m], x, precision="ld")[0, m:, :]).astype(np.float64)
+            # the 8-step block maxima of |P| per checkpoint and pair
+            nck = (nj + 7) // 8
+            pad = np.zeros((nck * 8, npair))
+            pad[:nj] = Pall
+            bmax = pad.reshape(nck, 8, npair).max(axis=1)
+            for b in range(npair // 64):
+                lanes = slice(64 * b, 64 * b + 64)
+                own = np.array([np.argmax(bmax[:, i] >= 2.0**(thr - 1)) * 8 if np.any(bmax[:, i] >= 2.0**(thr - 1))
+                                else nj for i in range(64 * b, 64 * b + 64)])
+                starts = sj[m, lanes]
+                if starts.min() >= nj:
+                    # a block that never starts: no lane of it reaches the threshold
+                    assert np.all(bmax[:, lanes] < 2.0**thr), (m, b)
+                    continue
+                b0 = starts.min()
+                # (the plan compares binary exponents: the threshold is met
+                # from 2^(thr-1) on; the oracle may differ by a rounding there)
+                assert abs(b0 - own.min()) <= 8, (m, b, b0, own.min())
+                for i in range(64 * b, 64 * b + 64):
+                    j = int(sj[m, i])
+                    if j < nj:
+                        assert np.all(Pall[:j, i] < 2.0**thr), (m, i)
+                    else:
+                        assert np.all(Pall[:, i] < 2.0**thr), (m, i)
+                    if j > b0:
+                        assert Pall[b0, i] < 2.0**-800, (m, i, j, b0, Pall[b0, i])
+            # two steps from the stored state, at a few lanes of each kind
+            for i in sorted({int(np.argmin(sj[m])), npair - 1, npair // 2, int(np.argmax(np.where(sj[m] < nj, sj[m], -1)))}):
                 j = int(sj[m, i])
-                P = oracle.plm(L, m, np.array([x[i]]), precision="ld")[:, 0]
-                Pm = np.abs(P[base:base + nj])
-                assert np.all(Pm[:j] < 2.0**thr), (m, i)
-                # (the plan compares binary exponents: the threshold is met from 2^(thr-1) on)
-                assert Pm[j:j + 8].max() >= 2.0**(thr - 1), (m, i)
-                # two steps from the stored state
+                if j >= nj:
+                    continue
+                P = oracle.plm_raw(L, [m], np.array([x[i]]), precision="ld")[0, m:, 0].astype(np.float64)
                 ua, ub = sy[m, i]
                 ua = x[i] * ub + t[T_BETA][base + j] * ua
                 got = [ua * t[T_GAMMA][base + j]]
                 if j + 1 < nj:
                     ub = x[i] * ua + t[T_BETA][base + j + 1] * ub
                     got.append(ub * t[T_GAMMA][base + j + 1])
-                ref = P[base + j:base + j + len(got)]
-                np.testing.assert_allclose(got, ref, rtol=1e-11)
+                ref = P[j:j + len(got)]
+                # Near the pole |P| grows slowly with n, so the next value is
+                # the difference of two nearly equal terms and the rounding of
+                # the stored pair is amplified (up to ~1e-10 relative for a
+                # lane that starts at ~2^-890); a wrong state is off by O(1).
+                np.testing.assert_allclose(got, ref, rtol=1e-9)
     finally:
         S.shtn_plan_destroy(h)
 
 
-def test_restart_states_match_recurrence():
+def _check_analysis_units(h, t, L, npair):
+    """Pieces cover every order's degrees once, start where they may, hold
+    the right restart slots; workgroup b runs on XCD b % 8, every order stays
+    on one XCD, each XCD runs its pieces longest first (by the plan's time
+    model) and the XCDs carry about equal work."""
+    til = t[T_TIL]
+    au = t[T_AU].reshape(-1, UI)
+    sj = t[T_INJJ].reshape(L + 1, npair)
+    lp, waves, nb = int(til[1]), int(til[6]), (npair + 63) // 64
+    bf = S.shtn_plan_table(h, 17).reshape(L + 1, nb)
+    ck = S.shtn_plan_table(h, 18).reshape(L + 1, -1, 2)
+    bfw = np.full((L + 1, waves * lp), 1 << 30)
+    bfw[:, :min(nb, waves * lp)] = bf[:, :waves * lp]
+    bfw = bfw.reshape(L + 1, waves, lp)
+
+    def unit_cost(u):
+        # ns: 4600 set-up, per half pass of 8 steps 320 + 100 per pair slot
+        # whose 64-pair block has started + 460 if start states are injected
+        # (the busiest of the unit's waves of analys_lp slots each)
+        m, js, j1 = int(u[U_M]), int(u[U_JS]), int(u[U_J1])
+        if js >= j1:
+            return 0
+        tot = 4600
+        for c in range(js, j1, 8):
+            k = np.sum(bfw[m] <= c, axis=1)
+            inj = np.array([(int(ck[m, c // 8, 0]) >> (w * lp)) & ((1 << lp) - 1) != 0 for w in range(waves)])
+            tot += int(np.max(320 + 100 * k + 460 * inj))
+        return tot
+
+    xcd = np.arange(len(au)) % 8
+    real = au[:, U_M] >= 0
+    load = np.zeros(8)
+    for x in range(8):
+        q = au[(xcd == x) & real]
+        cost = np.array([unit_cost(u) for u in q])
+        assert np.all(np.diff(cost) <= 0), "units are ordered longest first"
+        load[x] = cost.sum()
+    # orders dealt largest first to the least loaded XCD: within one order's
+    # cost of each other
+    mcost = np.zeros(L + 1)
+    for u in au[real]:
+        mcost[int(u[U_M])] += unit_cost(u)
+    assert load.max() - load.min() <= mcost.max() + 1
+    assert np.all(au[~real][:, U_M] == -1)
+    xcd = xcd[real]
+    au = au[real]
+    for m in range(L + 1):
+        assert len(set(xcd[au[:, U_M] == m])) == 1
+    cover = {}
+    for u in au:
+        m, js, jw, j0, j1, r = (int(v) for v in u[[U_M, U_JS, U_JW, U_PB, U_J1, U_RST]])
+        cover.setdefault(m, []).append((j0, j1))
+        assert (r < 0) == (j0 == 0)
+        assert j0 % 32 == 0
+        # the unit starts at a segment boundary no later than its first
+        # started lane, and its window covers every start inside it
+        assert j0 <= js <= j1 and (js - j0) % 32 == 0
+        lanes = sj[m]
+        assert not np.any((lanes >= j0) & (lanes < js)) or js == j0
+        inside = lanes[(lanes >= js) & (lanes < j1)]
+        if inside.size:
+            assert jw >= inside.max()
+        if js > j0:
+            assert not np.any(lanes < js)
+    for m in range(L + 1):
+        segs = sorted(cover[m])
+        assert segs[0][0] == 0 and segs[-1][1] == L - m + 1
+        assert all(a[1] == b[0] for a, b in zip(segs, segs[1:]))
+    return au
+
+
+@pytest.mark.parametrize("split", [0, 128])
+def test_restart_states_match_recurrence(split):
     L = 255
+    npair = 128
     h = S.shtn_plan(L, L, 256, 512)
     try:
+        if split:
+            S.shtn_plan_set_tiling(h, 1, 2, 1, 1, 0, split, 0)
         t = _tables(h)
-        til = t[T_TIL]
-        split = int(til[4])
-        au = t[T_AU].reshape(-1, UI)
-        npair = 128
+        # (0: automatic, 64-degree pieces at lmax 255)
+        assert int(t[T_TIL][4]) == (split or 64)
+        au = _check_analysis_units(h, t, L, npair)
         sj = t[T_INJJ].reshape(L + 1, npair)
-        # every order's degree range is covered exactly once
-        # workgroup b runs on XCD b % 8: each XCD runs its units longest
-        # first, all units of one order on one XCD, padding units without work
-        xcd = np.arange(len(au)) % 8
-        real = au[:, U_M] >= 0
-        for x in range(8):
-            q = au[(xcd == x) & real]
-            cost = q[:, U_J1] - q[:, U_JS]
-            assert np.all(np.diff(cost) <= 0), "units are ordered longest first"
-        for m in range(L + 1):
-            assert len(set(xcd[au[:, U_M] == m])) == 1
-        assert np.all(au[~real][:, U_M] == -1)
-        au = au[real]
-        cover = {}
-        for u in au:
-            m, js, jw, j0, j1, r = (int(v) for v in u[[U_M, U_JS, U_JW, U_PB, U_J1, U_RST]])
-            cover.setdefault(m, []).append((j0, j1))
-            assert (r < 0) == (j0 == 0)
-            assert j0 % split == 0
-            # the unit starts at a segment boundary no later than its first
-            # started lane, and its window covers every start inside it
-            assert j0 <= js <= j1 and (js - j0) % 32 == 0
-            lanes = sj[m]
-            assert not np.any((lanes >= j0) & (lanes < js)) or js == j0
-            inside = lanes[(lanes >= js) & (lanes < j1)]
-            if inside.size:
-                assert jw >= inside.max()
-            if js > j0:
-                assert not np.any(lanes < js)
-        for m in range(L + 1):
-            segs = sorted(cover[m])
-            assert segs[0][0] == 0 and segs[-1][1] == L - m + 1
-            assert all(a[1] == b[0] for a, b in zip(segs, segs[1:]))
         # a restart state equals the recurrence run from the lane starts
         ry = t[T_RSTY].reshape(-1, npair, 2)
         assert t[T_RSTK].size == 0
+        assert au[au[:, U_RST] >= 0].shape[0] > 0
         for u in au[au[:, U_RST] >= 0][:6]:
             m, j0, r = int(u[U_M]), int(u[U_PB]), int(u[U_RST])
             last = {}
@@ -424,6 +500,18 @@ def test_restart_states_match_recurrence():
                 want = np.where(live, last[k] * sc, 0.0)
                 np.testing.assert_allclose(ry[r, :, k], want, rtol=0,
                                            atol=1e-12 * max(np.max(np.abs(want)), 1e-300))
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(1023, 1023, 1024, 2048), (511, 511, 512, 1024)])
+def test_analysis_units_at_workload_sizes(shape):
+    # automatic pieces (256 degrees at lmax 1023), coverage, order per XCD
+    L, M, nlat, nphi = shape
+    h = S.shtn_plan(L, M, nlat, nphi)
+    try:
+        t = _tables(h)
+        _check_analysis_units(h, t, L, (nlat + 1) // 2)
     finally:
         S.shtn_plan_destroy(h)
 
@@ -555,6 +643,44 @@ def test_polar_threshold_setting():
         again = _tables(h)
         for k in (T_INJJ, T_INJY, T_FIRST, T_AU, T_SU, T_RSTY):
             assert np.array_equal(again[k], base[k]), k
+    finally:
+        S.shtn_plan_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(63, 40, 65, 128), (255, 255, 256, 512), (1023, 1023, 1024, 2048),
+                                   (300, 300, 2100, 1024)])
+def test_block_start_tables(shape):
+    # Tables 17 and 18 summarise the lane starts (table 15) per block of 64
+    # latitude pairs: the first start step of each block, and per checkpoint
+    # (every 8 steps) the blocks with a lane starting there and the blocks
+    # with a lane started by then.  The analysis kernel runs only the pair
+    # slots of started blocks and injects start states only where a bit is
+    # set, so these must agree exactly with the lane starts.
+    L, M, nlat, nphi = shape
+    h = S.shtn_plan(L, M, nlat, nphi)
+    try:
+        npair = (nlat + 1) // 2
+        nb = (npair + 63) // 64
+        inj = S.shtn_plan_table(h, 15).reshape(M + 1, npair)
+        bf = S.shtn_plan_table(h, 17).reshape(M + 1, nb)
+        ck = S.shtn_plan_table(h, 18).reshape(M + 1, -1, 2)
+        nck = ck.shape[1]
+        assert nck == (L + 32) // 8 + 2
+        for m in range(M + 1):
+            nj = L - m + 1
+            for b in range(nb):
+                js = inj[m, 64 * b:64 * (b + 1)]
+                started = js[js < nj]
+                assert bf[m, b] == (started.min() if started.size else nj)
+                if b >= 32:
+                    continue
+                bit = np.uint32(1 << b)
+                starts_at = np.zeros(nck, bool)
+                starts_at[np.unique(started // 8)] = True
+                assert np.all(started % 8 == 0)
+                assert np.array_equal((ck[m, :, 0] & bit) != 0, starts_at)
+                k = np.arange(nck)
+                assert np.array_equal((ck[m, :, 1] & bit) != 0, (8 * k >= bf[m, b]) & (bf[m, b] < nj))
     finally:
         S.shtn_plan_destroy(h)
 
