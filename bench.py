@@ -35,19 +35,33 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(kernel_name, launches_bytes_scale=None):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCE = {"legendre_synth": "legendre.hip", "legendre_analys": "legendre.hip", "prescale": "legendre.hip",
+                 "c2r": "fft.hip", "r2c": "fft.hip"}
+
+
+def _summary(file_name, kernel_name, field):
+    """A per-launch figure from a committed counter summary under profiles/,
+    if it was taken on the current source of the kernel; else None."""
+    path = os.path.join(ROOT, "profiles", file_name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    src = os.path.join(ROOT, "paper_1202_6522_amd", "csrc", "legendre.hip")
+    src = os.path.join(ROOT, "paper_1202_6522_amd", "csrc", KERNEL_SOURCE[kernel_name])
     k = d.get(kernel_name)
     if not k or k.get("source_sha") != _src_hash(src):
         return None
-    return k.get("bytes_per_launch")
+    return k.get(field)
+
+
+def _traffic(kernel_name):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return _summary("traffic.json", kernel_name, "bytes_per_launch")
+
+
+def _counter_flops(kernel_name):
+    """FP64 operations per launch counted by the SQ counters."""
+    return _summary("fp64_flops.json", kernel_name, "flops_per_launch")
 
 
 def _host_model():
@@ -467,10 +481,17 @@ def main():
     flops = plan.legendre_flops()
     avg_s = kern[dom]["avg_us"] * 1e-6
     achieved = flops / avg_s / 1e12
+    # FP64 operations the hardware counted per launch (committed summary of a
+    # rocprofv3 run on this source) over the live kernel time
+    counter = {}
+    for k in ("legendre_synth", "legendre_analys"):
+        c = _counter_flops(k)
+        counter[k] = None if c is None else round(c / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
             "traffic": _traffic(dom), "kernel": dom,
-            "flops_per_launch": flops}
+            "flops_per_launch": flops, "counter_tflops": counter[dom]}
+    stage_us = kern["legendre_synth"]["avg_us"] + kern["legendre_analys"]["avg_us"]
     out = {
         "metric": METRIC,
         "value": round(2.0 * args.steps / (ms * 1e-3), 2),
@@ -492,6 +513,10 @@ def main():
         "round_trip_rel_err": err,
         "legendre_tflops": {k: round(flops / (kern[k]["avg_us"] * 1e-6) / 1e12, 3)
                             for k in ("legendre_synth", "legendre_analys")},
+        "counter_tflops": counter,
+        # the Legendre stage as a whole: both directions' algorithmic FP64
+        # operations over the two kernel times, against the FP64 vector peak
+        "legendre_stage_frac": round(2 * flops / (stage_us * 1e-6) / 1e12 / PEAK_FP64_TFLOPS, 4),
         # the paper's efficiency measure: (N+1)^3 / (2 T) elements per second,
         # T the mean of the two transform times
         "paper_efficiency_elements_per_s": round((L + 1) ** 3 / (2 * (0.5 * ms_step * 1e-3)), 1),
