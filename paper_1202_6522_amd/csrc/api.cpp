@@ -34,7 +34,7 @@ int hip_error(int e, const char* where)
 
 int rows_per_block(const Plan& p)
 {
-    // rows of K points that fill one FFT workgroup (1024 points per wave)
+    // rows of K points that fill one FFT workgroup (4096 points)
     const int cap = fft_rows_cap(p.K);
     int r = p.tiling.fft_rows > 0 ? p.tiling.fft_rows : cap;
     if (r > cap) r = cap;

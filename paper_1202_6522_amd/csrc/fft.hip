@@ -3,26 +3,38 @@
 //
 // A real transform of length N = 2K is computed as a complex FFT of length K
 // on z_k = f_{2k} + i f_{2k+1}, with an O(K) pre/post-pass that separates the
-// even and odd samples.  The complex FFT is a Stockham autosort with radix-16
-// passes (a 16-point DFT in registers as 4 x 4) and one radix-4 or radix-2
-// pass for the remaining factor: three passes through LDS at K = 1024.
+// even and odd samples.  The complex FFT is a Stockham autosort with radix-P
+// passes (P points per thread: 4, 8 or 16; the 16-point DFT runs in
+// registers as 4 x 4, the 8-point one as 2 x 4) and one radix-4 and/or
+// radix-2 pass for the remaining factors.
 //
-// A workgroup holds rows x K <= 4096 complex points in LDS with one thread
-// per 16 points (one to four waves), so several workgroups share a CU; the
-// twiddles come from a two-level table of at most 128 entries in LDS.  Every
-// thread owns 16 points of every pass (16/R butterflies of radix R); all
-// index arithmetic is shifts and masks (K is a power of two).  Row blocks are
-// spread over the XCDs so that neighbouring blocks share an L2.
+// The longitude stage moves every byte of F and of the grid once and does
+// little arithmetic, so it is bound by memory latency and bandwidth: a launch
+// needs many waves in flight, on every SIMD.  A workgroup holds rows x K <=
+// 4096 points in LDS (whole rows; at lmax 1023 four rows, so that the reads
+// of F, stored in tiles of eight latitudes per order, come in 64-byte runs)
+// next to the K twiddles e^{-2 pi i t/K} (at most 135 KB), with one thread
+// per P points: P = 8 up to K = 2048 (512 threads: at lmax 1023 2048 waves,
+// two per SIMD), 16 at K = 4096.  Every thread owns P points
+// of every pass (P/R butterflies of radix R); all index arithmetic is shifts
+// and masks (K is a power of two).  The rows and the pre/post-pass twiddles
+// are requested before anything waits for memory, the twiddle table goes to
+// LDS while they arrive.  Row blocks are spread over the XCDs so that
+// neighbouring blocks share an L2.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "shtn_internal.h"
 
 namespace shtn {
 
-constexpr int kFftMaxThreads = 256;           // at most four waves
-constexpr int kFftPoints = 4096;              // complex points per workgroup at most (LDS)
-constexpr int kFftPerThread = 16;             // points per thread: one radix-16 butterfly per pass
-constexpr int kTwEntries = 128;               // two-level twiddle table, K <= 4096
+constexpr int kFftPoints = 4096;  // complex points per workgroup at most (LDS)
+
+// Points per thread for rows of K points (see above), and the most threads a
+// workgroup of that kind has.
+__host__ __device__ constexpr int fft_pts(int K) { return K <= 2048 ? 8 : 16; }
+__host__ __device__ constexpr int fft_max_threads(int P) { return kFftPoints / P; }
 
 // Twiddle tables are read through global-address-space pointers (the plan
 // descriptor holds them as generic pointers, which would compile to flat
@@ -104,12 +116,33 @@ __device__ __forceinline__ void dft16(double2 (&v)[16], int dir)
     for (int k1 = 0; k1 < 4; k1++) dft4(v, 4 * k1, 1, dir);  // v[4 k1 + k2] = X[k1 + 4 k2]
 }
 
+// In-place 8-point DFT with e^{dir 2 pi i jk/8}: index j = 4 j1 + j2, k = k1
+// + 2 k2.  Four DFT_2 over j1, twiddles e^{dir 2 pi i j2 k1/8}, two DFT_4
+// over j2.  The result X[k1 + 2 k2] is left in v[4 k1 + k2].
+__device__ __forceinline__ void dft8(double2 (&v)[8], int dir)
+{
+    constexpr double c = 0.70710678118654752440;
+#pragma unroll
+    for (int j2 = 0; j2 < 4; j2++) {
+        const double2 a = v[j2], b = v[4 + j2];
+        v[j2] = cadd(a, b);
+        v[4 + j2] = csub(a, b);
+    }
+    const double sd = dir;
+    v[5] = cmul(v[5], make_double2(c, sd * c));   // w^1
+    v[6] = cmuli(v[6], dir);                      // w^2 = dir i
+    v[7] = cmul(v[7], make_double2(-c, sd * c));  // w^3
+    dft4(v, 0, 1, dir);
+    dft4(v, 4, 1, dir);
+}
+
 // Register holding output q of dft_r<R>: the radix-16 DFT leaves X[k1 + 4 k2]
-// in v[4 k1 + k2]; the others are in natural order.
+// in v[4 k1 + k2], the radix-8 one X[k1 + 2 k2] in v[4 k1 + k2]; the others
+// are in natural order.
 template <int R>
 __device__ __forceinline__ constexpr int out_slot(int q)
 {
-    return R == 16 ? 4 * (q & 3) + (q >> 2) : q;
+    return R == 16 ? 4 * (q & 3) + (q >> 2) : (R == 8 ? 4 * (q & 1) + (q >> 1) : q);
 }
 
 template <int R>
@@ -117,6 +150,8 @@ __device__ __forceinline__ void dft_r(double2 (&v)[R], int dir)
 {
     if constexpr (R == 16) {
         dft16(v, dir);
+    } else if constexpr (R == 8) {
+        dft8(v, dir);
     } else if constexpr (R == 4) {
         dft4(v, 0, 1, dir);
     } else {
@@ -126,25 +161,20 @@ __device__ __forceinline__ void dft_r(double2 (&v)[R], int dir)
     }
 }
 
-// Twiddle e^{-2 pi i t/K} (0 <= t < K = 2^lgK) from the two-level table in
-// LDS: t = hi 2^lo + lo_part with lo = ceil(lgK/2); entries [0, 2^lo) hold
-// e^{-2 pi i b/K}, entries [2^lo, 2^lo + 2^(lgK-lo)) hold e^{-2 pi i a 2^lo/K}.
-__device__ __forceinline__ double2 tw_at(const double2* twl, int t, int lgK)
-{
-    const int lo = (lgK + 1) >> 1;
-    return cmul(twl[t & ((1 << lo) - 1)], twl[(1 << lo) + (t >> lo)]);
-}
-
 // One Stockham pass of radix R over the rows held in buf (npts = rows x K
 // points, K = 2^lgK); Ns = 2^lgNs = product of the radices of the previous
-// passes; twl = the two-level twiddle table in LDS.  Each thread reads
-// its 16/R butterflies, the workgroup synchronises, then they are written
+// passes; twl = the K twiddles e^{-2 pi i t/K} in LDS.  Each thread reads
+// its P/R butterflies, the workgroup synchronises, then they are written
 // back in place.  dir = -1 forward (e^{-2 pi i}), +1 inverse.
-template <int R, int LGR>
+// ZIN (first pass of the synthesis only): buf holds Y_m and the pass reads
+// Z_m = (Y_m + conj Y_{K-m}) + i w^m (Y_m - conj Y_{K-m}) instead, Y_K = 0,
+// with w^m of each of the thread's points in zw.
+template <int P, int R, int LGR, bool ZIN = false>
 __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, int lgK, int npts, int lgNs,
-                                              int dir)
+                                              int dir, const double2 (*zw)[R] = nullptr)
 {
-    constexpr int NB = 16 / R;
+    static_assert(R <= P, "a thread holds whole butterflies");
+    constexpr int NB = P / R;
     const int lgKR = lgK - LGR;
     const int nb = npts >> LGR;
     const int KR = 1 << lgKR;
@@ -158,14 +188,25 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
             const int r = b >> lgKR, jj = b & (KR - 1);
             const int js = jj & ((1 << lgNs) - 1);
             const int rowb = r << lgK;
+            if constexpr (ZIN) {
 #pragma unroll
-            for (int q = 0; q < R; q++) v[i][q] = buf[at(rowb + jj + q * KR)];
+                for (int q = 0; q < R; q++) {
+                    const int m = jj + q * KR;
+                    const double2 ym = buf[at(rowb + m)];
+                    const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(rowb + (1 << lgK) - m)];
+                    const double2 sm = cadd(ym, cconj(yc)), d = csub(ym, cconj(yc));
+                    v[i][q] = cadd(sm, cmuli(cmul(zw[i][q], d), 1));
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < R; q++) v[i][q] = buf[at(rowb + jj + q * KR)];
+            }
             if (lgNs > 0) {  // the first pass has js = 0: all twiddles are 1
                 // twiddle index q js K / (Ns R)
                 const int tstep = js << (lgK - lgNs - LGR);
 #pragma unroll
                 for (int q = 1; q < R; q++) {
-                    double2 w = tw_at(twl, q * tstep, lgK);
+                    double2 w = twl[q * tstep];
                     if (dir > 0) w = cconj(w);
                     v[i][q] = cmul(v[i][q], w);
                 }
@@ -185,28 +226,38 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
     __syncthreads();
 }
 
-// Complex FFT of length K = 2^lgK on every row held in buf: radix 16 while
-// four or more factors of 2 remain, then one radix-4 and/or radix-2 pass.
-__device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, int lgK, int npts, int dir)
+// Complex FFT of length K = 2^lgK on every row held in buf: radix P while
+// lg P or more factors of 2 remain, then one radix-4 and/or radix-2 pass.
+template <int P>
+constexpr int lg_pts() { return P == 16 ? 4 : (P == 8 ? 3 : 2); }
+
+// zw non-null: the first pass is of radix P (lgK >= lg P) and forms the
+// synthesis's Z from Y in buf (see stockham_pass).
+template <int P>
+__device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, int lgK, int npts, int dir,
+                                            const double2 (*zw)[P] = nullptr)
 {
+    constexpr int LGP = lg_pts<P>();
     int lgNs = 0;
-    while (lgK - lgNs >= 4) {
-        stockham_pass<16, 4>(buf, twl, lgK, npts, lgNs, dir);
-        lgNs += 4;
+    if (zw) {
+        stockham_pass<P, P, LGP, true>(buf, twl, lgK, npts, 0, dir, zw);
+        lgNs = LGP;
     }
-    if (lgK - lgNs >= 2) {
-        stockham_pass<4, 2>(buf, twl, lgK, npts, lgNs, dir);
+    while (lgK - lgNs >= LGP) {
+        stockham_pass<P, P, LGP>(buf, twl, lgK, npts, lgNs, dir);
+        lgNs += LGP;
+    }
+    if (P > 4 && lgK - lgNs >= 2) {
+        stockham_pass<P, 4, 2>(buf, twl, lgK, npts, lgNs, dir);
         lgNs += 2;
     }
-    if (lgK - lgNs == 1) stockham_pass<2, 1>(buf, twl, lgK, npts, lgNs, dir);
+    if (lgK - lgNs == 1) stockham_pass<P, 2, 1>(buf, twl, lgK, npts, lgNs, dir);
 }
 
-// Builds the two-level twiddle table (see tw_at) from the K-entry table
-// e^{-2 pi i t/K} in global memory.
-__device__ __forceinline__ void stage_twiddles(double2* twl, gdp tw, int lgK)
+// Copies the K-entry table e^{-2 pi i t/K} from global memory to LDS.
+__device__ __forceinline__ void stage_twiddles(double2* twl, gdp tw, int K)
 {
-    const int lo = (lgK + 1) >> 1, nlo = 1 << lo, n = nlo + (1 << (lgK - lo));
-    for (int t = threadIdx.x; t < n; t += blockDim.x) twl[t] = ld2(tw, t < nlo ? t : (t - nlo) << lo);
+    for (int t = threadIdx.x; t < K; t += blockDim.x) twl[t] = ld2(tw, t);
 }
 
 struct RowBlock {
@@ -241,7 +292,7 @@ __device__ __forceinline__ RowBlock row_block(const FftArgs& a, int nlat)
 // tiles (whole tiles, or an aligned part of one), every order contributes
 // one contiguous run per tile, read or written by consecutive threads;
 // otherwise point by point.
-template <bool LOAD>
+template <int P, bool LOAD>
 __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* Fout, long ts, int M,
                                        int lgK, int row0, int nrows)
 {
@@ -250,21 +301,21 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
     if (LOAD && pow2 && nrows <= kFTile && (row0 & (nrows - 1)) == 0) {
         // The block is one aligned run inside a tile: entry e is order
         // e >> lg, row e & (nrows - 1).  Every thread owns at most
-        // kFftPerThread entries (nrows (M+1) <= nrows K <= kFftPerThread
+        // P entries (nrows (M+1) <= nrows K <= P
         // threads), all loaded, from valid addresses, before any LDS write:
         // one memory round trip instead of one per entry.
         const int lg = __builtin_ctz(nrows);
         const int n = nrows * (M + 1);
         const long tb = (long)(row0 >> kFTileLg) * ts + (row0 & (kFTile - 1));
-        double2 v[kFftPerThread];
+        double2 v[P];
 #pragma unroll
-        for (int k = 0; k < kFftPerThread; k++) {
+        for (int k = 0; k < P; k++) {
             const int e = threadIdx.x + k * blockDim.x;
             const int ec = e < n ? e : 0;
             v[k] = *(const double2*)(Fin + 2 * (tb + ((long)(ec >> lg) << kFTileLg) + (ec & (nrows - 1))));
         }
 #pragma unroll
-        for (int k = 0; k < kFftPerThread; k++) {
+        for (int k = 0; k < P; k++) {
             const int e = threadIdx.x + k * blockDim.x;
             const int m = e >> lg, r = e & (nrows - 1);
             if (e < n) buf[at((r << lgK) + m)] = make_double2(v[k].x, m == 0 ? 0.0 : v[k].y);
@@ -276,15 +327,15 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
         const int lg = __builtin_ctz(nrows);
         const int n = nrows * (M + 1);
         const long tb = (long)(row0 >> kFTileLg) * ts + (row0 & (kFTile - 1));
-        double2 v[kFftPerThread];
+        double2 v[P];
 #pragma unroll
-        for (int k = 0; k < kFftPerThread; k++) {
+        for (int k = 0; k < P; k++) {
             const int e = threadIdx.x + k * blockDim.x;
             const int ec = e < n ? e : 0;
             v[k] = buf[at(((ec & (nrows - 1)) << lgK) + (ec >> lg))];
         }
 #pragma unroll
-        for (int k = 0; k < kFftPerThread; k++) {
+        for (int k = 0; k < P; k++) {
             const int e = threadIdx.x + k * blockDim.x;
             if (e < n)
                 *(double2*)(Fout + 2 * (tb + ((long)(e >> lg) << kFTileLg) + (e & (nrows - 1)))) = v[k];
@@ -327,11 +378,12 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
 }
 
 // Fourier synthesis of rows: f_ik = Re F_0 + 2 Re sum_{m=1}^{M} F_m e^{2 pi i m k / N}.
-__global__ void __launch_bounds__(kFftMaxThreads) k_c2r(FftArgs a)
+template <int P>
+__global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
 {
-    extern __shared__ double2 lds[];  // points (16 per thread), then the twiddle table
+    extern __shared__ double2 lds[];  // points (P per thread), then the twiddle table
     double2* buf = lds;
-    double2* twl = lds + lds_points(blockDim.x * kFftPerThread);
+    double2* twl = lds + lds_points(blockDim.x * P);
     const int pl = a.rowblocks ? a.rowblocks[4 * blockIdx.x + 1] : 0;
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
@@ -344,42 +396,55 @@ __global__ void __launch_bounds__(kFftMaxThreads) k_c2r(FftArgs a)
     double* g = a.out + (a.g_off ? a.g_off[rb.field] : (long)rb.field * nlat * nphi);
     const int npts = rb.nrows << lgK;
 
-    stage_twiddles(twl, tw, lgK);
-    // w^m of this thread's points, loaded while the rows arrive
-    double2 rw[kFftPerThread];
+    // Z_m = (Y_m + conj Y_{K-m}) + i w^m (Y_m - conj Y_{K-m}), w = e^{i pi/K},
+    // Y_K = 0 (M < K): formed by the first radix-P pass as it reads Y, when
+    // there is one (lgK >= lg P), else by a pass of its own.
+    constexpr int LGP = lg_pts<P>();
+    const bool fused = lgK >= LGP;
+    // w^m of the points this thread forms Z for, loaded while the rows arrive
+    double2 rw[P];
+    if (fused) {
+        const int jj = threadIdx.x & ((K >> LGP) - 1);
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++)
-        rw[e] = ld2(rtw, (threadIdx.x + e * blockDim.x) & (K - 1));
+        for (int q = 0; q < P; q++) rw[q] = ld2(rtw, jj + q * (K >> LGP));
+    } else {
+#pragma unroll
+        for (int e = 0; e < P; e++) rw[e] = ld2(rtw, (threadIdx.x + e * blockDim.x) & (K - 1));
+    }
     // Y_m (Y_0 = Re F_0, Y_m = F_m for 1 <= m <= M, 0 above) row by row
     for (int idx = threadIdx.x; idx < npts; idx += blockDim.x)
         if ((idx & (K - 1)) > M) buf[at(idx)] = make_double2(0.0, 0.0);
-    move_f<true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
+    move_f<P, true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
+    stage_twiddles(twl, tw, K);
     __syncthreads();
-    // Z_m = (Y_m + conj Y_{K-m}) + i w^m (Y_m - conj Y_{K-m}), w = e^{i pi/K},
-    // Y_K = 0 (M < K)
-    double2 z[kFftPerThread];
+    if (fused) {
+        const double2(*zw)[P] = (const double2(*)[P])rw;
+        complex_fft<P>(buf, twl, lgK, npts, +1, zw);
+    } else {
+        double2 z[P];
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * blockDim.x;
-        z[e] = make_double2(0.0, 0.0);
-        if (idx < npts) {
-            const int m = idx & (K - 1);
-            const double2 ym = buf[at(idx)];
-            const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(idx - m + (K - m))];
-            const double2 s = cadd(ym, cconj(yc)), d = csub(ym, cconj(yc));
-            z[e] = cadd(s, cmuli(cmul(rw[e], d), 1));
+        for (int e = 0; e < P; e++) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            z[e] = make_double2(0.0, 0.0);
+            if (idx < npts) {
+                const int m = idx & (K - 1);
+                const double2 ym = buf[at(idx)];
+                const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(idx - m + (K - m))];
+                const double2 s = cadd(ym, cconj(yc)), d = csub(ym, cconj(yc));
+                z[e] = cadd(s, cmuli(cmul(rw[e], d), 1));
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) {
-        const int idx = threadIdx.x + e * blockDim.x;
-        if (idx < npts) buf[at(idx)] = z[e];
+        for (int e = 0; e < P; e++) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            if (idx < npts) buf[at(idx)] = z[e];
+        }
+        __syncthreads();
+        complex_fft<P>(buf, twl, lgK, npts, +1);
     }
-    __syncthreads();
-    complex_fft(buf, twl, lgK, npts, +1);
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) {
+    for (int e = 0; e < P; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) {
             const int r = idx >> lgK, k = idx & (K - 1);
@@ -389,11 +454,12 @@ __global__ void __launch_bounds__(kFftMaxThreads) k_c2r(FftArgs a)
 }
 
 // Fourier analysis of rows: F_m(theta_i) = scale * sum_k f_ik e^{-2 pi i m k / N}, m <= M.
-__global__ void __launch_bounds__(kFftMaxThreads) k_r2c(FftArgs a)
+template <int P>
+__global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
 {
-    extern __shared__ double2 lds[];  // points (16 per thread), then the twiddle table
+    extern __shared__ double2 lds[];  // points (P per thread), then the twiddle table
     double2* buf = lds;
-    double2* twl = lds + lds_points(blockDim.x * kFftPerThread);
+    double2* twl = lds + lds_points(blockDim.x * P);
     const int pl = a.rowblocks ? a.rowblocks[4 * blockIdx.x + 1] : 0;
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
@@ -405,55 +471,85 @@ __global__ void __launch_bounds__(kFftMaxThreads) k_r2c(FftArgs a)
     const double* g = a.in + (a.g_off ? a.g_off[rb.field] : (long)rb.field * nlat * nphi);
     double* F = a.out + (a.f_off ? a.f_off[rb.field] : (long)rb.field * 2 * D.f_size);
     const int npts = rb.nrows << lgK;
-    stage_twiddles(twl, tw, lgK);
     // Straight-line loads from valid addresses, then LDS writes without
-    // branches (idx < 16 blockDim stays inside the point buffer; slots past
+    // branches (idx < P blockDim stays inside the point buffer; slots past
     // npts are never read), so every load is issued before the first wait.
-    double2 v[kFftPerThread];
+    double2 v[P];
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) {
+    for (int e = 0; e < P; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
         const int ic = idx < npts ? idx : 0;
         const int r = ic >> lgK, k = ic & (K - 1);
         v[e] = *(const double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k);
     }
+    // When the block is a power-of-two run of rows aligned inside an F tile
+    // (the usual case), each thread computes the outputs X_m it stores,
+    // straight from Z in LDS (entry e: order e >> lg, row e & (nrows - 1));
+    // otherwise a post-pass writes X over the buffer first.
+    const bool direct = (rb.nrows & (rb.nrows - 1)) == 0 && rb.nrows <= kFTile && (rb.row0 & (rb.nrows - 1)) == 0;
+    const int lgr = __builtin_ctz(rb.nrows);
+    const int nout = rb.nrows * (M + 1);
+    // w^m of this thread's outputs for the post-pass, requested with the rows
+    double2 rw[P];
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) buf[at(threadIdx.x + e * blockDim.x)] = v[e];
+    for (int e = 0; e < P; e++) {
+        const int idx = threadIdx.x + e * blockDim.x;
+        rw[e] = ld2(rtw, direct ? ((idx < nout ? idx : 0) >> lgr) : (idx & (K - 1)));
+    }
+    stage_twiddles(twl, tw, K);
+#pragma unroll
+    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x)] = v[e];
 
     __syncthreads();
-    complex_fft(buf, twl, lgK, npts, -1);
-    // w^m of this thread's points for the post-pass
-    double2 rw[kFftPerThread];
-#pragma unroll
-    for (int e = 0; e < kFftPerThread; e++)
-        rw[e] = ld2(rtw, (threadIdx.x + e * blockDim.x) & (K - 1));
+    complex_fft<P>(buf, twl, lgK, npts, -1);
     // scale <= 0: the analysis scale 2 pi / nphi of each field's plan
     const double sc = a.scale > 0.0 ? a.scale : 2.0 * 3.14159265358979323846 / nphi;
+    // X_m = (Z_m + conj Z_{K-m}) / 2 + conj(w^m) (Z_m - conj Z_{K-m}) / (2i),
+    // scaled; Im X_0 = 0
+    auto post = [&](double2 zm, double2 zc, double2 w, int m) {
+        const double2 A = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
+        const double2 Dd = csub(zm, zc);
+        const double2 B = make_double2(0.5 * Dd.y, -0.5 * Dd.x);
+        double2 X = cadd(A, cmul(cconj(w), B));
+        X.x *= sc;
+        X.y = m == 0 ? 0.0 : X.y * sc;
+        return X;
+    };
+    if (direct) {
+        const long tb = (long)(rb.row0 >> kFTileLg) * D.f_ts + (rb.row0 & (kFTile - 1));
+        double2 x[P];
+#pragma unroll
+        for (int e = 0; e < P; e++) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            const int ec = idx < nout ? idx : 0;
+            const int m = ec >> lgr, rbase = (ec & (rb.nrows - 1)) << lgK;
+            x[e] = post(buf[at(rbase + m)], cconj(buf[at(rbase + ((K - m) & (K - 1)))]), rw[e], m);
+        }
+#pragma unroll
+        for (int e = 0; e < P; e++) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            if (idx < nout)
+                *(double2*)(F + 2 * (tb + ((long)(idx >> lgr) << kFTileLg) + (idx & (rb.nrows - 1)))) = x[e];
+        }
+        return;
+    }
     // X_m from Z_m and Z_{K-m}, computed in registers, then written over the
     // buffer so that F leaves in tile order
     // (straight-line: every index below stays inside the point buffer, a
-    // row of K points lying within its 16 blockDim slots; points past npts
+    // row of K points lying within its P blockDim slots; points past npts
     // are computed from unused slots and never read back)
-    double2 x[kFftPerThread];
+    double2 x[P];
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) {
+    for (int e = 0; e < P; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
         const int m = idx & (K - 1);
-        const double2 zm = buf[at(idx)];
-        const double2 zc = cconj(buf[at(idx - m + ((K - m) & (K - 1)))]);
-        const double2 A = make_double2(0.5 * (zm.x + zc.x), 0.5 * (zm.y + zc.y));
-        const double2 Dd = csub(zm, zc);
-        const double2 B = make_double2(0.5 * Dd.y, -0.5 * Dd.x);  // (Z_m - conj Z_{K-m}) / (2i)
-        double2 X = cadd(A, cmul(cconj(rw[e]), B));
-        X.x *= sc;
-        X.y = m == 0 ? 0.0 : X.y * sc;
-        x[e] = X;
+        x[e] = post(buf[at(idx)], cconj(buf[at(idx - m + ((K - m) & (K - 1)))]), rw[e], m);
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < kFftPerThread; e++) buf[at(threadIdx.x + e * blockDim.x)] = x[e];
+    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x)] = x[e];
     __syncthreads();
-    move_f<false>(buf, nullptr, F, D.f_ts, M, lgK, rb.row0, rb.nrows);
+    move_f<P, false>(buf, nullptr, F, D.f_ts, M, lgK, rb.row0, rb.nrows);
 }
 
 static FftArgs fft_args(const FftLaunch& l)
@@ -466,50 +562,58 @@ static FftArgs fft_args(const FftLaunch& l)
 int fft_rows_cap(int K) { return K <= kFftPoints ? kFftPoints / K : 1; }
 
 // Threads of a launch whose largest block holds `points` complex points: one
-// per 16 points, whole waves, one to four.
-static int fft_threads(int points)
+// per P points, whole waves.
+static int fft_threads(int points, int P)
 {
-    const int t = (points + kFftPerThread - 1) / kFftPerThread;
-    return t < 64 ? 64 : (t > kFftMaxThreads ? kFftMaxThreads : (t + 63) / 64 * 64);
+    const int t = (points + P - 1) / P;
+    return t < 64 ? 64 : std::min(fft_max_threads(P), (t + 63) / 64 * 64);
 }
 
-// Dynamic LDS for that thread count: 16 points per thread plus the twiddles.
-static size_t fft_lds_bytes(int threads)
+// Dynamic LDS for that thread count and row length: P points per thread
+// plus the K twiddles.
+static size_t fft_lds_bytes(int threads, int P, int K)
 {
-    return sizeof(double2) * ((size_t)lds_points(threads * kFftPerThread) + kTwEntries);
+    return sizeof(double2) * ((size_t)lds_points(threads * P) + K);
 }
 
 // Allows the largest dynamic LDS of these kernels (above the 64 KB default).
+template <int P>
 static int allow_lds()
 {
     static const int rc = [] {
-        const int bytes = (int)fft_lds_bytes(kFftMaxThreads);
-        hipError_t e = hipFuncSetAttribute((const void*)k_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        const int bytes = (int)fft_lds_bytes(fft_max_threads(P), P, kFftPoints);
+        hipError_t e = hipFuncSetAttribute((const void*)k_c2r<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            e = hipFuncSetAttribute((const void*)k_r2c<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         return (int)e;
     }();
     return rc;
 }
 
-int launch_c2r(const FftLaunch& l, void* stream)
+template <int P, bool C2R>
+static int launch_fft_t(const FftLaunch& l, void* stream)
 {
-    if (l.K < 1 || l.K > kFftPoints || l.points < l.K || l.points > kFftPoints) return (int)hipErrorInvalidValue;
-    if (int e = allow_lds()) return e;
-    const int nt = fft_threads(l.points);
-    hipLaunchKernelGGL(k_c2r, dim3(l.nblocks, l.grid_y), dim3(nt), fft_lds_bytes(nt),
-                       (hipStream_t)stream, fft_args(l));
+    if (int e = allow_lds<P>()) return e;
+    const int nt = fft_threads(l.points, P);
+    if (nt * P < l.points) return (int)hipErrorInvalidValue;
+    const size_t lds = fft_lds_bytes(nt, P, l.K);
+    if (C2R)
+        hipLaunchKernelGGL(k_c2r<P>, dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream, fft_args(l));
+    else
+        hipLaunchKernelGGL(k_r2c<P>, dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream, fft_args(l));
     return (int)hipGetLastError();
 }
 
-int launch_r2c(const FftLaunch& l, void* stream)
+// One points-per-thread variant per launch, chosen by its longest rows.
+template <bool C2R>
+static int launch_fft(const FftLaunch& l, void* stream)
 {
     if (l.K < 1 || l.K > kFftPoints || l.points < l.K || l.points > kFftPoints) return (int)hipErrorInvalidValue;
-    if (int e = allow_lds()) return e;
-    const int nt = fft_threads(l.points);
-    hipLaunchKernelGGL(k_r2c, dim3(l.nblocks, l.grid_y), dim3(nt), fft_lds_bytes(nt),
-                       (hipStream_t)stream, fft_args(l));
-    return (int)hipGetLastError();
+    return fft_pts(l.K) == 8 ? launch_fft_t<8, C2R>(l, stream) : launch_fft_t<16, C2R>(l, stream);
 }
+
+int launch_c2r(const FftLaunch& l, void* stream) { return launch_fft<true>(l, stream); }
+
+int launch_r2c(const FftLaunch& l, void* stream) { return launch_fft<false>(l, stream); }
 
 }  // namespace shtn

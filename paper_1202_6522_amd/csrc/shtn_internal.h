@@ -314,7 +314,7 @@ struct FftLaunch {
     int grid_y;
     int K;                    // longest rows of the launch
     int points;               // most complex points in one block (rows x K <= 4096): sizes
-                              // the workgroup (one thread per 16 points) and its LDS
+                              // the workgroup (one thread per 4, 8 or 16 points) and its LDS
     int rows_per_block;
     const long* g_off;        // per-field grid offset (doubles) or null
     const long* f_off;        // per-field F offset (doubles) or null
