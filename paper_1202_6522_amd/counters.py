@@ -10,6 +10,13 @@ file (bench.py uses a summary only while the source is unchanged).
 Counting: SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 count wave instructions; a
 wave instruction covers 64 lanes, an FMA is two operations, the others one.
 SQ_INSTS_VALU_FLOPS_FP64, where the hardware offers it, is kept as read.
+
+`python -m paper_1202_6522_amd.counters traffic <fetch.csv> <write.csv> <MiB> <out.json>`
+reads two such runs (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch) of
+`bench.py --scalar-only --calibrate-copy <MiB>` and writes the HBM bytes per
+launch of every shtn kernel, each counter scaled by what it reads for the
+calibration kernel (torch.neg over <MiB> MiB of float64: reads and writes
+<MiB> MiB once).
 """
 import collections
 import csv
@@ -77,16 +84,49 @@ def fp64_summary(path):
     return res
 
 
+def calibration_kib(path, counter):
+    """Median of `counter` over the dispatches of the calibration kernel."""
+    vals = collections.defaultdict(float)
+    for r in csv.DictReader(open(path)):
+        if "neg" in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+    if not vals:
+        raise ValueError("no calibration kernel in %s" % path)
+    return statistics.median(vals.values())
+
+
+def traffic_summary(fetch_csv, write_csv, mib):
+    known = mib * 1024.0  # KiB read, and written, by the calibration kernel
+    sf = known / calibration_kib(fetch_csv, "FETCH_SIZE")
+    sw = known / calibration_kib(write_csv, "WRITE_SIZE")
+    fe, wr = medians(fetch_csv), medians(write_csv)
+    res = {"_calibration": {"mib": mib, "fetch_scale": sf, "write_scale": sw}}
+    for k in sorted(set(fe) & set(wr)):
+        fk, wk = fe[k].get("FETCH_SIZE", 0.0), wr[k].get("WRITE_SIZE", 0.0)
+        res[k] = {"source": fe[k]["_source"], "source_sha": source_hash(fe[k]["_source"]),
+                  "fetch_kib": fk, "write_kib": wk,
+                  "bytes_per_launch": int(round(1024.0 * (fk * sf + wk * sw)))}
+    return res
+
+
 def main(argv):
-    if len(argv) != 4 or argv[1] != "fp64":
-        print(__doc__)
-        return 2
-    res = fp64_summary(argv[2])
-    with open(argv[3], "w") as f:
-        json.dump(res, f, indent=1, sort_keys=True)
-    for k, v in sorted(res.items()):
-        print("%-16s %.4g FP64 ops per launch" % (k, v["flops_per_launch"]))
-    return 0
+    if len(argv) == 4 and argv[1] == "fp64":
+        res = fp64_summary(argv[2])
+        with open(argv[3], "w") as f:
+            json.dump(res, f, indent=1, sort_keys=True)
+        for k, v in sorted(res.items()):
+            print("%-16s %.4g FP64 ops per launch" % (k, v["flops_per_launch"]))
+        return 0
+    if len(argv) == 6 and argv[1] == "traffic":
+        res = traffic_summary(argv[2], argv[3], float(argv[4]))
+        with open(argv[5], "w") as f:
+            json.dump(res, f, indent=1, sort_keys=True)
+        for k, v in sorted(res.items()):
+            if not k.startswith("_"):
+                print("%-16s %.2f MB per launch" % (k, v["bytes_per_launch"] / 1e6))
+        return 0
+    print(__doc__)
+    return 2
 
 
 if __name__ == "__main__":
