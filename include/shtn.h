@@ -32,7 +32,13 @@
  *    device pointer owned by the caller; arrays are contiguous.  `stream` is a
  *    hipStream_t passed as void* (NULL = the default stream).  The library
  *    allocates no device memory: tables and scratch live in caller buffers.
- *    Inputs are never modified.  Inputs and outputs must not overlap.
+ *    Inputs are never modified.  A buffer a call writes (an output, the
+ *    workspace) must share no byte with any other buffer of the call: its
+ *    inputs, its other outputs, the plan's device and stored-P buffers, a
+ *    batch's device buffer.  Buffers a call only reads may overlap.  Calls
+ *    check this over the byte ranges their arguments define (nfields fields,
+ *    the workspace size) and return SHTN_EINVAL, before any launch, when
+ *    two ranges overlap; buffers that only touch are accepted.
  *  Errors: entry points return SHTN_OK (0) or a negative code below;
  *    shtn_last_error_detail() gives a thread-local message.  Transform calls
  *    are asynchronous on `stream`: a device fault surfaces at the caller's
@@ -222,8 +228,9 @@ int shtn_synth_noalloc(shtn_plan_t plan, const double* Q, double* grid, int nfie
  * weighted longitude coefficients) with the plan's algorithm, tiling and
  * polar threshold, through sin(theta) dP_n^m/dtheta = n x P_n^m -
  * c_n P_{n-1}^m.  work: shtn_vec_work_bytes(plan, nfields) bytes of device
- * memory, 256-byte aligned.  Errors as for shtn_synth; outputs must not
- * alias inputs or each other. */
+ * memory, 256-byte aligned.  Errors as for shtn_synth; the two outputs may
+ * overlap no other buffer of the call (S and T may be one buffer, as may
+ * Vtheta and Vphi on input). */
 size_t shtn_vec_work_bytes(shtn_plan_t plan, int nfields);
 int shtn_vec_synth(shtn_plan_t plan, const double* S, const double* T, double* Vtheta, double* Vphi, int nfields,
                    void* work, void* stream);
@@ -289,7 +296,8 @@ int shtn_plan_get_algorithm(shtn_plan_t plan);
  * us4 (may be NULL) receives the mean times in microseconds: synthesis
  * on-the-fly, synthesis stored, analysis on-the-fly, analysis stored (-1
  * when not timed).  Q, grid and Qout are device buffers of nfields fields;
- * Qout must not alias Q.  Blocks until done. */
+ * Qout, like grid, may overlap no other buffer of the call.  Blocks until
+ * done. */
 int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, double* Qout, int nfields,
                              void* work, void* stream, int reps, float* us4);
 
@@ -386,7 +394,7 @@ int shtn_batch_replay(shtn_batch_t batch, int which, void* stream);
  * appended; entries that do not parse or name a tiling outside the values
  * above are ignored (the candidates are timed).  *best_us (may be NULL)
  * receives the best round-trip time, or -1 when taken from the cache.  The
- * batch must be uploaded; Qout must not alias the other buffers. */
+ * batch must be uploaded; Qout may overlap no other buffer of the call. */
 int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacked, double* Qout,
                     void* work, void* stream, int reps, const char* cache_path, float* best_us);
 

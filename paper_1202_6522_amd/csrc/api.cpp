@@ -32,6 +32,28 @@ int hip_error(int e, const char* where)
     return SHTN_EHIP;
 }
 
+int check_disjoint(const std::vector<Range>& r)
+{
+    for (size_t i = 0; i < r.size(); i++)
+        for (size_t j = i + 1; j < r.size(); j++) {
+            if (!r[i].written && !r[j].written) continue;
+            const uintptr_t a = (uintptr_t)r[i].p, b = (uintptr_t)r[j].p;
+            if (r[i].bytes && r[j].bytes && a < b + r[j].bytes && b < a + r[i].bytes)
+                return set_error(SHTN_EINVAL, std::string(r[i].what) + " overlaps " + r[j].what);
+        }
+    return SHTN_OK;
+}
+
+// Device memory the plan reads during a transform: its uploaded image and,
+// when built, its stored-P table.
+void plan_ranges(const Plan& p, std::vector<Range>& r)
+{
+    r.push_back({"the plan's device buffer", p.dev, p.image.size(), false});
+    if (p.ptab.dev)
+        r.push_back({"the plan's stored-P buffer", p.ptab.dev,
+                     p.ptab.head_bytes + (size_t)p.ptab.nblocks * 256 * sizeof(double), false});
+}
+
 int rows_per_block(const Plan& p)
 {
     // rows of K points that fill one FFT workgroup (4096 points)
@@ -52,15 +74,27 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 const DevPlan* dplan(const Plan& p) { return (const DevPlan*)p.dev; }
 const int* dev_table_int(const Plan& p, int t) { return (const int*)((char*)p.dev + p.table_off[t]); }
 
-int check_call(shtn_plan_t plan, const void* in, const void* out, int nfields, const void* work)
+size_t data_bytes(const Plan& p, Data k, int nfields)
+{
+    return k == Data::spec ? (size_t)nfields * (size_t)p.nlm * 16 : (size_t)nfields * (size_t)p.nlat * (size_t)p.nphi * 8;
+}
+
+
+// A scalar call reading nfields fields of kind kin at `in` and writing
+// fields of kind kout at `out`, with the workspace at `work`.
+int check_call(shtn_plan_t plan, const void* in, Data kin, const void* out, Data kout, int nfields, const void* work)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
     if (nfields < 1 || nfields > SHTN_MAX_FIELDS)
         return fail(SHTN_EINVAL, "nfields must be in [1, SHTN_MAX_FIELDS = 65535]: split the call");
     if (!plan->p->uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
     if (!in || !out || !work) return fail(SHTN_EINVAL, "null data or workspace pointer");
-    if (in == out) return fail(SHTN_EINVAL, "input and output must not alias");
-    return SHTN_OK;
+    const Plan& p = *plan->p;
+    std::vector<Range> r{{"the input", in, data_bytes(p, kin, nfields), false},
+                         {"the output", out, data_bytes(p, kout, nfields), true},
+                         {"the workspace", work, work_layout(p, nfields).total, true}};
+    plan_ranges(p, r);
+    return check_disjoint(r);
 }
 
 // Which passes of an algorithm choice read the stored table.
@@ -219,24 +253,32 @@ VecLayout vec_layout(const Plan& p, int nfields)
     return v;
 }
 
-int check_vec_call(shtn_plan_t plan, const void* a, const void* b, const void* c, const void* d, int nfields,
-                   const void* work)
+// A vector call reading nfields fields of kind kin at a and b and writing
+// fields of kind kout at c and d, with the workspace at `work`.
+int check_vec_call(shtn_plan_t plan, const void* a, const void* b, Data kin, const void* c, const void* d, Data kout,
+                   int nfields, const void* work)
 {
     if (!plan || !plan->p) return fail(SHTN_EINVAL, "null plan");
     if (nfields < 1 || nfields > SHTN_MAX_VEC_FIELDS)
         return fail(SHTN_EINVAL, "nfields must be in [1, SHTN_MAX_VEC_FIELDS = 16383]: split the call");
     if (!plan->p->uploaded) return fail(SHTN_ESTATE, "plan not uploaded (call shtn_plan_upload)");
     if (!a || !b || !c || !d || !work) return fail(SHTN_EINVAL, "null data or workspace pointer");
-    if (c == a || c == b || d == a || d == b || c == d)
-        return fail(SHTN_EINVAL, "outputs must not alias inputs or each other");
-    return SHTN_OK;
+    const Plan& p = *plan->p;
+    const size_t ni = data_bytes(p, kin, nfields), no = data_bytes(p, kout, nfields);
+    std::vector<Range> r{{"the first input", a, ni, false},
+                         {"the second input", b, ni, false},
+                         {"the first output", c, no, true},
+                         {"the second output", d, no, true},
+                         {"the workspace", work, vec_layout(p, nfields).total, true}};
+    plan_ranges(p, r);
+    return check_disjoint(r);
 }
 
 // Legendre synthesis-type pass (synthesis or adjoint of the analysis) then c2r.
 int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* work, void* stream,
             int adjoint)
 {
-    int rc = check_call(plan, Q, grid, nfields, work);
+    int rc = check_call(plan, Q, Data::spec, grid, Data::grid, nfields, work);
     if (rc) return rc;
     const Plan& p = *plan->p;
     WorkLayout wl = work_layout(p, nfields);
@@ -250,7 +292,7 @@ int to_grid(shtn_plan_t plan, const double* Q, double* grid, int nfields, void* 
 int to_spec(shtn_plan_t plan, const double* grid, double* Q, int nfields, void* work, void* stream,
             int adjoint)
 {
-    int rc = check_call(plan, grid, Q, nfields, work);
+    int rc = check_call(plan, grid, Data::grid, Q, Data::spec, nfields, work);
     if (rc) return rc;
     const Plan& p = *plan->p;
     if ((rc = check_analys_stage(p))) return rc;
@@ -567,7 +609,7 @@ namespace {
 int vec_to_grid(shtn_plan_t plan, const double* S, const double* T, double* Vt, double* Vp, int nfields,
                 void* work, void* stream, int adjoint)
 {
-    int rc = check_vec_call(plan, S, T, Vt, Vp, nfields, work);
+    int rc = check_vec_call(plan, S, T, Data::spec, Vt, Vp, Data::grid, nfields, work);
     if (rc) return rc;
     const Plan& p = *plan->p;
     const VecLayout v = vec_layout(p, nfields);
@@ -591,7 +633,7 @@ int vec_to_grid(shtn_plan_t plan, const double* S, const double* T, double* Vt, 
 int vec_to_spec(shtn_plan_t plan, const double* Vt, const double* Vp, double* S, double* T, int nfields,
                 void* work, void* stream, int adjoint)
 {
-    int rc = check_vec_call(plan, Vt, Vp, S, T, nfields, work);
+    int rc = check_vec_call(plan, Vt, Vp, Data::grid, S, T, Data::spec, nfields, work);
     if (rc) return rc;
     const Plan& p = *plan->p;
     if ((rc = check_analys_stage(p))) return rc;
@@ -727,10 +769,14 @@ int shtn_plan_get_algorithm(shtn_plan_t plan)
 int shtn_plan_tune_algorithm(shtn_plan_t plan, const double* Q, double* grid, double* Qout, int nfields,
                              void* work, void* stream, int reps, float* us4)
 {
-    int rc = check_call(plan, Q, grid, nfields, work);
+    int rc = check_call(plan, Q, Data::spec, grid, Data::grid, nfields, work);
     if (rc) return rc;
-    if (!Qout || Qout == Q || (const void*)Qout == (const void*)grid)
-        return fail(SHTN_EINVAL, "Qout must be a separate buffer");
+    if (!Qout) return fail(SHTN_EINVAL, "null Qout");
+    if ((rc = check_call(plan, grid, Data::grid, Qout, Data::spec, nfields, work))) return rc;
+    {
+        const size_t sb = data_bytes(*plan->p, Data::spec, nfields);
+        if ((rc = check_disjoint({{"Q", Q, sb, false}, {"Qout", Qout, sb, true}}))) return rc;
+    }
     if (reps < 1) reps = 5;
     Plan& p = *plan->p;
     const int keep = p.algo;

@@ -276,14 +276,26 @@ void drop_graphs(shtn_batch_s& b)
     }
 }
 
-int check_batch(const shtn_batch_s* b, const void* in, const void* out, const void* work)
+size_t packed_bytes(const shtn_batch_s& b, Data k)
+{
+    return (k == Data::spec ? b.q_off.back() : b.g_off.back()) * sizeof(double);
+}
+
+// A batch call reading packed fields of kind kin at `in` and writing packed
+// fields of kind kout at `out`, with the workspace at `work`.
+int check_batch(const shtn_batch_s* b, const void* in, Data kin, const void* out, Data kout, const void* work)
 {
     if (!b) return set_error(SHTN_EINVAL, "null batch");
     if (!b->uploaded) return set_error(SHTN_ESTATE, "batch not uploaded (call shtn_batch_upload)");
     if (!in || !out || !work) return set_error(SHTN_EINVAL, "null data or workspace pointer");
-    if (in == out) return set_error(SHTN_EINVAL, "input and output must not alias");
     for (auto* p : b->plans)
         if (!p->uploaded) return set_error(SHTN_ESTATE, "a plan of the batch is no longer uploaded");
+    std::vector<Range> r{{"the input", in, packed_bytes(*b, kin), false},
+                         {"the output", out, packed_bytes(*b, kout), true},
+                         {"the batch's device buffer", b->dev, b->image.size(), false},
+                         {"the workspace", work, b->work_total_bytes, true}};
+    for (auto* p : b->plans) plan_ranges(*p, r);
+    if (int rc = check_disjoint(r)) return rc;
     if (plan_gens(*b) != b->upload_gen)
         return set_error(SHTN_ESTATE, "a plan of the batch changed since the batch upload (upload, tiling, polar "
                                       "threshold or stored-P table): call shtn_batch_upload again");
@@ -457,9 +469,10 @@ int upload(shtn_batch_s& b, void* dev_buf, void* stream)
 
 int capture(shtn_batch_s& b, int which, const double* in, double* out, void* work)
 {
-    int rc = check_batch(&b, in, out, work);
-    if (rc) return rc;
     if (which != 0 && which != 1) return set_error(SHTN_EINVAL, "which must be 0 (synthesis) or 1 (analysis)");
+    int rc = which == 0 ? check_batch(&b, in, Data::spec, out, Data::grid, work)
+                        : check_batch(&b, in, Data::grid, out, Data::spec, work);
+    if (rc) return rc;
     if (!b.cap_stream) {
         hipError_t e = hipStreamCreateWithFlags(&b.cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_error((int)e, "capture stream");
@@ -666,7 +679,7 @@ int shtn_batch_upload(shtn_batch_t batch, void* dev_buf, void* stream)
 int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpacked, void* work,
                      void* stream)
 {
-    int rc = check_batch(batch, Qpacked, gridpacked, work);
+    int rc = check_batch(batch, Qpacked, Data::spec, gridpacked, Data::grid, work);
     if (rc) return rc;
     return run_synth(*batch, Qpacked, gridpacked, work, stream);
 }
@@ -674,7 +687,7 @@ int shtn_batch_synth(shtn_batch_t batch, const double* Qpacked, double* gridpack
 int shtn_batch_analys(shtn_batch_t batch, const double* gridpacked, double* Qpacked, void* work,
                       void* stream)
 {
-    int rc = check_batch(batch, gridpacked, Qpacked, work);
+    int rc = check_batch(batch, gridpacked, Data::grid, Qpacked, Data::spec, work);
     if (rc) return rc;
     return run_analys(*batch, gridpacked, Qpacked, work, stream);
 }
@@ -753,10 +766,14 @@ int shtn_batch_replay(shtn_batch_t batch, int which, void* stream)
 int shtn_batch_tune(shtn_batch_t batch, const double* Qpacked, double* gridpacked, double* Qout,
                     void* work, void* stream, int reps, const char* cache_path, float* best_us)
 {
-    int rc = check_batch(batch, Qpacked, gridpacked, work);
+    int rc = check_batch(batch, Qpacked, Data::spec, gridpacked, Data::grid, work);
     if (rc) return rc;
-    if (!Qout || Qout == Qpacked || (const void*)Qout == (const void*)gridpacked)
-        return set_error(SHTN_EINVAL, "Qout must be a separate buffer");
+    if (!Qout) return set_error(SHTN_EINVAL, "null Qout");
+    if ((rc = check_batch(batch, gridpacked, Data::grid, Qout, Data::spec, work))) return rc;
+    {
+        const size_t sb = packed_bytes(*batch, Data::spec);
+        if ((rc = check_disjoint({{"Qpacked", Qpacked, sb, false}, {"Qout", Qout, sb, true}}))) return rc;
+    }
     if (reps < 1) reps = 10;
     shtn_batch_s& b = *batch;
     void* dev = b.dev;

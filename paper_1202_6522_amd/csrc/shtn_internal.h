@@ -203,6 +203,23 @@ void ptable_layout(Plan& p);  // geometry of the stored-P table
 // Error reporting shared by the C-ABI sources (api.cpp): sets the detail
 // string of shtn_last_error_detail and returns the code.
 int set_error(int code, const std::string& msg);
+
+// A device byte range a call touches; `written` when the call writes it.
+struct Range {
+    const char* what;
+    const void* p;
+    size_t bytes;
+    bool written;
+};
+// SHTN_OK, or SHTN_EINVAL when a written range shares a byte with any
+// other range of the list (read-only ranges may overlap); the message names
+// the first such pair in list order.
+int check_disjoint(const std::vector<Range>& r);
+// Fields of a transform: spectra (nlm complex each) or grids (nlat x nphi).
+enum class Data { spec, grid };
+// Appends the device memory a plan's transforms read: its uploaded image
+// and, when built, its stored-P table.
+void plan_ranges(const Plan& p, std::vector<Range>& r);
 int hip_error(int e, const char* where);
 int rows_per_block(const Plan& p);  // FFT rows per workgroup for a plan
 
