@@ -45,9 +45,19 @@ typedef const __attribute__((address_space(1))) double* gdp;
 __device__ __forceinline__ double2 ld2(gdp t, int i) { return make_double2(t[2 * i], t[2 * i + 1]); }
 
 // LDS slot of point x: one pad slot after every 16 points, so the strided
-// writes of a radix-16 pass spread over the banks.
-__device__ __forceinline__ int at(int x) { return x + (x >> 4); }
-constexpr int lds_points(int p) { return p + p / 16; }
+// writes of a radix-16 pass spread over the banks, and two more after every
+// row of 2^rs >= 64 points (rs = 31: none), so that the same order of
+// neighbouring rows, which the F loads and stores touch together, falls in
+// different banks.
+__device__ __forceinline__ int at(int x, int rs) { return x + (x >> 4) + ((x >> rs) << 1); }
+// row shift for rows of 2^lgK points
+__device__ __forceinline__ int row_shift(int lgK) { return lgK >= 6 ? lgK : 31; }
+// slots for p points, whatever the row length
+constexpr int lds_points(int p) { return p + p / 16 + p / 32; }
+// twiddle t of the K-entry table in LDS, padded like the points: the
+// strided reads of a pass's twiddles spread over the banks
+__device__ __forceinline__ int tw_at(int t) { return t + (t >> 4); }
+constexpr int tw_slots(int K) { return K + K / 16; }
 
 struct FftArgs {
     const DevPlan* plans;
@@ -173,6 +183,7 @@ template <int P, int R, int LGR, bool ZIN = false>
 __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, int lgK, int npts, int lgNs,
                                               int dir, const double2 (*zw)[R] = nullptr)
 {
+    const int rs = row_shift(lgK);
     static_assert(R <= P, "a thread holds whole butterflies");
     constexpr int NB = P / R;
     const int lgKR = lgK - LGR;
@@ -192,24 +203,25 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
 #pragma unroll
                 for (int q = 0; q < R; q++) {
                     const int m = jj + q * KR;
-                    const double2 ym = buf[at(rowb + m)];
-                    const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(rowb + (1 << lgK) - m)];
+                    const double2 ym = buf[at(rowb + m, rs)];
+                    const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(rowb + (1 << lgK) - m, rs)];
                     const double2 sm = cadd(ym, cconj(yc)), d = csub(ym, cconj(yc));
                     v[i][q] = cadd(sm, cmuli(cmul(zw[i][q], d), 1));
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < R; q++) v[i][q] = buf[at(rowb + jj + q * KR)];
+                for (int q = 0; q < R; q++) v[i][q] = buf[at(rowb + jj + q * KR, rs)];
             }
             if (lgNs > 0) {  // the first pass has js = 0: all twiddles are 1
-                // twiddle index q js K / (Ns R)
-                const int tstep = js << (lgK - lgNs - LGR);
+                // twiddle q is w^q, w = table entry js K / (Ns R): one read,
+                // the powers by products at most four deep
+                double2 w[R];
+                w[1] = twl[tw_at(js << (lgK - lgNs - LGR))];
+                if (dir > 0) w[1] = cconj(w[1]);
 #pragma unroll
-                for (int q = 1; q < R; q++) {
-                    double2 w = twl[q * tstep];
-                    if (dir > 0) w = cconj(w);
-                    v[i][q] = cmul(v[i][q], w);
-                }
+                for (int q = 2; q < R; q++) w[q] = cmul(w[q >> 1], w[q - (q >> 1)]);
+#pragma unroll
+                for (int q = 1; q < R; q++) v[i][q] = cmul(v[i][q], w[q]);
             }
             dft_r<R>(v[i], dir);
             dst[i] = rowb + (((jj >> lgNs) << (lgNs + LGR)) | js);
@@ -220,7 +232,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
     for (int i = 0; i < NB; i++) {
         if (dst[i] >= 0) {
 #pragma unroll
-            for (int q = 0; q < R; q++) buf[at(dst[i] + (q << lgNs))] = v[i][out_slot<R>(q)];
+            for (int q = 0; q < R; q++) buf[at(dst[i] + (q << lgNs), rs)] = v[i][out_slot<R>(q)];
         }
     }
     __syncthreads();
@@ -257,7 +269,7 @@ __device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, in
 // Copies the K-entry table e^{-2 pi i t/K} from global memory to LDS.
 __device__ __forceinline__ void stage_twiddles(double2* twl, gdp tw, int K)
 {
-    for (int t = threadIdx.x; t < K; t += blockDim.x) twl[t] = ld2(tw, t);
+    for (int t = threadIdx.x; t < K; t += blockDim.x) twl[tw_at(t)] = ld2(tw, t);
 }
 
 struct RowBlock {
@@ -296,6 +308,7 @@ template <int P, bool LOAD>
 __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* Fout, long ts, int M,
                                        int lgK, int row0, int nrows)
 {
+    const int rs = row_shift(lgK);
     const int run = nrows < kFTile ? nrows : kFTile;  // rows per tile in the block
     const bool pow2 = (run & (run - 1)) == 0;
     if (LOAD && pow2 && nrows <= kFTile && (row0 & (nrows - 1)) == 0) {
@@ -318,7 +331,7 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
         for (int k = 0; k < P; k++) {
             const int e = threadIdx.x + k * blockDim.x;
             const int m = e >> lg, r = e & (nrows - 1);
-            if (e < n) buf[at((r << lgK) + m)] = make_double2(v[k].x, m == 0 ? 0.0 : v[k].y);
+            if (e < n) buf[at((r << lgK) + m, rs)] = make_double2(v[k].x, m == 0 ? 0.0 : v[k].y);
         }
         return;
     }
@@ -332,7 +345,7 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
         for (int k = 0; k < P; k++) {
             const int e = threadIdx.x + k * blockDim.x;
             const int ec = e < n ? e : 0;
-            v[k] = buf[at(((ec & (nrows - 1)) << lgK) + (ec >> lg))];
+            v[k] = buf[at(((ec & (nrows - 1)) << lgK) + (ec >> lg), rs)];
         }
 #pragma unroll
         for (int k = 0; k < P; k++) {
@@ -354,9 +367,9 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
                 if (LOAD) {
                     double2 y = *(const double2*)(Fin + 2 * off);
                     if (m == 0) y.y = 0.0;
-                    buf[at((r << lgK) + m)] = y;
+                    buf[at((r << lgK) + m, rs)] = y;
                 } else {
-                    *(double2*)(Fout + 2 * off) = buf[at((r << lgK) + m)];
+                    *(double2*)(Fout + 2 * off) = buf[at((r << lgK) + m, rs)];
                 }
             }
         }
@@ -369,9 +382,9 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
             if (LOAD) {
                 double2 y = *(const double2*)(Fin + 2 * off);
                 if (m == 0) y.y = 0.0;
-                buf[at((r << lgK) + m)] = y;
+                buf[at((r << lgK) + m, rs)] = y;
             } else {
-                *(double2*)(Fout + 2 * off) = buf[at((r << lgK) + m)];
+                *(double2*)(Fout + 2 * off) = buf[at((r << lgK) + m, rs)];
             }
         }
     }
@@ -389,7 +402,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     const RowBlock rb = row_block(a, D.nlat);
     if (rb.field >= a.nfields || rb.nrows <= 0) return;
     const int K = D.K, M = D.M, nlat = D.nlat, nphi = D.nphi;
-    const int lgK = __builtin_ctz(K);
+    const int lgK = __builtin_ctz(K), rs = row_shift(lgK);
     const gdp tw = (gdp)D.tw;
     const gdp rtw = (gdp)D.rtw;
     const double* F = a.in + (a.f_off ? a.f_off[rb.field] : (long)rb.field * 2 * D.f_size);
@@ -413,7 +426,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     }
     // Y_m (Y_0 = Re F_0, Y_m = F_m for 1 <= m <= M, 0 above) row by row
     for (int idx = threadIdx.x; idx < npts; idx += blockDim.x)
-        if ((idx & (K - 1)) > M) buf[at(idx)] = make_double2(0.0, 0.0);
+        if ((idx & (K - 1)) > M) buf[at(idx, rs)] = make_double2(0.0, 0.0);
     move_f<P, true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
     stage_twiddles(twl, tw, K);
     __syncthreads();
@@ -428,8 +441,8 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
             z[e] = make_double2(0.0, 0.0);
             if (idx < npts) {
                 const int m = idx & (K - 1);
-                const double2 ym = buf[at(idx)];
-                const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(idx - m + (K - m))];
+                const double2 ym = buf[at(idx, rs)];
+                const double2 yc = m == 0 ? make_double2(0.0, 0.0) : buf[at(idx - m + (K - m), rs)];
                 const double2 s = cadd(ym, cconj(yc)), d = csub(ym, cconj(yc));
                 z[e] = cadd(s, cmuli(cmul(rw[e], d), 1));
             }
@@ -438,7 +451,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
 #pragma unroll
         for (int e = 0; e < P; e++) {
             const int idx = threadIdx.x + e * blockDim.x;
-            if (idx < npts) buf[at(idx)] = z[e];
+            if (idx < npts) buf[at(idx, rs)] = z[e];
         }
         __syncthreads();
         complex_fft<P>(buf, twl, lgK, npts, +1);
@@ -448,7 +461,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
         const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) {
             const int r = idx >> lgK, k = idx & (K - 1);
-            *(double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k) = buf[at(idx)];
+            *(double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k) = buf[at(idx, rs)];
         }
     }
 }
@@ -465,7 +478,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
     const RowBlock rb = row_block(a, D.nlat);
     if (rb.field >= a.nfields || rb.nrows <= 0) return;
     const int K = D.K, M = D.M, nlat = D.nlat, nphi = D.nphi;
-    const int lgK = __builtin_ctz(K);
+    const int lgK = __builtin_ctz(K), rs = row_shift(lgK);
     const gdp tw = (gdp)D.tw;
     const gdp rtw = (gdp)D.rtw;
     const double* g = a.in + (a.g_off ? a.g_off[rb.field] : (long)rb.field * nlat * nphi);
@@ -498,7 +511,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
     }
     stage_twiddles(twl, tw, K);
 #pragma unroll
-    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x)] = v[e];
+    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x, rs)] = v[e];
 
     __syncthreads();
     complex_fft<P>(buf, twl, lgK, npts, -1);
@@ -523,7 +536,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
             const int idx = threadIdx.x + e * blockDim.x;
             const int ec = idx < nout ? idx : 0;
             const int m = ec >> lgr, rbase = (ec & (rb.nrows - 1)) << lgK;
-            x[e] = post(buf[at(rbase + m)], cconj(buf[at(rbase + ((K - m) & (K - 1)))]), rw[e], m);
+            x[e] = post(buf[at(rbase + m, rs)], cconj(buf[at(rbase + ((K - m) & (K - 1)), rs)]), rw[e], m);
         }
 #pragma unroll
         for (int e = 0; e < P; e++) {
@@ -543,11 +556,11 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
     for (int e = 0; e < P; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
         const int m = idx & (K - 1);
-        x[e] = post(buf[at(idx)], cconj(buf[at(idx - m + ((K - m) & (K - 1)))]), rw[e], m);
+        x[e] = post(buf[at(idx, rs)], cconj(buf[at(idx - m + ((K - m) & (K - 1)), rs)]), rw[e], m);
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x)] = x[e];
+    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x, rs)] = x[e];
     __syncthreads();
     move_f<P, false>(buf, nullptr, F, D.f_ts, M, lgK, rb.row0, rb.nrows);
 }
@@ -573,7 +586,7 @@ static int fft_threads(int points, int P)
 // plus the K twiddles.
 static size_t fft_lds_bytes(int threads, int P, int K)
 {
-    return sizeof(double2) * ((size_t)lds_points(threads * P) + K);
+    return sizeof(double2) * ((size_t)lds_points(threads * P) + tw_slots(K));
 }
 
 // Allows the largest dynamic LDS of these kernels (above the 64 KB default).
