@@ -161,6 +161,7 @@ FftLaunch fft_launch(const Plan& p, const double* in, double* out, int nfields, 
     f.points = f.rows_per_block * p.K;
     f.grid_y = nfields;
     f.K = p.K;
+    f.uniform_k = 1;
     f.in = in;
     f.out = out;
     f.nfields = nfields;

@@ -283,6 +283,14 @@ size_t packed_bytes(const shtn_batch_s& b, Data k)
 
 // A batch call reading packed fields of kind kin at `in` and writing packed
 // fields of kind kout at `out`, with the workspace at `work`.
+// 1 if every plan of the batch has rows of the same length.
+int uniform_k(const shtn_batch_s& b)
+{
+    for (const Plan* p : b.plans)
+        if (p->K != b.fft_kmax) return 0;
+    return 1;
+}
+
 int check_batch(const shtn_batch_s* b, const void* in, Data kin, const void* out, Data kout, const void* work)
 {
     if (!b) return set_error(SHTN_EINVAL, "null batch");
@@ -367,6 +375,7 @@ int run_synth(const shtn_batch_s& b, const double* Q, double* grid, void* work, 
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
     f.K = b.fft_kmax;
+    f.uniform_k = uniform_k(b);
     f.points = b.fft_points;
     f.nblocks = (int)(b.rowblocks.size() / 4);
     f.grid_y = 1;
@@ -393,6 +402,7 @@ int run_analys(const shtn_batch_s& b, const double* grid, double* Q, void* work,
     f.plans = plans;
     f.rowblocks = dev_at<const int>(b, b.off_rb);
     f.K = b.fft_kmax;
+    f.uniform_k = uniform_k(b);
     f.points = b.fft_points;
     f.nblocks = (int)(b.rowblocks.size() / 4);
     f.grid_y = 1;

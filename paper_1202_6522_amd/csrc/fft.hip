@@ -391,7 +391,9 @@ __device__ __forceinline__ void move_f(double2* buf, const double* Fin, double* 
 }
 
 // Fourier synthesis of rows: f_ik = Re F_0 + 2 Re sum_{m=1}^{M} F_m e^{2 pi i m k / N}.
-template <int P>
+// LGK > 0: every row of the launch has K = 2^LGK points, so the passes and
+// all index arithmetic are fixed at compile time; LGK = 0: K per block.
+template <int P, int LGK>
 __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
 {
     extern __shared__ double2 lds[];  // points (P per thread), then the twiddle table
@@ -401,8 +403,8 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
     if (rb.field >= a.nfields || rb.nrows <= 0) return;
-    const int K = D.K, M = D.M, nlat = D.nlat, nphi = D.nphi;
-    const int lgK = __builtin_ctz(K), rs = row_shift(lgK);
+    const int K = LGK > 0 ? 1 << LGK : D.K, M = D.M, nlat = D.nlat, nphi = D.nphi;
+    const int lgK = LGK > 0 ? LGK : __builtin_ctz(K), rs = row_shift(lgK);
     const gdp tw = (gdp)D.tw;
     const gdp rtw = (gdp)D.rtw;
     const double* F = a.in + (a.f_off ? a.f_off[rb.field] : (long)rb.field * 2 * D.f_size);
@@ -466,8 +468,9 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     }
 }
 
-// Fourier analysis of rows: F_m(theta_i) = scale * sum_k f_ik e^{-2 pi i m k / N}, m <= M.
-template <int P>
+// Fourier analysis of rows: F_m(theta_i) = scale * sum_k f_ik e^{-2 pi i m k / N}, m <= M
+// (LGK as for k_c2r).
+template <int P, int LGK>
 __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
 {
     extern __shared__ double2 lds[];  // points (P per thread), then the twiddle table
@@ -477,8 +480,8 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
     if (rb.field >= a.nfields || rb.nrows <= 0) return;
-    const int K = D.K, M = D.M, nlat = D.nlat, nphi = D.nphi;
-    const int lgK = __builtin_ctz(K), rs = row_shift(lgK);
+    const int K = LGK > 0 ? 1 << LGK : D.K, M = D.M, nlat = D.nlat, nphi = D.nphi;
+    const int lgK = LGK > 0 ? LGK : __builtin_ctz(K), rs = row_shift(lgK);
     const gdp tw = (gdp)D.tw;
     const gdp rtw = (gdp)D.rtw;
     const double* g = a.in + (a.g_off ? a.g_off[rb.field] : (long)rb.field * nlat * nphi);
@@ -590,39 +593,55 @@ static size_t fft_lds_bytes(int threads, int P, int K)
 }
 
 // Allows the largest dynamic LDS of these kernels (above the 64 KB default).
-template <int P>
+template <int P, int LGK>
 static int allow_lds()
 {
     static const int rc = [] {
         const int bytes = (int)fft_lds_bytes(fft_max_threads(P), P, kFftPoints);
-        hipError_t e = hipFuncSetAttribute((const void*)k_c2r<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        hipError_t e =
+            hipFuncSetAttribute((const void*)k_c2r<P, LGK>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_r2c<P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            e = hipFuncSetAttribute((const void*)k_r2c<P, LGK>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         return (int)e;
     }();
     return rc;
 }
 
-template <int P, bool C2R>
+template <int P, int LGK, bool C2R>
 static int launch_fft_t(const FftLaunch& l, void* stream)
 {
-    if (int e = allow_lds<P>()) return e;
+    if (int e = allow_lds<P, LGK>()) return e;
     const int nt = fft_threads(l.points, P);
     if (nt * P < l.points) return (int)hipErrorInvalidValue;
     const size_t lds = fft_lds_bytes(nt, P, l.K);
     if (C2R)
-        hipLaunchKernelGGL(k_c2r<P>, dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream, fft_args(l));
+        hipLaunchKernelGGL((k_c2r<P, LGK>), dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream,
+                           fft_args(l));
     else
-        hipLaunchKernelGGL(k_r2c<P>, dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream, fft_args(l));
+        hipLaunchKernelGGL((k_r2c<P, LGK>), dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream,
+                           fft_args(l));
     return (int)hipGetLastError();
 }
 
-// One points-per-thread variant per launch, chosen by its longest rows.
+// One points-per-thread variant per launch, chosen by its longest rows; when
+// every row has the same K = 64 ... 4096 points, the variant built for it.
 template <bool C2R>
 static int launch_fft(const FftLaunch& l, void* stream)
 {
     if (l.K < 1 || l.K > kFftPoints || l.points < l.K || l.points > kFftPoints) return (int)hipErrorInvalidValue;
-    return fft_pts(l.K) == 8 ? launch_fft_t<8, C2R>(l, stream) : launch_fft_t<16, C2R>(l, stream);
+    if (l.uniform_k) {
+        switch (l.K) {
+        case 64: return launch_fft_t<8, 6, C2R>(l, stream);
+        case 128: return launch_fft_t<8, 7, C2R>(l, stream);
+        case 256: return launch_fft_t<8, 8, C2R>(l, stream);
+        case 512: return launch_fft_t<8, 9, C2R>(l, stream);
+        case 1024: return launch_fft_t<8, 10, C2R>(l, stream);
+        case 2048: return launch_fft_t<8, 11, C2R>(l, stream);
+        case 4096: return launch_fft_t<16, 12, C2R>(l, stream);
+        default: break;
+        }
+    }
+    return fft_pts(l.K) == 8 ? launch_fft_t<8, 0, C2R>(l, stream) : launch_fft_t<16, 0, C2R>(l, stream);
 }
 
 int launch_c2r(const FftLaunch& l, void* stream) { return launch_fft<true>(l, stream); }

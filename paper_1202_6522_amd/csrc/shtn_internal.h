@@ -339,6 +339,7 @@ struct FftLaunch {
     double* out;
     int nfields;
     double scale;             // r2c: output scale (2 pi/nphi or 1)
+    int uniform_k = 0;        // 1: every row of the launch has K points
 };
 int launch_c2r(const FftLaunch& a, void* stream);
 int fft_rows_cap(int K);     // rows of K complex points held by one FFT workgroup
