@@ -209,8 +209,11 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
                     v[i][q] = cadd(sm, cmuli(cmul(zw[i][q], d), 1));
                 }
             } else {
+                // jj < KR and q KR have no bit in common, and stay in the
+                // row: the slots are the first one plus fixed offsets
+                const int rd = at(rowb + jj, rs);
 #pragma unroll
-                for (int q = 0; q < R; q++) v[i][q] = buf[at(rowb + jj + q * KR, rs)];
+                for (int q = 0; q < R; q++) v[i][q] = buf[rd + q * KR + ((q * KR) >> 4)];
             }
             if (lgNs > 0) {  // the first pass has js = 0: all twiddles are 1
                 // twiddle q is w^q, w = table entry js K / (Ns R): one read,
@@ -231,8 +234,10 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
 #pragma unroll
     for (int i = 0; i < NB; i++) {
         if (dst[i] >= 0) {
+            // dst has no bit in [lgNs, lgNs + LGR), where q << lgNs lies
+            const int wr = at(dst[i], rs);
 #pragma unroll
-            for (int q = 0; q < R; q++) buf[at(dst[i] + (q << lgNs), rs)] = v[i][out_slot<R>(q)];
+            for (int q = 0; q < R; q++) buf[wr + (q << lgNs) + ((q << lgNs) >> 4)] = v[i][out_slot<R>(q)];
         }
     }
     __syncthreads();
