@@ -311,3 +311,27 @@ def test_tuner_ignores_damaged_cache_entries(dev, tmp_path):
     with open(cache, "w") as f:
         f.write(good + "\n")
     assert b.tune(Qp, g, a, reps=2, cache_path=cache) == -1.0
+
+
+def test_batch_of_one_row_length_against_oracle(dev):
+    # every field has nphi = 128 (K = 64 complex points per row), so the batch's
+    # longitude launches take the kernels built for that row length, with
+    # the per-block row tables; each field against the oracle
+    from paper_1202_6522_amd.shtn import Batch
+    shapes = [(63, 63, 64, 128), (40, 33, 51, 128), (63, 50, 64, 128), (21, 21, 30, 128)]
+    b = Batch(shapes, device=dev)
+    rng = np.random.default_rng(128)
+    specs = [inputs.draw_spectrum(rng, L, M, 1.0, 1)[0] for (L, M, _, _) in shapes]
+    gb = b.synth(b.pack_spectra(specs))
+    grids = []
+    for f, (L, M, nlat, nphi) in enumerate(shapes):
+        want = oracle.synth(specs[f][None], L, M, nlat, nphi)[0]
+        assert rel(b.field_grid(gb, f).cpu().numpy(), want) <= 1e-11, f
+        grids.append(rng.standard_normal((nlat, nphi)))
+    gp = b.new_grids()
+    for f, g in enumerate(grids):
+        b.field_grid(gp, f).copy_(torch.from_numpy(g))
+    ab = b.analys(gp)
+    for f, (L, M, nlat, nphi) in enumerate(shapes):
+        want = oracle.analys(grids[f][None], L, M, nlat, nphi)[0]
+        assert rel(b.field_spectrum(ab, f).cpu().numpy(), want) <= 1e-11, f

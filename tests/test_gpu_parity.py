@@ -65,6 +65,7 @@ EDGE = [
     (30, 30, 45, 64),
     (100, 20, 101, 64),
     (127, 127, 128, 256),
+    (255, 200, 256, 1024),
 ]
 
 
