@@ -693,6 +693,9 @@ __device__ __forceinline__ void analys_unit(
     AState<LP, FW> s;
     int sj[LP];
     const bool from_rst = rst >= 0 && js0 == j0;
+    // no lane starts inside the unit (window -1): its start states are not
+    // needed, all lanes come live from the restart state
+    const bool starts = jwin >= js0;
     {
         const bool odd = lane & 1;
         int pc[LP], jv[LP];
@@ -707,8 +710,13 @@ __device__ __forceinline__ void analys_unit(
             const size_t q = (size_t)m * npair + pc[p];
             xv[p] = P->xp[pc[p]];
             wl[p] = P->wq[pc[p]];
-            y[p] = *(const double2*)(P->inj_y + 2 * q);
-            jv[p] = P->inj_j[q];
+            if (starts) {
+                y[p] = *(const double2*)(P->inj_y + 2 * q);
+                jv[p] = P->inj_j[q];
+            } else {
+                y[p] = make_double2(0.0, 0.0);
+                jv[p] = nj;
+            }
 #pragma unroll
             for (int f = 0; f < FW; f++) {
                 const double* F = a.in + foff[f];

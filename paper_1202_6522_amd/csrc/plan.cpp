@@ -509,15 +509,16 @@ int rebuild_units(Plan& p, std::string& err)
         // may skip ahead (in whole segments) to its first start
         const bool live0 = start_range(p, m, 0, np, 0, j0 + (j0 == 0 ? 1 : 0), jmin, jmax);
         int js, jw;
+        // jw: the last start step inside the piece, -1 if no lane starts in it
         if (live0) {
             js = j0;
-            jw = start_range(p, m, 0, np, j0, j1, jmin, jmax) ? jmax : j0;
+            jw = start_range(p, m, 0, np, j0, j1, jmin, jmax) ? jmax : -1;
         } else if (start_range(p, m, 0, np, j0, j1, jmin, jmax)) {
             js = j0 + ((jmin - j0) / kSegLen) * kSegLen;
             jw = jmax;
         } else {
             js = j1;  // nothing starts: the piece only writes zeros
-            jw = j1;
+            jw = -1;
         }
         int r = -1;
         if (j0 > 0) {

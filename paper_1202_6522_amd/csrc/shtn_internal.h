@@ -67,7 +67,7 @@ enum UnitField {
     U_PLAN = 2,   // plan index (batch) or 0
     U_M = 3,      // order m, or -1 for a unit without work
     U_JS = 4,     // first step executed (lanes start there or later)
-    U_JW = 5,     // last step at which a lane of the unit starts (injection window)
+    U_JW = 5,     // last step at which a lane of the unit starts (injection window; analysis: -1 if none)
     U_PB = 6,     // synthesis: first latitude pair of the block; analysis: first output step j0
     U_J1 = 7,     // analysis: one past the last output step
     U_RST = 8,    // analysis: restart slot of j0 or -1 (j0 = 0)
