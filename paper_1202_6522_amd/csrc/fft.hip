@@ -13,11 +13,11 @@
 // needs many waves in flight, on every SIMD.  A workgroup holds rows x K <=
 // 4096 points in LDS (whole rows; at lmax 1023 four rows, so that the reads
 // of F, stored in tiles of eight latitudes per order, come in 64-byte runs)
-// next to the K twiddles e^{-2 pi i t/K} (at most 135 KB), with one thread
-// per P points: P = 8 up to K = 2048 (512 threads: at lmax 1023 2048 waves,
-// two per SIMD), 16 at K = 4096.  Every thread owns P points
-// of every pass (P/R butterflies of radix R); all index arithmetic is shifts
-// and masks (K is a power of two).  The rows and the pre/post-pass twiddles
+// next to the K twiddles e^{-2 pi i t/K} (at most 141 KB with the padding
+// against bank conflicts), with one thread per P points: P = 8 up to
+// K = 2048 (512 threads: at lmax 1023 2048 waves, two per SIMD), 16 at
+// K = 4096.  Every thread owns P points of every pass (P/R butterflies of
+// radix R); all index arithmetic is shifts and masks (K is a power of two).  The rows and the pre/post-pass twiddles
 // are requested before anything waits for memory, the twiddle table goes to
 // LDS while they arrive.  Row blocks are spread over the XCDs so that
 // neighbouring blocks share an L2.
