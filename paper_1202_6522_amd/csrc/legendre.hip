@@ -400,16 +400,22 @@ __global__ void __launch_bounds__((synth_max_threads<LP, FW>())) k_legendre_synt
         shn = js + kSegLen < nj ? segexp[js / kSegLen + 1] : 0;
         if (je - js == kSegLen) {
             constexpr int NS = SBlock<FW>::NS;
+            // operands of the segment from one base pointer per table, so
+            // that the block loads take fixed offsets
+            const cdp bseg = bet + js;
+            cdp qseg[FW];
+#pragma unroll
+            for (int f = 0; f < FW; f++) qseg[f] = qs[f] + 2 * js;
 #pragma unroll
             for (int bk = 0; bk < kSegLen; bk += NS) {
                 if (FW == 1) {
                     SBlock<FW> nxt;
-                    load_block(nxt, bet, qs, js + bk + NS);
+                    load_block(nxt, bseg, qseg, bk + NS);
                     synth_block(s, cur, NS);
                     cur = nxt;
                 } else {
                     SBlock<FW> b0;
-                    load_block(b0, bet, qs, js + bk);
+                    load_block(b0, bseg, qseg, bk);
                     synth_block(s, b0, NS);
                 }
             }
