@@ -10,7 +10,10 @@ roofline: the dominant Legendre kernel, algorithmic FP64 work
 launch duration, timed with HIP event pairs recorded by the library on the
 launch stream during the timed steps (only around that kernel: each event
 pair costs GPU time between kernels); peak = FP64 vector 78.6 TFLOP/s.
-kernels_us: every kernel timed the same way in an untimed pass before.
+kernels_us: every kernel timed the same way in an untimed pass before; the
+other Legendre kernel again in an untimed pass of its own, with only its
+event pairs (as for the dominant one: events around every kernel lengthen
+the synthesis by a few per cent, see rocprofv3).
 cpu_baseline: the oracle (plain C, OpenMP) doing full synthesis + analysis
 round trips of the same workload on the host cores for at least 10 s.
 """
@@ -457,6 +460,17 @@ def main():
         kern[name] = {"avg_us": 1e3 * tot / max(n, 1), "launches": n}
     dom = max(("legendre_synth", "legendre_analys"), key=lambda k: kern[k]["avg_us"])
     dom_kind = [k for k, v in S.PROFILE_KINDS.items() if v == dom][0]
+    other = "legendre_synth" if dom == "legendre_analys" else "legendre_analys"
+    other_kind = [k for k, v in S.PROFILE_KINDS.items() if v == other][0]
+    S.shtn_profile_select([other_kind])
+    S.shtn_profile_reset()
+    S.shtn_profile_enable(True)
+    for _ in range(pre):
+        step()
+    torch.cuda.synchronize(dev)
+    S.shtn_profile_enable(False)
+    tot, n = S.shtn_profile_read(other_kind)
+    kern[other] = {"avg_us": 1e3 * tot / max(n, 1), "launches": n}
 
     # the timed region: only the dominant kernel is bracketed by events (each
     # event pair costs GPU time between kernels, which would count in `value`)
