@@ -163,3 +163,19 @@ def test_batch_ranges(dev):
     refused(lib.shtn_batch_capture(b.handle, 1, p(G.data_ptr()), p(G.data_ptr() + 8), p(b.work)),
             ["input", "output"])
     torch.cuda.synchronize(dev)
+
+
+def test_noalloc_ranges(dev):
+    # the static-workspace synthesis checks its input and output the same way
+    from paper_1202_6522_amd import shtn as S
+    lib = S.load_library()
+    plan = S.Plan(L, L, NLAT, NPHI, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    sb, gb = plan.nlm * 16, NLAT * NPHI * 8
+    a = Arena(sb + gb, dev)
+    p = lambda off: ctypes.c_void_p(a.ptr(off))
+    assert lib.shtn_synth_noalloc(plan.handle, p(0), p(sb), 1, stream) == S.SHTN_OK
+    assert lib.shtn_synth_noalloc(plan.handle, p(0), p(sb - 16), 1, stream) == S.SHTN_EINVAL
+    detail = lib.shtn_last_error_detail().decode()
+    assert "overlaps" in detail and "input" in detail and "output" in detail, detail
+    torch.cuda.synchronize(dev)
