@@ -243,8 +243,83 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
     __syncthreads();
 }
 
+// v of the neighbouring lane (lanes 2i and 2i + 1 swap; DPP quad_perm
+// [1,0,3,2]; every lane takes part).
+__device__ __forceinline__ double swap_pair(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double2 swap_pair(double2 v) { return make_double2(swap_pair(v.x), swap_pair(v.y)); }
+
+// The last radix-P pass (stage Ns = K/(2P)) and the radix-2 pass after it in
+// one LDS round trip.  The outputs of radix-P butterflies js and js + Ns
+// land K/2 apart, which is what the radix-2 pass pairs; they run on lanes 2i
+// and 2i + 1, which swap half of their outputs and finish the radix-2
+// butterflies of the even (lane 2i) and odd (lane 2i + 1) output slots.
+// One butterfly per thread (P points), as stockham_pass<P, P, ...>.
+template <int P, int LGP>
+__device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl, int lgK, int npts, int dir)
+{
+    const int rs = row_shift(lgK);
+    const int lgNs = lgK - LGP - 1, Ns = 1 << lgNs;
+    const int lgKR = lgK - LGP, KR = 1 << lgKR;  // 2 Ns radix-P butterflies per row
+    const int nb = npts >> LGP;                 // even: lanes 2i and 2i + 1 are valid together
+    const bool valid = (int)threadIdx.x < nb;
+    const int bc = valid ? (int)threadIdx.x : 0;
+    const int r = bc >> lgKR, u = bc & (KR - 1);
+    const int half = u & 1, js = u >> 1;
+    const int rowb = r << lgK;
+    double2 v[P];
+    const int rd = at(rowb + (half << lgNs) + js, rs);
+#pragma unroll
+    for (int q = 0; q < P; q++) v[q] = buf[rd + q * KR + ((q * KR) >> 4)];
+    if (lgNs > 0) {
+        double2 w[P];
+        w[1] = twl[tw_at(js << (lgK - lgNs - LGP))];
+        if (dir > 0) w[1] = cconj(w[1]);
+#pragma unroll
+        for (int q = 2; q < P; q++) w[q] = cmul(w[q >> 1], w[q - (q >> 1)]);
+#pragma unroll
+        for (int q = 1; q < P; q++) v[q] = cmul(v[q], w[q]);
+    }
+    dft_r<P>(v, dir);
+    // output slot q of this lane's butterfly: v[out_slot<P>(q)], at js + q Ns
+    // of its half of the row
+    double2 lo[P / 2], hi[P / 2];
+#pragma unroll
+    for (int k = 0; k < P / 2; k++) {
+        // (fixed register indices, the lane's choice by selects)
+        const double2 ev = v[out_slot<P>(2 * k)], od = v[out_slot<P>(2 * k + 1)];
+        const double2 mine = half ? od : ev;
+        const double2 got = swap_pair(half ? ev : od);
+        const double2 a = half ? got : mine, b = half ? mine : got;
+        double2 w = twl[tw_at(js + (2 * k + half) * Ns)];
+        if (dir > 0) w = cconj(w);
+        const double2 t = cmul(w, b);
+        lo[k] = cadd(a, t);
+        hi[k] = csub(a, t);
+    }
+    __syncthreads();
+    if (valid) {
+        const int wr = at(rowb + js, rs);
+        const int K2 = 1 << (lgK - 1);
+#pragma unroll
+        for (int k = 0; k < P / 2; k++) {
+            const int o = (2 * k + half) * Ns;  // js + o and K/2 + js + o: no bit of js in o
+            buf[wr + o + (o >> 4)] = lo[k];
+            buf[wr + K2 + o + ((K2 + o) >> 4)] = hi[k];
+        }
+    }
+    __syncthreads();
+}
+
 // Complex FFT of length K = 2^lgK on every row held in buf: radix P while
-// lg P or more factors of 2 remain, then one radix-4 and/or radix-2 pass.
+// lg P or more factors of 2 remain, then one radix-4 and/or radix-2 pass
+// (with eight points per thread a last radix-2 pass joins the radix-8 one
+// before it).
 template <int P>
 constexpr int lg_pts() { return P == 16 ? 4 : (P == 8 ? 3 : 2); }
 
@@ -261,6 +336,10 @@ __device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, in
         lgNs = LGP;
     }
     while (lgK - lgNs >= LGP) {
+        if (P == 8 && lgK - lgNs == LGP + 1) {
+            stockham_last2<P, LGP>(buf, twl, lgK, npts, dir);
+            return;
+        }
         stockham_pass<P, P, LGP>(buf, twl, lgK, npts, lgNs, dir);
         lgNs += LGP;
     }
