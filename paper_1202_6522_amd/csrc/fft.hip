@@ -259,9 +259,12 @@ __device__ __forceinline__ double2 swap_pair(double2 v) { return make_double2(sw
 // land K/2 apart, which is what the radix-2 pass pairs; they run on lanes 2i
 // and 2i + 1, which swap half of their outputs and finish the radix-2
 // butterflies of the even (lane 2i) and odd (lane 2i + 1) output slots.
-// One butterfly per thread (P points), as stockham_pass<P, P, ...>.
+// One butterfly per thread (P points), as stockham_pass<P, P, ...>.  With
+// gout the results go straight to global memory (row r of the block at
+// gout + r gstride, point p as the doubles 2p, 2p + 1) instead of buf.
 template <int P, int LGP>
-__device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl, int lgK, int npts, int dir)
+__device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl, int lgK, int npts, int dir,
+                                               double* gout, size_t gstride)
 {
     const int rs = row_shift(lgK);
     const int lgNs = lgK - LGP - 1, Ns = 1 << lgNs;
@@ -302,10 +305,22 @@ __device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl,
         lo[k] = cadd(a, t);
         hi[k] = csub(a, t);
     }
+    const int K2 = 1 << (lgK - 1);
+    if (gout) {
+        if (valid) {
+            double* row = gout + (size_t)r * gstride + 2 * js;
+#pragma unroll
+            for (int k = 0; k < P / 2; k++) {
+                const int o = (2 * k + half) * Ns;
+                *(double2*)(row + 2 * o) = lo[k];
+                *(double2*)(row + 2 * (K2 + o)) = hi[k];
+            }
+        }
+        return;
+    }
     __syncthreads();
     if (valid) {
         const int wr = at(rowb + js, rs);
-        const int K2 = 1 << (lgK - 1);
 #pragma unroll
         for (int k = 0; k < P / 2; k++) {
             const int o = (2 * k + half) * Ns;  // js + o and K/2 + js + o: no bit of js in o
@@ -324,10 +339,13 @@ template <int P>
 constexpr int lg_pts() { return P == 16 ? 4 : (P == 8 ? 3 : 2); }
 
 // zw non-null: the first pass is of radix P (lgK >= lg P) and forms the
-// synthesis's Z from Y in buf (see stockham_pass).
+// synthesis's Z from Y in buf (see stockham_pass).  gout non-null: when the
+// last passes are the joined radix-8 and radix-2 ones, they store the result
+// there (see stockham_last2) and the call returns true; else it is in buf.
 template <int P>
-__device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, int lgK, int npts, int dir,
-                                            const double2 (*zw)[P] = nullptr)
+__device__ __forceinline__ bool complex_fft(double2* buf, const double2* twl, int lgK, int npts, int dir,
+                                            const double2 (*zw)[P] = nullptr, double* gout = nullptr,
+                                            size_t gstride = 0)
 {
     constexpr int LGP = lg_pts<P>();
     int lgNs = 0;
@@ -337,8 +355,8 @@ __device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, in
     }
     while (lgK - lgNs >= LGP) {
         if (P == 8 && lgK - lgNs == LGP + 1) {
-            stockham_last2<P, LGP>(buf, twl, lgK, npts, dir);
-            return;
+            stockham_last2<P, LGP>(buf, twl, lgK, npts, dir, gout, gstride);
+            return gout != nullptr;
         }
         stockham_pass<P, P, LGP>(buf, twl, lgK, npts, lgNs, dir);
         lgNs += LGP;
@@ -348,6 +366,7 @@ __device__ __forceinline__ void complex_fft(double2* buf, const double2* twl, in
         lgNs += 2;
     }
     if (lgK - lgNs == 1) stockham_pass<P, 2, 1>(buf, twl, lgK, npts, lgNs, dir);
+    return false;
 }
 
 // Copies the K-entry table e^{-2 pi i t/K} from global memory to LDS.
@@ -516,9 +535,11 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     move_f<P, true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
     stage_twiddles(twl, tw, K);
     __syncthreads();
+    double* grow = g + (size_t)rb.row0 * nphi;  // the block's first grid row
+    bool stored;
     if (fused) {
         const double2(*zw)[P] = (const double2(*)[P])rw;
-        complex_fft<P>(buf, twl, lgK, npts, +1, zw);
+        stored = complex_fft<P>(buf, twl, lgK, npts, +1, zw, grow, nphi);
     } else {
         double2 z[P];
 #pragma unroll
@@ -540,14 +561,15 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
             if (idx < npts) buf[at(idx, rs)] = z[e];
         }
         __syncthreads();
-        complex_fft<P>(buf, twl, lgK, npts, +1);
+        stored = complex_fft<P>(buf, twl, lgK, npts, +1, nullptr, grow, nphi);
     }
+    if (stored) return;
 #pragma unroll
     for (int e = 0; e < P; e++) {
         const int idx = threadIdx.x + e * blockDim.x;
         if (idx < npts) {
             const int r = idx >> lgK, k = idx & (K - 1);
-            *(double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k) = buf[at(idx, rs)];
+            *(double2*)(grow + (size_t)r * nphi + 2 * k) = buf[at(idx, rs)];
         }
     }
 }
