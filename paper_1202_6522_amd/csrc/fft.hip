@@ -345,10 +345,10 @@ constexpr int lg_pts() { return P == 16 ? 4 : (P == 8 ? 3 : 2); }
 template <int P>
 __device__ __forceinline__ bool complex_fft(double2* buf, const double2* twl, int lgK, int npts, int dir,
                                             const double2 (*zw)[P] = nullptr, double* gout = nullptr,
-                                            size_t gstride = 0)
+                                            size_t gstride = 0, int lgNs0 = 0)
 {
     constexpr int LGP = lg_pts<P>();
-    int lgNs = 0;
+    int lgNs = lgNs0;
     if (zw) {
         stockham_pass<P, P, LGP, true>(buf, twl, lgK, npts, 0, dir, zw);
         lgNs = LGP;
@@ -597,11 +597,26 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
     // branches (idx < P blockDim stays inside the point buffer; slots past
     // npts are never read), so every load is issued before the first wait.
     double2 v[P];
+    // With lgK >= lg P the thread loads the P points of its butterfly of the
+    // first radix-P pass (jj + q K/P of its row), which then runs in
+    // registers; else the points idx = tid + e blockDim, put in LDS as they are.
+    constexpr int LGP = lg_pts<P>();
+    const bool first_in_regs = lgK >= LGP;
+    const int lgKR = lgK - LGP;
+    const int nb = npts >> LGP;
+    const int bc = (int)threadIdx.x < nb ? (int)threadIdx.x : 0;
 #pragma unroll
     for (int e = 0; e < P; e++) {
-        const int idx = threadIdx.x + e * blockDim.x;
-        const int ic = idx < npts ? idx : 0;
-        const int r = ic >> lgK, k = ic & (K - 1);
+        int r, k;
+        if (first_in_regs) {
+            r = bc >> lgKR;
+            k = (bc & ((1 << lgKR) - 1)) + (e << lgKR);
+        } else {
+            const int idx = threadIdx.x + e * blockDim.x;
+            const int ic = idx < npts ? idx : 0;
+            r = ic >> lgK;
+            k = ic & (K - 1);
+        }
         v[e] = *(const double2*)(g + (size_t)(rb.row0 + r) * nphi + 2 * k);
     }
     // When the block is a power-of-two run of rows aligned inside an F tile
@@ -619,11 +634,24 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
         rw[e] = ld2(rtw, direct ? ((idx < nout ? idx : 0) >> lgr) : (idx & (K - 1)));
     }
     stage_twiddles(twl, tw, K);
+    if (first_in_regs) {
+        // the first pass (Ns = 1, no twiddles): DFT of the loaded points,
+        // outputs to slots (jj << lg P) + q of the row
+        dft_r<P>(v, -1);
+        if ((int)threadIdx.x < nb) {
+            const int r = bc >> lgKR, jj = bc & ((1 << lgKR) - 1);
+            const int wr = at((r << lgK) + (jj << LGP), rs);  // jj << lg P has no bit below lg P
 #pragma unroll
-    for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x, rs)] = v[e];
-
-    __syncthreads();
-    complex_fft<P>(buf, twl, lgK, npts, -1);
+            for (int q = 0; q < P; q++) buf[wr + q + (q >> 4)] = v[out_slot<P>(q)];
+        }
+        __syncthreads();
+        complex_fft<P>(buf, twl, lgK, npts, -1, nullptr, nullptr, 0, LGP);
+    } else {
+#pragma unroll
+        for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x, rs)] = v[e];
+        __syncthreads();
+        complex_fft<P>(buf, twl, lgK, npts, -1);
+    }
     // scale <= 0: the analysis scale 2 pi / nphi of each field's plan
     const double sc = a.scale > 0.0 ? a.scale : 2.0 * 3.14159265358979323846 / nphi;
     // X_m = (Z_m + conj Z_{K-m}) / 2 + conj(w^m) (Z_m - conj Z_{K-m}) / (2i),
