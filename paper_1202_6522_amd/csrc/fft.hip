@@ -19,8 +19,11 @@
 // K = 4096.  Every thread owns P points of every pass (P/R butterflies of
 // radix R); all index arithmetic is shifts and masks (K is a power of two).  The rows and the pre/post-pass twiddles
 // are requested before anything waits for memory, the twiddle table goes to
-// LDS while they arrive.  Row blocks are spread over the XCDs so that
-// neighbouring blocks share an L2.
+// LDS while they arrive.  Both directions load the points of each thread's
+// butterfly of the first radix-P pass straight into registers and run that
+// pass there; with P = 8 the last radix-8 pass and a radix-2 pass after it
+// share one LDS round trip, and the c2r stores the grid rows from it.  Row
+// blocks are spread over the XCDs so that neighbouring blocks share an L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -519,6 +522,60 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     // there is one (lgK >= lg P), else by a pass of its own.
     constexpr int LGP = lg_pts<P>();
     const bool fused = lgK >= LGP;
+    double* grow = g + (size_t)rb.row0 * nphi;  // the block's first grid row
+    // When the block is a power-of-two run of rows aligned inside an F tile
+    // (the usual case), each thread loads the points of its butterfly of the
+    // first pass, Y_m for m = jj + q K/P and their mirrors Y_{K-m}, straight
+    // from F (rows fastest over the threads: four threads read one 64-byte
+    // run of a tile), forms Z and runs that pass in registers: Y never goes
+    // through LDS.
+    if (fused && (rb.nrows & (rb.nrows - 1)) == 0 && rb.nrows <= kFTile && (rb.row0 & (rb.nrows - 1)) == 0) {
+        const int lgr = __builtin_ctz(rb.nrows);
+        const int lgKR = lgK - LGP;
+        const int nb = npts >> LGP;
+        const int bc = (int)threadIdx.x < nb ? (int)threadIdx.x : 0;
+        const int r = bc & (rb.nrows - 1), jj = bc >> lgr;
+        const double* Fr = F + 2 * ((long)(rb.row0 >> kFTileLg) * D.f_ts + (rb.row0 & (kFTile - 1)) + r);
+        // straight-line loads from valid addresses (orders above M read
+        // order 0 and are replaced by 0 below)
+        double2 ym[P], yc[P], rw[P];
+#pragma unroll
+        for (int q = 0; q < P; q++) {
+            const int m = jj + (q << lgKR), mc = K - m;  // mc = K only for m = 0
+            ym[q] = *(const double2*)(Fr + 2 * ((long)(m <= M ? m : 0) << kFTileLg));
+            yc[q] = *(const double2*)(Fr + 2 * ((long)(mc <= M ? mc : 0) << kFTileLg));
+            rw[q] = ld2(rtw, m);
+        }
+        stage_twiddles(twl, tw, K);
+        double2 v[P];
+#pragma unroll
+        for (int q = 0; q < P; q++) {
+            const int m = jj + (q << lgKR), mc = K - m;
+            const double2 y = m > M ? make_double2(0.0, 0.0) : make_double2(ym[q].x, m == 0 ? 0.0 : ym[q].y);
+            const double2 c = mc > M ? make_double2(0.0, 0.0) : yc[q];
+            const double2 sm = cadd(y, cconj(c)), d = csub(y, cconj(c));
+            v[q] = cadd(sm, cmuli(cmul(rw[q], d), 1));
+        }
+        // the first pass (Ns = 1, no twiddles): outputs to slots
+        // (jj << lg P) + q of the row
+        dft_r<P>(v, +1);
+        if ((int)threadIdx.x < nb) {
+            const int wr = at((r << lgK) + (jj << LGP), rs);  // jj << lg P has no bit below lg P
+#pragma unroll
+            for (int q = 0; q < P; q++) buf[wr + q + (q >> 4)] = v[out_slot<P>(q)];
+        }
+        __syncthreads();
+        if (complex_fft<P>(buf, twl, lgK, npts, +1, nullptr, grow, nphi, LGP)) return;
+#pragma unroll
+        for (int e = 0; e < P; e++) {
+            const int idx = threadIdx.x + e * blockDim.x;
+            if (idx < npts) {
+                const int rr = idx >> lgK, k = idx & (K - 1);
+                *(double2*)(grow + (size_t)rr * nphi + 2 * k) = buf[at(idx, rs)];
+            }
+        }
+        return;
+    }
     // w^m of the points this thread forms Z for, loaded while the rows arrive
     double2 rw[P];
     if (fused) {
@@ -535,7 +592,6 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     move_f<P, true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
     stage_twiddles(twl, tw, K);
     __syncthreads();
-    double* grow = g + (size_t)rb.row0 * nphi;  // the block's first grid row
     bool stored;
     if (fused) {
         const double2(*zw)[P] = (const double2(*)[P])rw;
