@@ -97,6 +97,9 @@ def check_all(plan, r, dev, label):
     dict(synth_lp=4, analys_lp=8, m_pairing=1, split=512, fft_rows=2),
     dict(synth_lp=2, analys_lp=4, analys_waves=2, m_pairing=0, split=256),
     dict(synth_lp=1, analys_lp=4, analys_waves=4, m_pairing=0),
+    # FFT blocks of three rows: the longitude kernels' general paths (F through
+    # LDS) at K = 1024, and a last block of one row
+    dict(synth_lp=1, analys_lp=8, m_pairing=0, fft_rows=3),
 ])
 def test_lmax1023_full_onthefly(tiling, ref1023, dev):
     from paper_1202_6522_amd.shtn import Plan
