@@ -610,8 +610,14 @@ __device__ __forceinline__ void start_slots(double (&ua)[LP], double (&ub)[LP], 
 // each lane pair's partial sums (one row per degree and field, one column
 // per thread: real parts in even columns, imaginary parts in odd ones) go to
 // LDS, while the sums of the previous pass are read back, added over the
-// columns (2W threads per output, padded rows) and stored: with several
-// waves the passes alternate between two buffers with one barrier per pass.
+// columns (2W threads per output, padded rows) and stored.  The rows live in
+// one buffer: one wave executes its LDS operations in order, so with W = 1
+// the reads of the previous pass, issued before this pass's writes, need no
+// barrier; with several waves a barrier after the reads lets every wave
+// finish reading before any wave writes, and one at the end of the pass
+// makes the rows visible.  (Two alternating buffers would save the first
+// barrier, but at W = 2 and 4 their LDS halves the workgroups a CU holds:
+// lmax 2047 and 4095 ran 14% and 33% slower that way.)
 // A workgroup of W waves covers 64 LP W latitude pairs: wave w takes pairs
 // [64 LP w, 64 LP (w + 1)), pair slot p of its lanes being the 64-pair block
 // LP w + p.  A pass runs as halves of kInject steps; each half first injects
@@ -630,10 +636,6 @@ struct AnalysGeom {
     // read distinct banks
     static constexpr int RS = NT + 2 * PR;
     static constexpr int NH = SC / kInject;  // halves per pass
-    // One wave executes its LDS operations in order, so with W = 1 the reads
-    // of the previous pass, issued before this pass's writes, need neither a
-    // second buffer nor a barrier.
-    static constexpr int NB = W == 1 ? 1 : 2;
 };
 
 // One unit: degrees [j0, j1) of one order for all latitude pairs (the
@@ -641,12 +643,11 @@ struct AnalysGeom {
 template <int LP, int FW, int W>
 __device__ __forceinline__ void analys_unit(
     const LegArgs& a, int ui,
-    double (&red)[AnalysGeom<LP, FW, W>::NB][AnalysGeom<LP, FW, W>::NR][AnalysGeom<LP, FW, W>::RS],
+    double (&red)[AnalysGeom<LP, FW, W>::NR][AnalysGeom<LP, FW, W>::RS],
     double2 (&start_y)[W][LP][64])
 {
     using G = AnalysGeom<LP, FW, W>;
     constexpr int SC = G::SC, NR = G::NR, NT = G::NT, PR = G::PR, NK = G::NK, RS = G::RS, NH = G::NH;
-    constexpr int NB = G::NB;
     static_assert(2 * NR * PR == NT, "the threads cover the outputs");
     static_assert(kSegLen % SC == 0, "passes tile a segment");
     static_assert(SC % kInject == 0, "passes are whole halves");
@@ -795,7 +796,6 @@ __device__ __forceinline__ void analys_unit(
     DBlk2u<2 * NH> mkw;
     load_u32(mkw, ckm + 2 * (js0 / kInject));
     int shn = 0;        // js0 is a segment start (the plan rounds it down)
-    int buf = 0;
     for (int c = js0; c < j1 + SC; c += SC) {
         const bool compute = c < j1;
         const int sh = shn;
@@ -813,9 +813,13 @@ __device__ __forceinline__ void analys_unit(
         }
         double part[NK];
 #pragma unroll
-        for (int k = 0; k < NK; k++) part[k] = red[(NB - 1) & (buf ^ 1)][row][2 * (k * PR + h) + comp];
+        for (int k = 0; k < NK; k++) part[k] = red[row][2 * (k * PR + h) + comp];
         // gamma of this thread's output in that pass, needed after the steps
         const double gl = gam_tab[min(max(c - SC, js0) + t_out, j1 - 1)];
+        // several waves: every wave has read the previous pass's rows before
+        // any wave writes this pass's (before the next scalar loads are
+        // issued, so that the barrier's wait does not drain them)
+        if (W > 1 && compute) __syncthreads();
         if (compute) {
             const int cn = c + SC;
             // two halves: the second half's beta; one half: the next pass's
@@ -825,7 +829,7 @@ __device__ __forceinline__ void analys_unit(
             __builtin_amdgcn_sched_barrier(0);
             if (sh != 0) rescale(s.ua, s.ub, sh);
             if (mk[0] != 0u && c <= jwin) start_slots(s.ua, s.ub, sj, start_y[wv], mk[0], c);
-            analys_half_from<LP, FW, RS>(lv[0] ? __builtin_ctz(lv[0]) : LP, s, bh0.v, &red[buf][0][col], 0);
+            analys_half_from<LP, FW, RS>(lv[0] ? __builtin_ctz(lv[0]) : LP, s, bh0.v, &red[0][col], 0);
             __builtin_amdgcn_sched_barrier(0);
             if constexpr (NH == 2) {
                 __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): bh1, the masks, the shift
@@ -834,8 +838,7 @@ __device__ __forceinline__ void analys_unit(
                 __builtin_amdgcn_sched_barrier(0);
                 const int c1 = c + kInject;
                 if (mk[1] != 0u && c1 <= jwin) start_slots(s.ua, s.ub, sj, start_y[wv], mk[1], c1);
-                analys_half_from<LP, FW, RS>(lv[1] ? __builtin_ctz(lv[1]) : LP, s, bh1.v, &red[buf][0][col],
-                                             kInject);
+                analys_half_from<LP, FW, RS>(lv[1] ? __builtin_ctz(lv[1]) : LP, s, bh1.v, &red[0][col], kInject);
             } else {
                 bh0 = bh1;
             }
@@ -860,7 +863,6 @@ __device__ __forceinline__ void analys_unit(
             }
         }
         if (W > 1) __syncthreads();
-        buf = (NB - 1) & (buf ^ 1);
     }
     // keeps the prefetch load alive; nfields is never negative
     if (a.nfields < 0) a.out[lane] = (double)pf_sink;
@@ -871,7 +873,7 @@ template <int LP, int FW, int W>
 __global__ void __launch_bounds__(64 * W) k_legendre_analys(LegArgs a)
 {
     using G = AnalysGeom<LP, FW, W>;
-    __shared__ double red[G::NB][G::NR][G::RS];
+    __shared__ double red[G::NR][G::RS];
     __shared__ double2 start_y[W][LP][64];  // stored lane start states
     analys_unit<LP, FW, W>(a, blockIdx.x, red, start_y);
 }
