@@ -38,6 +38,10 @@ constexpr int kFftPoints = 4096;  // complex points per workgroup at most (LDS)
 // workgroup of that kind has.
 __host__ __device__ constexpr int fft_pts(int K) { return K <= 2048 ? 8 : 16; }
 __host__ __device__ constexpr int fft_max_threads(int P) { return kFftPoints / P; }
+// Kernels built for rows of 2^lgk >= 2048 points read their twiddles from
+// global memory (see tw_get); the others, and the general kernels (lgk = 0),
+// from a copy in LDS.
+__host__ __device__ constexpr bool fft_global_tw(int lgk) { return lgk >= 11; }
 
 // Twiddle tables are read through global-address-space pointers (the plan
 // descriptor holds them as generic pointers, which would compile to flat
@@ -174,6 +178,18 @@ __device__ __forceinline__ void dft_r(double2 (&v)[R], int dir)
     }
 }
 
+// Twiddle e^{-2 pi i t/K}: from the LDS copy (padded slots), or with GT
+// straight from the plan's table in global memory (the long rows, whose
+// points alone fill half of a CU's LDS: without the copy two workgroups fit).
+template <bool GT>
+__device__ __forceinline__ double2 tw_get(const double2* twl, gdp twg, int t)
+{
+    if constexpr (GT)
+        return ld2(twg, t);
+    else
+        return twl[tw_at(t)];
+}
+
 // One Stockham pass of radix R over the rows held in buf (npts = rows x K
 // points, K = 2^lgK); Ns = 2^lgNs = product of the radices of the previous
 // passes; twl = the K twiddles e^{-2 pi i t/K} in LDS.  Each thread reads
@@ -182,9 +198,9 @@ __device__ __forceinline__ void dft_r(double2 (&v)[R], int dir)
 // ZIN (first pass of the synthesis only): buf holds Y_m and the pass reads
 // Z_m = (Y_m + conj Y_{K-m}) + i w^m (Y_m - conj Y_{K-m}) instead, Y_K = 0,
 // with w^m of each of the thread's points in zw.
-template <int P, int R, int LGR, bool ZIN = false>
+template <int P, int R, int LGR, bool ZIN = false, bool GT = false>
 __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, int lgK, int npts, int lgNs,
-                                              int dir, const double2 (*zw)[R] = nullptr)
+                                              int dir, const double2 (*zw)[R] = nullptr, gdp twg = nullptr)
 {
     const int rs = row_shift(lgK);
     static_assert(R <= P, "a thread holds whole butterflies");
@@ -222,7 +238,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, const double2* twl, 
                 // twiddle q is w^q, w = table entry js K / (Ns R): one read,
                 // the powers by products at most four deep
                 double2 w[R];
-                w[1] = twl[tw_at(js << (lgK - lgNs - LGR))];
+                w[1] = tw_get<GT>(twl, twg, js << (lgK - lgNs - LGR));
                 if (dir > 0) w[1] = cconj(w[1]);
 #pragma unroll
                 for (int q = 2; q < R; q++) w[q] = cmul(w[q >> 1], w[q - (q >> 1)]);
@@ -265,9 +281,9 @@ __device__ __forceinline__ double2 swap_pair(double2 v) { return make_double2(sw
 // One butterfly per thread (P points), as stockham_pass<P, P, ...>.  With
 // gout the results go straight to global memory (row r of the block at
 // gout + r gstride, point p as the doubles 2p, 2p + 1) instead of buf.
-template <int P, int LGP>
+template <int P, int LGP, bool GT = false>
 __device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl, int lgK, int npts, int dir,
-                                               double* gout, size_t gstride)
+                                               double* gout, size_t gstride, gdp twg = nullptr)
 {
     const int rs = row_shift(lgK);
     const int lgNs = lgK - LGP - 1, Ns = 1 << lgNs;
@@ -284,7 +300,7 @@ __device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl,
     for (int q = 0; q < P; q++) v[q] = buf[rd + q * KR + ((q * KR) >> 4)];
     if (lgNs > 0) {
         double2 w[P];
-        w[1] = twl[tw_at(js << (lgK - lgNs - LGP))];
+        w[1] = tw_get<GT>(twl, twg, js << (lgK - lgNs - LGP));
         if (dir > 0) w[1] = cconj(w[1]);
 #pragma unroll
         for (int q = 2; q < P; q++) w[q] = cmul(w[q >> 1], w[q - (q >> 1)]);
@@ -302,7 +318,7 @@ __device__ __forceinline__ void stockham_last2(double2* buf, const double2* twl,
         const double2 mine = half ? od : ev;
         const double2 got = swap_pair(half ? ev : od);
         const double2 a = half ? got : mine, b = half ? mine : got;
-        double2 w = twl[tw_at(js + (2 * k + half) * Ns)];
+        double2 w = tw_get<GT>(twl, twg, js + (2 * k + half) * Ns);
         if (dir > 0) w = cconj(w);
         const double2 t = cmul(w, b);
         lo[k] = cadd(a, t);
@@ -345,30 +361,30 @@ constexpr int lg_pts() { return P == 16 ? 4 : (P == 8 ? 3 : 2); }
 // synthesis's Z from Y in buf (see stockham_pass).  gout non-null: when the
 // last passes are the joined radix-8 and radix-2 ones, they store the result
 // there (see stockham_last2) and the call returns true; else it is in buf.
-template <int P>
+template <int P, bool GT = false>
 __device__ __forceinline__ bool complex_fft(double2* buf, const double2* twl, int lgK, int npts, int dir,
                                             const double2 (*zw)[P] = nullptr, double* gout = nullptr,
-                                            size_t gstride = 0, int lgNs0 = 0)
+                                            size_t gstride = 0, int lgNs0 = 0, gdp twg = nullptr)
 {
     constexpr int LGP = lg_pts<P>();
     int lgNs = lgNs0;
     if (zw) {
-        stockham_pass<P, P, LGP, true>(buf, twl, lgK, npts, 0, dir, zw);
+        stockham_pass<P, P, LGP, true, GT>(buf, twl, lgK, npts, 0, dir, zw, twg);
         lgNs = LGP;
     }
     while (lgK - lgNs >= LGP) {
         if (P == 8 && lgK - lgNs == LGP + 1) {
-            stockham_last2<P, LGP>(buf, twl, lgK, npts, dir, gout, gstride);
+            stockham_last2<P, LGP, GT>(buf, twl, lgK, npts, dir, gout, gstride, twg);
             return gout != nullptr;
         }
-        stockham_pass<P, P, LGP>(buf, twl, lgK, npts, lgNs, dir);
+        stockham_pass<P, P, LGP, false, GT>(buf, twl, lgK, npts, lgNs, dir, nullptr, twg);
         lgNs += LGP;
     }
     if (P > 4 && lgK - lgNs >= 2) {
-        stockham_pass<P, 4, 2>(buf, twl, lgK, npts, lgNs, dir);
+        stockham_pass<P, 4, 2, false, GT>(buf, twl, lgK, npts, lgNs, dir, nullptr, twg);
         lgNs += 2;
     }
-    if (lgK - lgNs == 1) stockham_pass<P, 2, 1>(buf, twl, lgK, npts, lgNs, dir);
+    if (lgK - lgNs == 1) stockham_pass<P, 2, 1, false, GT>(buf, twl, lgK, npts, lgNs, dir, nullptr, twg);
     return false;
 }
 
@@ -504,7 +520,8 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
 {
     extern __shared__ double2 lds[];  // points (P per thread), then the twiddle table
     double2* buf = lds;
-    double2* twl = lds + lds_points(blockDim.x * P);
+    constexpr bool GT = fft_global_tw(LGK);
+    double2* twl = lds + lds_points(blockDim.x * P);  // unused with GT
     const int pl = a.rowblocks ? a.rowblocks[4 * blockIdx.x + 1] : 0;
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
@@ -546,7 +563,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
             yc[q] = *(const double2*)(Fr + 2 * ((long)(mc <= M ? mc : 0) << kFTileLg));
             rw[q] = ld2(rtw, m);
         }
-        stage_twiddles(twl, tw, K);
+        if (!GT) stage_twiddles(twl, tw, K);
         double2 v[P];
 #pragma unroll
         for (int q = 0; q < P; q++) {
@@ -565,7 +582,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
             for (int q = 0; q < P; q++) buf[wr + q + (q >> 4)] = v[out_slot<P>(q)];
         }
         __syncthreads();
-        if (complex_fft<P>(buf, twl, lgK, npts, +1, nullptr, grow, nphi, LGP)) return;
+        if (complex_fft<P, GT>(buf, twl, lgK, npts, +1, nullptr, grow, nphi, LGP, tw)) return;
 #pragma unroll
         for (int e = 0; e < P; e++) {
             const int idx = threadIdx.x + e * blockDim.x;
@@ -590,12 +607,12 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     for (int idx = threadIdx.x; idx < npts; idx += blockDim.x)
         if ((idx & (K - 1)) > M) buf[at(idx, rs)] = make_double2(0.0, 0.0);
     move_f<P, true>(buf, F, nullptr, D.f_ts, M, lgK, rb.row0, rb.nrows);
-    stage_twiddles(twl, tw, K);
+    if (!GT) stage_twiddles(twl, tw, K);
     __syncthreads();
     bool stored;
     if (fused) {
         const double2(*zw)[P] = (const double2(*)[P])rw;
-        stored = complex_fft<P>(buf, twl, lgK, npts, +1, zw, grow, nphi);
+        stored = complex_fft<P, GT>(buf, twl, lgK, npts, +1, zw, grow, nphi, 0, tw);
     } else {
         double2 z[P];
 #pragma unroll
@@ -617,7 +634,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
             if (idx < npts) buf[at(idx, rs)] = z[e];
         }
         __syncthreads();
-        stored = complex_fft<P>(buf, twl, lgK, npts, +1, nullptr, grow, nphi);
+        stored = complex_fft<P, GT>(buf, twl, lgK, npts, +1, nullptr, grow, nphi, 0, tw);
     }
     if (stored) return;
 #pragma unroll
@@ -637,7 +654,8 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
 {
     extern __shared__ double2 lds[];  // points (P per thread), then the twiddle table
     double2* buf = lds;
-    double2* twl = lds + lds_points(blockDim.x * P);
+    constexpr bool GT = fft_global_tw(LGK);
+    double2* twl = lds + lds_points(blockDim.x * P);  // unused with GT
     const int pl = a.rowblocks ? a.rowblocks[4 * blockIdx.x + 1] : 0;
     const DevPlan& D = a.plans[pl];
     const RowBlock rb = row_block(a, D.nlat);
@@ -689,7 +707,7 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
         const int idx = threadIdx.x + e * blockDim.x;
         rw[e] = ld2(rtw, direct ? ((idx < nout ? idx : 0) >> lgr) : (idx & (K - 1)));
     }
-    stage_twiddles(twl, tw, K);
+    if (!GT) stage_twiddles(twl, tw, K);
     if (first_in_regs) {
         // the first pass (Ns = 1, no twiddles): DFT of the loaded points,
         // outputs to slots (jj << lg P) + q of the row
@@ -701,12 +719,12 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_r2c(FftArgs a)
             for (int q = 0; q < P; q++) buf[wr + q + (q >> 4)] = v[out_slot<P>(q)];
         }
         __syncthreads();
-        complex_fft<P>(buf, twl, lgK, npts, -1, nullptr, nullptr, 0, LGP);
+        complex_fft<P, GT>(buf, twl, lgK, npts, -1, nullptr, nullptr, 0, LGP, tw);
     } else {
 #pragma unroll
         for (int e = 0; e < P; e++) buf[at(threadIdx.x + e * blockDim.x, rs)] = v[e];
         __syncthreads();
-        complex_fft<P>(buf, twl, lgK, npts, -1);
+        complex_fft<P, GT>(buf, twl, lgK, npts, -1, nullptr, nullptr, 0, 0, tw);
     }
     // scale <= 0: the analysis scale 2 pi / nphi of each field's plan
     const double sc = a.scale > 0.0 ? a.scale : 2.0 * 3.14159265358979323846 / nphi;
@@ -777,9 +795,9 @@ static int fft_threads(int points, int P)
 
 // Dynamic LDS for that thread count and row length: P points per thread
 // plus the K twiddles.
-static size_t fft_lds_bytes(int threads, int P, int K)
+static size_t fft_lds_bytes(int threads, int P, int K, bool global_tw)
 {
-    return sizeof(double2) * ((size_t)lds_points(threads * P) + tw_slots(K));
+    return sizeof(double2) * ((size_t)lds_points(threads * P) + (global_tw ? 0 : tw_slots(K)));
 }
 
 // Allows the largest dynamic LDS of these kernels (above the 64 KB default).
@@ -787,7 +805,7 @@ template <int P, int LGK>
 static int allow_lds()
 {
     static const int rc = [] {
-        const int bytes = (int)fft_lds_bytes(fft_max_threads(P), P, kFftPoints);
+        const int bytes = (int)fft_lds_bytes(fft_max_threads(P), P, kFftPoints, fft_global_tw(LGK));
         hipError_t e =
             hipFuncSetAttribute((const void*)k_c2r<P, LGK>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e == hipSuccess)
@@ -803,7 +821,7 @@ static int launch_fft_t(const FftLaunch& l, void* stream)
     if (int e = allow_lds<P, LGK>()) return e;
     const int nt = fft_threads(l.points, P);
     if (nt * P < l.points) return (int)hipErrorInvalidValue;
-    const size_t lds = fft_lds_bytes(nt, P, l.K);
+    const size_t lds = fft_lds_bytes(nt, P, l.K, fft_global_tw(LGK));
     if (C2R)
         hipLaunchKernelGGL((k_c2r<P, LGK>), dim3(l.nblocks, l.grid_y), dim3(nt), lds, (hipStream_t)stream,
                            fft_args(l));
