@@ -12,14 +12,15 @@
 // little arithmetic, so it is bound by memory latency and bandwidth: a launch
 // needs many waves in flight, on every SIMD.  A workgroup holds rows x K <=
 // 4096 points in LDS (whole rows; at lmax 1023 four rows, so that the reads
-// of F, stored in tiles of eight latitudes per order, come in 64-byte runs)
-// next to the K twiddles e^{-2 pi i t/K} (at most 141 KB with the padding
-// against bank conflicts), with one thread per P points: P = 8 up to
-// K = 2048 (512 threads: at lmax 1023 2048 waves, two per SIMD), 16 at
-// K = 4096.  Every thread owns P points of every pass (P/R butterflies of
-// radix R); all index arithmetic is shifts and masks (K is a power of two).  The rows and the pre/post-pass twiddles
-// are requested before anything waits for memory, the twiddle table goes to
-// LDS while they arrive.  Both directions load the points of each thread's
+// of F, stored in tiles of eight latitudes per order, come in 64-byte runs;
+// 71 KB with the padding against bank conflicts), with one thread per P
+// points: P = 8 up to K = 2048 (512 threads: at lmax 1023 2048 waves, two
+// per SIMD), 16 at K = 4096.  Rows of K >= 1024 points read the K twiddles
+// e^{-2 pi i t/K} from the plan's table in global memory; shorter rows copy
+// them to LDS while their points arrive.  Every thread owns P points of every
+// pass (P/R butterflies of radix R); all index arithmetic is shifts and masks
+// (K is a power of two).  The rows and the pre/post-pass twiddles are
+// requested before anything waits for memory.  Both directions load the points of each thread's
 // butterfly of the first radix-P pass straight into registers and run that
 // pass there; with P = 8 the last radix-8 pass and a radix-2 pass after it
 // share one LDS round trip, and the c2r stores the grid rows from it.  Row
@@ -38,10 +39,10 @@ constexpr int kFftPoints = 4096;  // complex points per workgroup at most (LDS)
 // workgroup of that kind has.
 __host__ __device__ constexpr int fft_pts(int K) { return K <= 2048 ? 8 : 16; }
 __host__ __device__ constexpr int fft_max_threads(int P) { return kFftPoints / P; }
-// Kernels built for rows of 2^lgk >= 2048 points read their twiddles from
+// Kernels built for rows of 2^lgk >= 1024 points read their twiddles from
 // global memory (see tw_get); the others, and the general kernels (lgk = 0),
 // from a copy in LDS.
-__host__ __device__ constexpr bool fft_global_tw(int lgk) { return lgk >= 11; }
+__host__ __device__ constexpr bool fft_global_tw(int lgk) { return lgk >= 10; }
 
 // Twiddle tables are read through global-address-space pointers (the plan
 // descriptor holds them as generic pointers, which would compile to flat
@@ -179,8 +180,9 @@ __device__ __forceinline__ void dft_r(double2 (&v)[R], int dir)
 }
 
 // Twiddle e^{-2 pi i t/K}: from the LDS copy (padded slots), or with GT
-// straight from the plan's table in global memory (the long rows, whose
-// points alone fill half of a CU's LDS: without the copy two workgroups fit).
+// straight from the plan's table in global memory, where it stays in cache:
+// for long rows the copy costs more than it saves (its staging, and LDS that
+// at 2048 and 4096 points keeps a second workgroup off the CU).
 template <bool GT>
 __device__ __forceinline__ double2 tw_get(const double2* twl, gdp twg, int t)
 {
