@@ -542,13 +542,15 @@ __global__ void __launch_bounds__(fft_max_threads(P)) k_c2r(FftArgs a)
     constexpr int LGP = lg_pts<P>();
     const bool fused = lgK >= LGP;
     double* grow = g + (size_t)rb.row0 * nphi;  // the block's first grid row
-    // When the block is a power-of-two run of rows aligned inside an F tile
-    // (the usual case), each thread loads the points of its butterfly of the
-    // first pass, Y_m for m = jj + q K/P and their mirrors Y_{K-m}, straight
-    // from F (rows fastest over the threads: four threads read one 64-byte
-    // run of a tile), forms Z and runs that pass in registers: Y never goes
-    // through LDS.
-    if (fused && (rb.nrows & (rb.nrows - 1)) == 0 && rb.nrows <= kFTile && (rb.row0 & (rb.nrows - 1)) == 0) {
+    // When the block is a power-of-two run of two or more rows aligned inside
+    // an F tile (the usual case), each thread loads the points of its
+    // butterfly of the first pass, Y_m for m = jj + q K/P and their mirrors
+    // Y_{K-m}, straight from F (rows fastest over the threads: four threads
+    // read one 64-byte run of a tile), forms Z and runs that pass in
+    // registers: Y never goes through LDS.  A block of one row (K = 4096)
+    // would read every F value twice in 16-byte pieces; it goes through LDS.
+    if (fused && rb.nrows >= 2 && (rb.nrows & (rb.nrows - 1)) == 0 && rb.nrows <= kFTile &&
+        (rb.row0 & (rb.nrows - 1)) == 0) {
         const int lgr = __builtin_ctz(rb.nrows);
         const int lgKR = lgK - LGP;
         const int nb = npts >> LGP;
